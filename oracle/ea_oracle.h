@@ -1,0 +1,50 @@
+/*
+ * CPU oracle for the +-J Edwards-Anderson parallel-tempering Metropolis
+ * simulation (arXiv:1311.5582).  TEST INFRASTRUCTURE ONLY: loaded by the test
+ * suite, the smoke check and the benchmark's CPU-baseline leg, never by the
+ * library.  See ea_oracle.c for the definition it implements.
+ */
+#ifndef EA_ORACLE_H
+#define EA_ORACLE_H
+
+#include <stdint.h>
+
+#define ORC_MAX_TEMPS 64
+
+/* All arrays are owned by the caller.  Spins are stored one per byte (+1/-1),
+ * indexed by slot; temp_of_slot maps each slot to its temperature index. */
+typedef struct {
+    int L;                   /* lattice side, >= 2                              */
+    int n_T;                 /* temperatures (= slots) per copy, 1..64          */
+    int R;                   /* realizations held in this state                 */
+    int pad_;
+    uint64_t seed;           /* Philox key                                      */
+    int64_t t;               /* sweeps done (global sweep index of the next)    */
+    const int32_t *rid;      /* [R] realization id used as Philox counter word 2 */
+    const int8_t *J;         /* [R][N][3] couplings +-1, bond (i, i + e_mu)      */
+    const double *betas;     /* [n_T] inverse temperatures, index 0 = ladder start */
+    int8_t *spins;           /* [R][2][n_T][N]                                   */
+    int32_t *temp_of_slot;   /* [R][2][n_T]                                      */
+    int64_t *Urun;           /* [R][2][n_T] running unsatisfied-bond count or NULL */
+    int64_t *flip_tries;     /* [n_T][7] attempts by (temperature, u) or NULL    */
+    int64_t *flip_acc;       /* [n_T][7] accepted flips (with flip_tries)        */
+    int64_t *swap_tries;     /* [n_T-1] swap attempts per pair or NULL           */
+    int64_t *swap_acc;       /* [n_T-1] accepted swaps (with swap_tries)         */
+} orc_sim;
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+uint32_t orc_flip_threshold(double beta, int u);
+uint32_t orc_swap_threshold(double dbeta_abs, int64_t n);
+int orc_n_phases(int L);
+int orc_colour(int L, int x, int y, int z);
+int orc_local_unsat(int L, const int8_t *J, const int8_t *s, int i);
+int64_t orc_unsat_bonds(int L, const int8_t *J, const int8_t *s);
+void orc_init(orc_sim *sim);
+void orc_reset_running_energy(orc_sim *sim);
+/* returns 0; -1 if the running energy disagrees with the recomputed one after
+ * a sweep; -2 on invalid sizes */
+int orc_sweep(orc_sim *sim, int64_t n_sweeps, int swap_every);
+/* energy [R][2][n_T] by temperature index; overlap [R][n_T] (either may be NULL) */
+void orc_observables(const orc_sim *sim, int32_t *energy, int32_t *overlap);
+
+#endif

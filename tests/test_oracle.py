@@ -1,0 +1,271 @@
+"""Pins for the CPU oracle, against things other than the oracle itself.
+
+Each test fixes a property that the paper or the mathematics determines:
+an independent generator implementation (rocRAND), closed forms of the
+threshold tables, the Hamiltonian written out with numpy, the exact Boltzmann
+distribution by enumeration at L = 2, the zero- and infinite-temperature
+limits, gauge invariance, and the ferromagnetic ground state -3N.
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1311_5582_amd import inputs
+from tests import bruteforce as bf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10 (Sec. 4.3.2 evaluates the counter-based Philox family)
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def rocrand_probe(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available to build the rocRAND probe")
+    out = tmp_path_factory.mktemp("rr") / "rocrand_philox_blocks"
+    src = os.path.join(ROOT, "tests", "helpers", "rocrand_philox_blocks.cpp")
+    subprocess.run([hipcc, "--offload-arch=gfx950", "-O1", "-o", str(out), src], check=True,
+                   capture_output=True)
+    return str(out)
+
+
+def test_philox_matches_rocrand(oracle_lib, rocrand_probe):
+    rng = np.random.default_rng(123)
+    rows = []
+    for n in range(300):
+        c = rng.integers(0, 2 ** 32, size=4, dtype=np.uint64)
+        c[1] %= 2 ** 30            # reachable through rocRAND's public offset
+        k = rng.integers(0, 2 ** 32, size=2, dtype=np.uint64)
+        if n < 4:                  # small and extreme words too
+            c = np.array([n, 0, 0, 0] if n < 2 else [2 ** 32 - 1, 2 ** 30 - 1, 2 ** 32 - 1, 2 ** 32 - 1],
+                         dtype=np.uint64)
+            k = np.array([0, 0] if n % 2 == 0 else [2 ** 32 - 1, 2 ** 32 - 1], dtype=np.uint64)
+        rows.append((c, k))
+    text = "\n".join(" ".join(str(int(v)) for v in list(c) + list(k)) for c, k in rows) + "\n"
+    res = subprocess.run([rocrand_probe], input=text, capture_output=True, text=True, check=True)
+    got = [list(map(int, line.split())) for line in res.stdout.strip().splitlines()]
+    assert len(got) == len(rows)
+    for (c, k), ref in zip(rows, got):
+        assert list(oracle_lib.philox4x32_10(c, k)) == ref
+
+
+# --------------------------------------------------------------------------
+# Integer probability tables (Sec. 4.3.1, 4.3.2)
+# --------------------------------------------------------------------------
+def test_flip_threshold_closed_forms(oracle_lib):
+    # beta = ln2/4: exp(-beta*dE) = 2^(-dE/4), so thresholds are 2^29, 2^30, 2^31
+    # for u = 0, 1, 2 (dE = 12, 8, 4), up to one unit from rounding of ln 2
+    beta = math.log(2.0) / 4.0
+    for u, expo in ((0, 29), (1, 30), (2, 31)):
+        assert abs(oracle_lib.flip_threshold(beta, u) - 2 ** expo) <= 1
+    # infinite temperature: probability 1, clamped to 2^32 - 1
+    assert oracle_lib.flip_threshold(0.0, 0) == 2 ** 32 - 1
+    # large beta: below one part in 2^32 -> 0
+    assert oracle_lib.flip_threshold(5.6, 2) == 0
+    assert oracle_lib.flip_threshold(5.5, 2) > 0        # 2^32 e^-22 = 1.19
+    # monotone in u at fixed beta (higher u = smaller cost)
+    for beta in (0.3, 1.0, 2.5):
+        t = [oracle_lib.flip_threshold(beta, u) for u in range(3)]
+        assert t[0] <= t[1] <= t[2]
+
+
+def test_swap_threshold_closed_forms(oracle_lib):
+    # |dbeta| = ln2/2: exp(-2 |dbeta| n) = 2^-n
+    db = math.log(2.0) / 2.0
+    for n in range(1, 32):
+        assert abs(oracle_lib.swap_threshold(db, n) - 2 ** (32 - n)) <= 1
+    for n in range(33, 40):
+        assert oracle_lib.swap_threshold(db, n) == 0
+    assert oracle_lib.swap_threshold(db, 0) == 2 ** 32 - 1
+
+
+# --------------------------------------------------------------------------
+# Lattice, colouring and energy (Sec. 2.2, 3.1, 4.3 Eq. e)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("L", [2, 3, 4, 5, 6, 7, 9])
+def test_colouring_is_proper(oracle_lib, L):
+    n_col = oracle_lib.n_phases(L)
+    assert n_col == (2 if L % 2 == 0 else 3)
+    col = np.array([[[oracle_lib.colour(L, x, y, z) for x in range(L)] for y in range(L)] for z in range(L)])
+    assert set(np.unique(col)) == set(range(n_col))
+    for axis in range(3):
+        assert np.all(col != np.roll(col, -1, axis=axis))
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 5, 8])
+def test_energy_matches_hamiltonian(oracle_lib, L):
+    rng = np.random.default_rng(L)
+    J = inputs.couplings(L, 1, seed=77)[0]
+    for _ in range(5):
+        s = rng.choice(np.array([-1, 1], dtype=np.int8), size=L ** 3)
+        U = oracle_lib.unsat_bonds(L, J, s)
+        assert 2 * U - 3 * L ** 3 == bf.energy(L, J, s)
+        u = bf.local_field_unsat(L, J, s)
+        assert sum(oracle_lib.local_unsat(L, J, s, i) for i in range(L ** 3)) == 2 * U
+        assert [oracle_lib.local_unsat(L, J, s, i) for i in range(L ** 3)] == list(u)
+
+
+def test_ferro_ground_state_energy(oracle_lib):
+    for L in (2, 3, 4, 8):
+        J = inputs.ferro_couplings(L, 1)[0]
+        up = np.ones(L ** 3, dtype=np.int8)
+        assert 2 * oracle_lib.unsat_bonds(L, J, up) - 3 * L ** 3 == -3 * L ** 3
+        assert 2 * oracle_lib.unsat_bonds(L, -J, up) - 3 * L ** 3 == 3 * L ** 3
+
+
+# --------------------------------------------------------------------------
+# Dynamics
+# --------------------------------------------------------------------------
+def _sim(oracle_lib, L, J, betas, seed=11, **kw):
+    return oracle_lib.OracleSim(L, J, betas, seed, **kw)
+
+
+@pytest.mark.parametrize("L", [4, 5])
+def test_running_energy_equals_recomputed(oracle_lib, L):
+    J = inputs.couplings(L, 2, seed=5)
+    sim = _sim(oracle_lib, L, J, inputs.geometric_betas(6, 0.5, 3.0), track_energy=True)
+    sim.sweep(60, 1)      # raises if the running sum of 6 - 2u ever disagrees
+    sim.sweep(30, 7)
+
+
+@pytest.mark.parametrize("L", [4, 5])
+def test_zero_temperature_limit(oracle_lib, L):
+    # beta = 10: every threshold for u < 3 is 0, so the chain is the
+    # deterministic quench "flip iff u >= 3", colour class by colour class
+    J = inputs.couplings(L, 1, seed=9)
+    sim = _sim(oracle_lib, L, J, np.array([10.0, 12.0]))
+    s0 = sim.spins.copy()
+    sim.sweep(5, 0)
+    for c in range(2):
+        for slot in range(2):
+            assert np.array_equal(sim.spins[0, c, slot], bf.zero_temperature_sweeps(L, J[0], s0[0, c, slot], 5))
+
+
+def test_infinite_temperature_limit(oracle_lib):
+    # beta = 0: thresholds are 2^32 - 1, so a site flips unless the draw is
+    # 2^32 - 1; every site belongs to one colour class, so a sweep negates
+    # the whole configuration (with these seeds no draw equals 2^32 - 1)
+    for L in (4, 5):
+        J = inputs.couplings(L, 1, seed=3)
+        sim = _sim(oracle_lib, L, J, np.array([0.0, 0.0, 0.0]))
+        s0 = sim.spins.copy()
+        sim.sweep(3, 0)
+        assert np.array_equal(sim.spins, -s0)
+
+
+def test_frozen_ferromagnet(oracle_lib):
+    # all J = +1, aligned start, beta >= 1.85 makes the u = 0 threshold 0:
+    # no spin can ever flip and E stays -3N through PT swaps
+    L = 6
+    J = inputs.ferro_couplings(L, 2)
+    sim = _sim(oracle_lib, L, J, inputs.geometric_betas(4, 0.3, 0.54))
+    sim.set_state(np.ones_like(sim.spins), sim.temp_of_slot, 0)
+    sim.sweep(40, 1)
+    assert np.all(sim.spins == 1)
+    E, q = sim.observables()
+    assert np.all(E == -3 * L ** 3)
+    assert np.all(q == L ** 3)
+
+
+def test_ferro_pt_reaches_ground_state(oracle_lib):
+    # ferromagnet from a random start with a ladder down to T = 0.5: the
+    # coldest temperature reaches the ground state E = -3N
+    L = 4
+    J = inputs.ferro_couplings(L, 1)
+    sim = _sim(oracle_lib, L, J, inputs.geometric_betas(8, 0.5, 6.0), seed=21)
+    sim.sweep(400, 1)
+    E, _ = sim.observables()
+    assert np.all(E[0, :, 0] == -3 * L ** 3)
+
+
+def test_gauge_invariance(oracle_lib):
+    # acceptance depends on u only and u is gauge invariant, so the gauge
+    # image of a trajectory is the trajectory of the gauge image, bit for bit
+    for L in (4, 5):
+        rng = np.random.default_rng(100 + L)
+        R = 2
+        J = inputs.couplings(L, R, seed=8)
+        betas = inputs.geometric_betas(9, 0.4, 2.0)
+        a = _sim(oracle_lib, L, J, betas, seed=99)
+        tau = rng.choice(np.array([-1, 1], dtype=np.int8), size=(R, L ** 3))
+        Jg = np.empty_like(J)
+        sg = np.empty_like(a.spins)
+        for r in range(R):
+            Jg[r], _ = bf.gauge(L, J[r], a.spins[r, 0, 0], tau[r])
+            sg[r] = a.spins[r] * tau[r]
+        b = _sim(oracle_lib, L, Jg, betas, seed=99)
+        b.set_state(sg, a.temp_of_slot, 0)
+        for _ in range(4):
+            a.sweep(7, 2)
+            b.sweep(7, 2)
+            assert np.array_equal(b.spins, a.spins * tau[:, None, None, :])
+            assert np.array_equal(b.temp_of_slot, a.temp_of_slot)
+            assert np.array_equal(b.observables()[0], a.observables()[0])
+        # global flip is the special case tau = -1 everywhere
+        c = _sim(oracle_lib, L, J, betas, seed=99)
+        d = _sim(oracle_lib, L, J, betas, seed=99)
+        d.set_state(-c.spins, c.temp_of_slot, 0)
+        c.sweep(10, 1)
+        d.sweep(10, 1)
+        assert np.array_equal(d.spins, -c.spins)
+
+
+def test_exact_boltzmann_distribution_L2(oracle_lib):
+    """Time averages at every temperature index against exact enumeration of
+    the 2^8 states of the L = 2 lattice (24 bonds), including the expected
+    swap acceptance of every pair; the bound is 5 standard errors estimated
+    from batch means."""
+    L, R = 2, 24
+    J1 = inputs.couplings(L, 1, seed=2024)[0]
+    J = np.repeat(J1[None], R, axis=0)
+    betas = np.array([1.1, 0.75, 0.5, 0.3])
+    n_T = len(betas)
+    sim = _sim(oracle_lib, L, J, betas, seed=7, stats=True)
+    spectrum = bf.enumerate_energies(L, J1)
+    sim.sweep(200, 1)                                       # burn-in
+    sim.flip_tries[...] = 0
+    sim.flip_acc[...] = 0
+    sim.swap_tries[...] = 0
+    sim.swap_acc[...] = 0
+    n_batches, per_batch = 20, 600
+    levels = np.unique(spectrum)
+    hist = np.zeros((n_batches, n_T, len(levels)))
+    swap_rate = np.zeros((n_batches, n_T - 1))
+    for b in range(n_batches):
+        tries0, acc0 = sim.swap_tries.copy(), sim.swap_acc.copy()
+        for _ in range(per_batch):
+            sim.sweep(1, 1)
+            E, _ = sim.observables()
+            for k in range(n_T):
+                hist[b, k] += np.bincount(np.searchsorted(levels, E[:, :, k].ravel()), minlength=len(levels))
+        swap_rate[b] = (sim.swap_acc - acc0) / (sim.swap_tries - tries0)
+    hist /= hist.sum(axis=2, keepdims=True)
+    for k in range(n_T):
+        vals, p = bf.boltzmann_pdf(spectrum, betas[k])
+        assert np.array_equal(vals, levels)
+        mean = hist[:, k].mean(axis=0)
+        err = hist[:, k].std(axis=0, ddof=1) / math.sqrt(n_batches)
+        assert np.all(np.abs(mean - p) <= 5 * err + 2e-3), (k, mean, p)
+    for k in range(n_T - 1):
+        vals, pk = bf.boltzmann_pdf(spectrum, betas[k])
+        _, pk1 = bf.boltzmann_pdf(spectrum, betas[k + 1])
+        dE = vals[:, None] - vals[None, :]
+        expect = float(np.sum(pk[:, None] * pk1[None, :] * np.minimum(1.0, np.exp((betas[k] - betas[k + 1]) * dE))))
+        mean = swap_rate[:, k].mean()
+        err = swap_rate[:, k].std(ddof=1) / math.sqrt(n_batches)
+        assert abs(mean - expect) <= 5 * err + 2e-3, (k, mean, expect)
+    # acceptance per (temperature, u) class equals threshold / 2^32
+    for k in range(n_T):
+        for u in range(7):
+            n = sim.flip_tries[k, u]
+            if n < 100:
+                continue
+            p = 1.0 if u >= 3 else oracle_lib.flip_threshold(betas[k], u) / 2 ** 32
+            got = sim.flip_acc[k, u] / n
+            assert abs(got - p) <= 5 * math.sqrt(max(p * (1 - p), 1e-12) / n) + 1e-9, (k, u, got, p)
