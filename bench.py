@@ -1,0 +1,147 @@
+"""Benchmark: picoseconds per spin-flip attempt on one MI355X.
+
+Workload (default): 3D +-J EA model, L = 16 (4096 spins), 64 disorder
+realizations x 2 copies, 32 temperatures geometric in T in [0.4, 2.0],
+parallel tempering after every sweep, CAMSC layout.  One step = one sweep
+launch of --sweeps-per-step sweeps plus one measurement (energies and
+overlaps); the default 10 steps x 1000 sweeps is the whole 10^4-sweep job.
+ps/flip follows Eq. tsf of the paper: wall time / (sweeps x spins x
+temperatures x samples), samples = realizations x 2 copies.
+
+Prints one JSON line.  The roofline object prices the sweep kernel against
+the integer issue rate of the chip; the cpu_baseline object times the CPU
+oracle on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ps per spin-flip attempt (1 GPU, batched vs plain) + p50/p99 job latency"
+
+# Integer issue slots per spin-flip attempt the method itself needs (derived
+# in the design notes): a quarter of a Philox4x32-10 block (10 rounds x (2
+# quarter-rate 32x32->64 multiplies + 2 three-input xors) / 4 = 25 slots),
+# the table column, address, compare and insert (4 slots), and the share of
+# the bit-parallel bond energy (about 1 slot).
+ALG_SLOTS_PER_FLIP = 30
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = int32 issue slots per second
+PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+
+
+def cpu_baseline(L, n_T, t_min, t_max, seed, sweeps, threads):
+    """Time the oracle: `threads` realizations, one per thread, `sweeps` each."""
+    import oracle
+    from paper_1311_5582_amd import inputs
+    betas = inputs.geometric_betas(n_T, t_min, t_max)
+    sims = [oracle.OracleSim(L, inputs.couplings(L, 1, seed, r0=r), betas, seed, rid=np.array([r]))
+            for r in range(threads)]
+    ths = [threading.Thread(target=s.sweep, args=(sweeps, 1)) for s in sims]
+    t0 = time.perf_counter()
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    dt = time.perf_counter() - t0
+    flips = sweeps * L ** 3 * n_T * 2 * threads
+    return {"value": dt / flips * 1e12, "unit": "ps/flip", "cores": threads, "kind": "oracle",
+            "sample": f"{threads} realizations x 2 copies x {n_T} temps, L={L}, {sweeps} sweeps, "
+                      f"PT every sweep ({flips:.3g} flip attempts, {dt:.1f} s wall)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--sweeps-per-step", type=int, default=1000)
+    ap.add_argument("--workload", default="L16_R64")
+    ap.add_argument("--layout", default="camsc", choices=["camsc", "amsc4"])
+    ap.add_argument("--block-threads", type=int, default=0)
+    ap.add_argument("--cpu-sweeps", type=int, default=60)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: each realization is an independent Markov chain and this "
+              "build measures one GPU's share; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1311_5582_amd import binding as B
+    from paper_1311_5582_amd import inputs
+
+    cfg = dict(inputs.CONFIGS[args.workload])
+    L, R, n_T = cfg["L"], cfg["R"], cfg["n_T"]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    J = inputs.couplings(L, R, cfg["seed"])
+    betas = inputs.geometric_betas(n_T, cfg["t_min"], cfg["t_max"])
+    sim = B.Sim(L, J, betas, cfg["seed"], layout=args.layout, block_threads=args.block_threads, stream=stream)
+    S, se = args.sweeps_per_step, cfg["swap_every"]
+
+    def step(events=None):
+        if events is not None:
+            events[0].record(stream)
+        sim.sweep(S, se)
+        if events is not None:
+            events[1].record(stream)
+        return sim.observables()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = [a.elapsed_time(b) for a, b in evs]
+
+    flips_per_step = S * L ** 3 * n_T * R * 2
+    total_flips = flips_per_step * args.steps
+    ps_per_flip = wall / total_flips * 1e12
+    avg_launch_s = float(np.mean(kernel_ms)) / 1e3
+    achieved = ALG_SLOTS_PER_FLIP * flips_per_step / avg_launch_s / 1e12
+    peak = PEAK_SLOTS_PER_S / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(ps_per_flip, 4),
+        "unit": "ps/flip",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "L": L, "spins": L ** 3, "realizations": R, "copies": 2,
+                   "temperatures": n_T, "T_range": [cfg["t_min"], cfg["t_max"]], "sweeps_per_step": S,
+                   "swap_every": se, "layout": args.layout, "measurement_per_step": True,
+                   "kernel_ps_per_flip": round(avg_launch_s / flips_per_step * 1e12, 4),
+                   "paper_ps_per_flip_gtx580": 33.5},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "ops_per_flip": ALG_SLOTS_PER_FLIP,
+                     "kernel": "sweep_kernel<%s>" % ("CAMSC" if args.layout == "camsc" else "AMSC4")},
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        threads = max(1, min(os.cpu_count() or 1, 16))
+        out["cpu_baseline"] = cpu_baseline(L, n_T, cfg["t_min"], cfg["t_max"], cfg["seed"], args.cpu_sweeps, threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

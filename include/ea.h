@@ -1,0 +1,168 @@
+/*
+ * ea.h - C ABI of the MI355X (gfx950) parallel-tempering Metropolis library
+ * for the three-dimensional +-J Edwards-Anderson model over bit-packed
+ * temperature replicas (Fang et al., arXiv:1311.5582).
+ *
+ * Model (Sec. 2.2, Eq. 1, h = 0): H = -sum over the 3N nearest-neighbour
+ * bonds of a periodic L x L x L simple cubic lattice of J_b s_i s_j, with
+ * s, J in {+1, -1}.  Site i = x + L*(y + L*z); couplings[r][i][mu] is the bond
+ * between i and its +mu neighbour (mu = 0:x, 1:y, 2:z).  J = +1 is
+ * ferromagnetic, so the all-ferro ground state has E = -3N.
+ *
+ * Dynamics: checkerboard single-spin-flip Metropolis (Sec. 2.3, 3.1) with
+ * integer thresholds looked up by temperature and the 4-bit column 2E+S
+ * (Sec. 4.3.1, 4.3.2), Philox4x32-10 random numbers (the counter-based family
+ * of Sec. 4.3.2), and parallel-tempering swaps of adjacent temperatures
+ * (Sec. 2.4, 4.1) that exchange table rows, not spins.  Each realization
+ * carries two independent copies ("replicas" in the spin-glass sense) so that
+ * the overlap q can be measured.  Results are a pure function of the inputs
+ * and the seed: they do not depend on launch shape, batching, or how the
+ * sweeps are split across calls.
+ *
+ * The random stream, with key (lo32(seed), hi32(seed)) and counter words
+ * (c0, c1, c2, c3):
+ *   flip draw for (realization r, copy c, slot s, sweep t, site i):
+ *       block(i, t, r, c<<24 | s>>2)[s & 3]; the flip is taken iff u >= 3 or
+ *       draw < floor(2^32 exp(-beta_k (12 - 4u))) (clamped to 2^32-1), where
+ *       u is the number of unsatisfied bonds at i and k = temp_of_slot[s].
+ *   swap draw for pair (k, k+1) after sweep t: block(k, t, r, 1<<28 | c<<24)[0].
+ *   initial spin: s = +1 iff block(i, 0, r, 2<<28 | c<<24 | s>>2)[s & 3] & 1.
+ * A swap pass follows sweep t iff swap_every > 0 and (t+1) % swap_every == 0;
+ * it visits k = 0 .. n_T-2 in order, accepting when (beta_k - beta_{k+1}) *
+ * (E_a - E_b) >= 0 and otherwise iff draw < floor(2^32 exp(-2|beta_k -
+ * beta_{k+1}| |U_a - U_b|)), with U the number of unsatisfied bonds.  Odd L
+ * (not bipartite) is updated in three colour classes (g(x)+g(y)+g(z)) mod 3,
+ * g(x) = x & 1 for x < L-1, g(L-1) = 2; even L in the two parity classes,
+ * parity 0 first.
+ *
+ * Conventions for every function below:
+ *   - Every function returns EA_OK (0) or a negative status; ea_last_error()
+ *     then returns a thread-local message.  No C++ exception crosses the ABI.
+ *   - Input arrays are caller-owned host memory, read during the call only.
+ *     Output arrays are caller-allocated host memory of the documented shape.
+ *   - A handle is not thread-safe; distinct handles may be used concurrently
+ *     from different threads.
+ *   - Device memory is owned by the handle and released by ea_destroy.
+ */
+#ifndef EA_H
+#define EA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define EA_OK        0
+#define EA_EINVAL   -1   /* an argument is out of range; nothing was changed      */
+#define EA_ENOMEM   -2   /* a device or host allocation failed                    */
+#define EA_EDEVICE  -3   /* a HIP call failed (message names it)                  */
+#define EA_ESTATE   -4   /* the handle cannot do this now (e.g. sweep counter full) */
+
+/* spin layouts (Sec. 4.3.3) */
+#define EA_LAYOUT_CAMSC 0  /* 1 bit per temperature slot, 32 slots per 32-bit word; the
+                              bond energies are widened to 4-bit segments only to sum */
+#define EA_LAYOUT_AMSC4 1  /* 4-bit segment per slot (spin in bit 0), 8 slots per word */
+
+#define EA_MAX_TEMPS 64    /* temperatures (slots) per copy                           */
+#define EA_MAX_L     32    /* lattice side                                            */
+
+typedef struct ea_sim ea_sim;   /* opaque handle: one job of R realizations x 2 copies */
+
+typedef struct ea_options {
+    int layout;          /* EA_LAYOUT_CAMSC (default) or EA_LAYOUT_AMSC4               */
+    int block_threads;   /* threads per workgroup: 0 = library choice, else a multiple
+                            of 64 in [64, 1024]                                        */
+    int words_resident;  /* spin words per site held in LDS at once: 0 = as many as fit;
+                            fewer makes the kernel stage word groups through HBM       */
+    int reserved_;
+    void *stream;        /* hipStream_t to run on; NULL = the default stream            */
+    /* optional device allocator (e.g. backed by a framework's caching allocator);
+       both NULL = hipMalloc / hipFree.  dev_alloc returns NULL on failure.            */
+    void *(*dev_alloc)(size_t bytes, void *ctx);
+    void (*dev_free)(void *ptr, void *ctx);
+    void *alloc_ctx;
+} ea_options;
+
+/* Fill *opt with the defaults (CAMSC, library-chosen launch, default stream,
+ * hipMalloc). */
+void ea_default_options(ea_options *opt);
+
+/* Create a job (Sec. 2.2 problem statement; Sec. 3.2, 3.3 work mapping).
+ *   L            lattice side, 2 <= L <= EA_MAX_L.
+ *   couplings    int8 [n_realizations][L^3][3], each +1 or -1 (copied).
+ *   betas        double [n_T] inverse temperatures, finite and > 0; index 0 is
+ *                "temperature index 0" of the ladder (copied).
+ *   n_T          1 <= n_T <= EA_MAX_TEMPS.
+ *   n_realizations  >= 1; realization r uses r as its Philox counter word.
+ *   seed         64-bit Philox key.
+ *   opt          NULL for defaults.
+ * Initial state: spins from the initial-spin stream, temp_of_slot[s] = s,
+ * sweeps_done = 0.  Errors: EA_EINVAL (argument), EA_ENOMEM, EA_EDEVICE. */
+int ea_create(int L, const int8_t *couplings, const double *betas, int n_T,
+              int n_realizations, uint64_t seed, const ea_options *opt, ea_sim **out);
+
+/* Run n_sweeps >= 0 sweeps (Sec. 3.1: one sweep = the colour classes in
+ * order), with a parallel-tempering pass after every sweep t for which
+ * swap_every > 0 and (t+1) % swap_every == 0 (Sec. 4.1); swap_every = 0 turns
+ * PT off.  Asynchronous on the handle's stream when one was given, otherwise
+ * synchronous.  EA_ESTATE if the total sweep count would reach 2^32. */
+int ea_sweep(ea_sim *sim, int64_t n_sweeps, int swap_every);
+
+/* One launch over the ladders of several jobs of uneven size (north-star
+ * batching; Sec. 3.3 maps realizations to workgroups).  n_sweeps[j] and
+ * swap_every[j] apply to sims[j] exactly as in ea_sweep; each job's results
+ * equal those of running it alone.  All sims must live on the current device
+ * and share one layout; the launch uses sims[0]'s stream. */
+int ea_sweep_batch(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps,
+                   const int *swap_every);
+
+/* Measurement (Sec. 4.1, separate kernel): energy int32 [R][2][n_T] indexed by
+ * temperature index, E = 2U - 3N; overlap int32 [R][n_T]:
+ * q_k = sum_i s_i(copy 0 at temperature k) s_i(copy 1 at temperature k).
+ * Either pointer may be NULL.  Synchronous. */
+int ea_observables(ea_sim *sim, int32_t *energy, int32_t *overlap);
+
+/* Read the full state: spins int8 [R][2][n_T][L^3] (+1/-1, indexed by slot),
+ * temp_of_slot int32 [R][2][n_T], sweeps_done.  Any pointer may be NULL.
+ * Synchronous.  With ea_set_state this is checkpoint/resume: the stream is
+ * counter-based, so a resumed run continues bit-identically. */
+int ea_state(ea_sim *sim, int8_t *spins, int32_t *temp_of_slot, int64_t *sweeps_done);
+
+/* Overwrite the state (same shapes; temp_of_slot must be a permutation of
+ * 0..n_T-1 in every ladder, sweeps_done in [0, 2^32)).  EA_EINVAL leaves the
+ * state unchanged. */
+int ea_set_state(ea_sim *sim, const int8_t *spins, const int32_t *temp_of_slot,
+                 int64_t sweeps_done);
+
+/* Accepted swaps per (realization, copy, pair k) since creation, uint64
+ * [R][2][n_T-1] (n_T = 1: nothing written).  Synchronous. */
+int ea_swap_acceptance(ea_sim *sim, uint64_t *accepted);
+
+/* Shape queries. */
+int ea_get_dims(const ea_sim *sim, int *L, int *n_T, int *n_realizations, int *layout);
+
+/* Release the handle and its device memory (NULL is a no-op). */
+void ea_destroy(ea_sim *sim);
+
+/* Thread-local message for the last non-OK status on this thread. */
+const char *ea_last_error(void);
+
+/* Host-side table helpers (no device use), the same formulas the library
+ * uses (Sec. 4.3.1, 4.3.2):
+ *   flip_thr[k][u] = min(floor(2^32 exp(-betas[k] (12 - 4u))), 2^32-1), u = 0..2,
+ *   written as uint32 [n_T][3];
+ *   swap threshold = min(floor(2^32 exp(-2 dbeta_abs n)), 2^32-1). */
+int ea_flip_thresholds(const double *betas, int n_T, uint32_t *flip_thr);
+uint32_t ea_swap_threshold(double dbeta_abs, int64_t n);
+
+/* Library build identification (static string). */
+const char *ea_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EA_H */

@@ -1,0 +1,223 @@
+"""ctypes binding over the C ABI in include/ea.h (argument marshalling only).
+
+Every step of the simulation runs in the HIP kernels of libea_mi355x.so; this
+module converts numpy arrays to pointers and back.  When torch with a GPU is
+available, device memory comes from torch's caching allocator and the work
+runs on a torch stream; otherwise the library's own hipMalloc and the default
+stream are used.  A missing library is an error, never a fallback.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+LIB_PATH = os.path.join(PKG, "libea_mi355x.so")
+HEADER = os.path.join(ROOT, "include", "ea.h")
+
+EA_OK, EA_EINVAL, EA_ENOMEM, EA_EDEVICE, EA_ESTATE = 0, -1, -2, -3, -4
+LAYOUT_CAMSC, LAYOUT_AMSC4 = 0, 1
+LAYOUTS = {"camsc": LAYOUT_CAMSC, "amsc4": LAYOUT_AMSC4}
+MAX_TEMPS = 64
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("layout", ctypes.c_int), ("block_threads", ctypes.c_int),
+        ("words_resident", ctypes.c_int), ("reserved_", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+        ("dev_alloc", _ALLOC_FN), ("dev_free", _FREE_FN), ("alloc_ctx", ctypes.c_void_p),
+    ]
+
+
+class EAError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Open libea_mi355x.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        i8p, i32p, i64p = (ctypes.POINTER(t) for t in (ctypes.c_int8, ctypes.c_int32, ctypes.c_int64))
+        u32p, u64p, f64p = (ctypes.POINTER(t) for t in (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double))
+        sig = {
+            "ea_default_options": (None, [ctypes.POINTER(Options)]),
+            "ea_create": (ctypes.c_int, [ctypes.c_int, i8p, f64p, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                         ctypes.POINTER(Options), ctypes.POINTER(P)]),
+            "ea_sweep": (ctypes.c_int, [P, ctypes.c_int64, ctypes.c_int]),
+            "ea_sweep_batch": (ctypes.c_int, [ctypes.POINTER(P), ctypes.c_int, i64p, i32p]),
+            "ea_observables": (ctypes.c_int, [P, i32p, i32p]),
+            "ea_state": (ctypes.c_int, [P, i8p, i32p, i64p]),
+            "ea_set_state": (ctypes.c_int, [P, i8p, i32p, ctypes.c_int64]),
+            "ea_swap_acceptance": (ctypes.c_int, [P, u64p]),
+            "ea_get_dims": (ctypes.c_int, [P, i32p, i32p, i32p, i32p]),
+            "ea_destroy": (None, [P]),
+            "ea_last_error": (ctypes.c_char_p, []),
+            "ea_flip_thresholds": (ctypes.c_int, [f64p, ctypes.c_int, u32p]),
+            "ea_swap_threshold": (ctypes.c_uint32, [ctypes.c_double, ctypes.c_int64]),
+            "ea_version": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_functions():
+    """Names of the functions include/ea.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(ea_[a-z_0-9]+)\s*\(", text, re.M)))
+
+
+def last_error():
+    return lib().ea_last_error().decode()
+
+
+def check(rc):
+    if rc != EA_OK:
+        raise EAError(rc, last_error())
+
+
+def _p(a, t):
+    return a.ctypes.data_as(ctypes.POINTER(t))
+
+
+def flip_thresholds(betas):
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    out = np.zeros((len(b), 3), dtype=np.uint32)
+    check(lib().ea_flip_thresholds(_p(b, ctypes.c_double), len(b), _p(out, ctypes.c_uint32)))
+    return out
+
+
+def swap_threshold(dbeta_abs, n):
+    return int(lib().ea_swap_threshold(float(dbeta_abs), int(n)))
+
+
+class TorchAllocator:
+    """Device memory for the library from torch's caching allocator."""
+
+    def __init__(self, device=0):
+        import torch
+        self._torch = torch
+        self.device = device
+        self.live = {}
+        self.alloc_cb = _ALLOC_FN(self._alloc)
+        self.free_cb = _FREE_FN(self._free)
+
+    def _alloc(self, nbytes, ctx):
+        try:
+            t = self._torch.empty(int(nbytes), dtype=self._torch.uint8, device=f"cuda:{self.device}")
+        except Exception:   # out of memory: the library reports EA_ENOMEM
+            return None
+        self.live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _free(self, ptr, ctx):
+        self.live.pop(ptr, None)
+
+
+def _torch_gpu():
+    try:
+        import torch
+        return torch if torch.cuda.is_available() else None
+    except Exception:
+        return None
+
+
+class Sim:
+    """One job: R realizations x 2 copies x n_T temperature slots on the GPU."""
+
+    def __init__(self, L, couplings, betas, seed, layout="camsc", block_threads=0, words_resident=0,
+                 stream=None, torch_memory=True):
+        L = int(L)
+        J = np.ascontiguousarray(couplings, dtype=np.int8)
+        if J.ndim != 3 or J.shape[1:] != (L ** 3, 3):
+            raise ValueError(f"couplings must have shape [R][{L ** 3}][3]")
+        b = np.ascontiguousarray(betas, dtype=np.float64)
+        opt = Options()
+        lib().ea_default_options(ctypes.byref(opt))
+        opt.layout = LAYOUTS[layout] if isinstance(layout, str) else int(layout)
+        opt.block_threads = int(block_threads)
+        opt.words_resident = int(words_resident)
+        self._alloc = None
+        torch = _torch_gpu() if (torch_memory or stream is not None) else None
+        if stream is not None:
+            opt.stream = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+        if torch is not None and torch_memory:
+            self._alloc = TorchAllocator(torch.cuda.current_device())
+            opt.dev_alloc = self._alloc.alloc_cb
+            opt.dev_free = self._alloc.free_cb
+        self.stream = stream
+        self.L, self.N, self.R, self.n_T = L, L ** 3, J.shape[0], len(b)
+        self.layout = opt.layout
+        self._h = ctypes.c_void_p()
+        check(lib().ea_create(L, _p(J, ctypes.c_int8), _p(b, ctypes.c_double), len(b), J.shape[0],
+                              ctypes.c_uint64(int(seed) & (2 ** 64 - 1)), ctypes.byref(opt), ctypes.byref(self._h)))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().ea_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def sweep(self, n_sweeps, swap_every=1):
+        check(lib().ea_sweep(self._h, int(n_sweeps), int(swap_every)))
+
+    def observables(self):
+        E = np.zeros((self.R, 2, self.n_T), dtype=np.int32)
+        q = np.zeros((self.R, self.n_T), dtype=np.int32)
+        check(lib().ea_observables(self._h, _p(E, ctypes.c_int32), _p(q, ctypes.c_int32)))
+        return E, q
+
+    def state(self):
+        s = np.zeros((self.R, 2, self.n_T, self.N), dtype=np.int8)
+        perm = np.zeros((self.R, 2, self.n_T), dtype=np.int32)
+        t = ctypes.c_int64()
+        check(lib().ea_state(self._h, _p(s, ctypes.c_int8), _p(perm, ctypes.c_int32), ctypes.byref(t)))
+        return s, perm, int(t.value)
+
+    def set_state(self, spins, temp_of_slot, sweeps_done):
+        s = np.ascontiguousarray(spins, dtype=np.int8)
+        p = np.ascontiguousarray(temp_of_slot, dtype=np.int32)
+        check(lib().ea_set_state(self._h, _p(s, ctypes.c_int8), _p(p, ctypes.c_int32), int(sweeps_done)))
+
+    def swap_acceptance(self):
+        a = np.zeros((self.R, 2, max(self.n_T - 1, 0)), dtype=np.uint64)
+        check(lib().ea_swap_acceptance(self._h, _p(a, ctypes.c_uint64)))
+        return a
+
+
+def sweep_batch(sims, n_sweeps, swap_every):
+    """One launch over several jobs; n_sweeps / swap_every are per-job lists."""
+    n = len(sims)
+    hs = (ctypes.c_void_p * n)(*[s.handle.value for s in sims])
+    ns = np.ascontiguousarray(n_sweeps, dtype=np.int64)
+    se = np.ascontiguousarray(swap_every, dtype=np.int32)
+    check(lib().ea_sweep_batch(hs, n, _p(ns, ctypes.c_int64), _p(se, ctypes.c_int32)))

@@ -1,0 +1,572 @@
+// Host side of the C ABI declared in include/ea.h: argument validation,
+// integer probability tables (Sec. 4.3.1, 4.3.2), lattice colour classes,
+// device buffers and launch planning.  All simulation arithmetic runs in the
+// kernels of ea_kernels.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ea.h"
+#include "ea_internal.h"
+
+using namespace ea;
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+#define EA_HIP(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess) return fail(EA_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Integer probability tables
+// ---------------------------------------------------------------------------
+uint32_t prob_to_u32(double p)
+{
+    const double x = std::floor(std::ldexp(p, 32));
+    if (!(x < 4294967295.0)) return 0xFFFFFFFFu;
+    if (x <= 0.0) return 0u;
+    return (uint32_t)x;
+}
+
+// Metropolis: dE = 12 - 4u for a site with u unsatisfied bonds.
+uint32_t flip_thr(double beta, int u)
+{
+    return prob_to_u32(std::exp(-(beta * (double)(12 - 4 * u))));
+}
+
+// Replica exchange: |dE| = 2n for |U_a - U_b| = n.
+uint32_t swap_thr(double dbeta_abs, int64_t n)
+{
+    return prob_to_u32(std::exp(-(2.0 * dbeta_abs * (double)n)));
+}
+
+struct DeviceAlloc {
+    void *(*alloc)(size_t, void *) = nullptr;
+    void (*release)(void *, void *) = nullptr;
+    void *ctx = nullptr;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Handle
+// ---------------------------------------------------------------------------
+struct ea_sim {
+    int L = 0, N = 0, n_T = 0, R = 0, layout = 0, NW = 0;
+    int block_threads = 0, words_resident = 0;
+    int device = 0;
+    uint64_t seed = 0;
+    int64_t t = 0;                    // host shadow of the sweep counter
+    hipStream_t stream = nullptr;
+    bool user_stream = false;
+    DeviceAlloc da;
+    std::vector<void *> owned;        // device buffers to release
+    JobDesc h{};                      // host copy of the descriptor
+    JobDesc *d_job = nullptr;
+    uint32_t *d_units = nullptr;      // ladders of this job for a lone launch
+    uint32_t *d_counters = nullptr;   // [0] sweep counter, [1] work queue
+    int64_t swap_total = 0;           // entries in the swap tables
+};
+
+namespace {
+
+int dev_alloc(ea_sim *s, size_t bytes, void **out)
+{
+    bytes = std::max<size_t>(bytes, 16);
+    void *p = nullptr;
+    if (s->da.alloc) {
+        p = s->da.alloc(bytes, s->da.ctx);
+        if (!p) return fail(EA_ENOMEM, "device allocator returned NULL for %zu bytes", bytes);
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) return fail(EA_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    s->owned.push_back(p);
+    *out = p;
+    return EA_OK;
+}
+
+void release_all(ea_sim *s)
+{
+    for (void *p : s->owned) {
+        if (s->da.release)
+            s->da.release(p, s->da.ctx);
+        else
+            (void)hipFree(p);
+    }
+    s->owned.clear();
+}
+
+template <class T>
+int upload(ea_sim *s, const std::vector<T> &v, T **out)
+{
+    void *p = nullptr;
+    int rc = dev_alloc(s, v.size() * sizeof(T), &p);
+    if (rc) return rc;
+    if (!v.empty()) EA_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    *out = (T *)p;
+    return EA_OK;
+}
+
+int sync_if_needed(ea_sim *s)
+{
+    if (!s->user_stream) EA_HIP(hipStreamSynchronize(s->stream));
+    return EA_OK;
+}
+
+// Colour classes (Sec. 3.1 checkerboard; odd L uses three classes).
+void colour_classes(int L, std::vector<uint32_t> &sites, int32_t off[4], int *n_classes)
+{
+    const int nc = (L % 2 == 0) ? 2 : 3;
+    auto g = [L](int a) { return a == L - 1 ? 2 : (a & 1); };
+    sites.clear();
+    for (int c = 0; c < nc; ++c) {
+        off[c] = (int32_t)sites.size();
+        for (int z = 0; z < L; ++z)
+            for (int y = 0; y < L; ++y)
+                for (int x = 0; x < L; ++x) {
+                    const int col = (L % 2 == 0) ? ((x + y + z) & 1) : ((g(x) + g(y) + g(z)) % 3);
+                    if (col == c) sites.push_back((uint32_t)x | ((uint32_t)y << 8) | ((uint32_t)z << 16));
+                }
+    }
+    for (int c = nc; c < 4; ++c) off[c] = (int32_t)sites.size();
+    *n_classes = nc;
+}
+
+constexpr size_t kLdsBudget = 160 * 1024 - 1024;   // dynamic LDS; the rest is static
+
+int plan_launch(int N, int NW, const ea_options &opt, int *block_threads, int *words_resident)
+{
+    // words resident in LDS
+    const size_t fixed = lds_bytes(N, 0, 0);
+    if (fixed + (size_t)N * 4 > kLdsBudget)
+        return fail(EA_EINVAL, "lattice of %d sites does not fit one spin word in LDS", N);
+    int wr_max = (int)((kLdsBudget - fixed) / ((size_t)N * 4));
+    int wr = std::min(NW, wr_max);
+    if (opt.words_resident < 0) return fail(EA_EINVAL, "words_resident=%d < 0", opt.words_resident);
+    if (opt.words_resident > 0) {
+        if (opt.words_resident > wr_max)
+            return fail(EA_EINVAL, "words_resident=%d exceeds the %d words that fit in LDS", opt.words_resident, wr_max);
+        wr = std::min(NW, opt.words_resident);
+    }
+    // threads: one site of a colour class per thread where possible
+    int min_bt = ((N + 84) / 85 + 63) / 64 * 64;   // keeps per-lane bond counts below 256
+    int bt = opt.block_threads;
+    if (bt == 0) {
+        bt = std::min(kMaxBlock, std::max(256, (N / 2 + 63) / 64 * 64));
+        bt = std::max(bt, min_bt);
+    }
+    if (bt < 64 || bt > kMaxBlock || bt % 64 != 0)
+        return fail(EA_EINVAL, "block_threads=%d must be a multiple of 64 in [64, %d]", bt, kMaxBlock);
+    if (bt < min_bt) return fail(EA_EINVAL, "block_threads=%d is below %d for %d sites", bt, min_bt, N);
+    *block_threads = bt;
+    *words_resident = wr;
+    return EA_OK;
+}
+
+int device_grid(int layout, int bt, size_t lds, int n_units, int *grid)
+{
+    int dev = 0;
+    EA_HIP(hipGetDevice(&dev));
+    int cus = 0;
+    EA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int per_cu = sweep_max_blocks_per_cu(layout, bt, lds);
+    if (per_cu < 1) return fail(EA_EDEVICE, "sweep kernel cannot be resident with %d threads and %zu B LDS", bt, lds);
+    *grid = std::max(1, std::min(n_units, cus * per_cu));
+    return EA_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void ea_default_options(ea_options *opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof *opt);
+    opt->layout = EA_LAYOUT_CAMSC;
+}
+
+const char *ea_last_error(void) { return g_error.c_str(); }
+
+const char *ea_version(void) { return "ea-mi355x 0.1 (gfx950, Philox4x32-10, CAMSC/AMSC4)"; }
+
+uint32_t ea_swap_threshold(double dbeta_abs, int64_t n) { return swap_thr(dbeta_abs, n); }
+
+int ea_flip_thresholds(const double *betas, int n_T, uint32_t *out)
+{
+    if (!betas || !out || n_T < 1 || n_T > EA_MAX_TEMPS) return fail(EA_EINVAL, "ea_flip_thresholds: bad arguments");
+    for (int k = 0; k < n_T; ++k)
+        for (int u = 0; u < 3; ++u) out[k * 3 + u] = flip_thr(betas[k], u);
+    return EA_OK;
+}
+
+int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int n_realizations, uint64_t seed,
+              const ea_options *opt_in, ea_sim **out)
+{
+    if (!out) return fail(EA_EINVAL, "ea_create: out is NULL");
+    *out = nullptr;
+    ea_options opt;
+    ea_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    if (L < 2 || L > EA_MAX_L) return fail(EA_EINVAL, "L=%d outside [2, %d]", L, EA_MAX_L);
+    if (n_T < 1 || n_T > EA_MAX_TEMPS) return fail(EA_EINVAL, "n_T=%d outside [1, %d]", n_T, EA_MAX_TEMPS);
+    if (n_realizations < 1 || n_realizations > (1 << 19))
+        return fail(EA_EINVAL, "n_realizations=%d outside [1, 2^19]", n_realizations);
+    if (!couplings || !betas) return fail(EA_EINVAL, "couplings and betas must not be NULL");
+    if (opt.layout != EA_LAYOUT_CAMSC && opt.layout != EA_LAYOUT_AMSC4)
+        return fail(EA_EINVAL, "unknown layout %d", opt.layout);
+    if ((opt.dev_alloc == nullptr) != (opt.dev_free == nullptr))
+        return fail(EA_EINVAL, "dev_alloc and dev_free must be given together");
+    for (int k = 0; k < n_T; ++k)
+        if (!std::isfinite(betas[k]) || !(betas[k] > 0.0))
+            return fail(EA_EINVAL, "betas[%d]=%g must be finite and > 0", k, betas[k]);
+    const int N = L * L * L;
+    const size_t nJ = (size_t)n_realizations * N * 3;
+    for (size_t b = 0; b < nJ; ++b)
+        if (couplings[b] != 1 && couplings[b] != -1)
+            return fail(EA_EINVAL, "couplings[%zu]=%d is not +1 or -1", b, (int)couplings[b]);
+
+    const int spw = slots_per_word(opt.layout);
+    const int NW = (n_T + spw - 1) / spw;
+    int bt = 0, wr = 0;
+    if (int rc = plan_launch(N, NW, opt, &bt, &wr)) return rc;
+
+    ea_sim *s = new (std::nothrow) ea_sim;
+    if (!s) return fail(EA_ENOMEM, "host allocation failed");
+    s->L = L; s->N = N; s->n_T = n_T; s->R = n_realizations; s->layout = opt.layout; s->NW = NW;
+    s->block_threads = bt; s->words_resident = wr; s->seed = seed;
+    s->stream = (hipStream_t)opt.stream;
+    s->user_stream = opt.stream != nullptr;
+    s->da.alloc = opt.dev_alloc; s->da.release = opt.dev_free; s->da.ctx = opt.alloc_ctx;
+
+    auto bail = [s](int rc) { release_all(s); delete s; return rc; };
+    hipError_t he = hipGetDevice(&s->device);
+    if (he != hipSuccess) return bail(fail(EA_EDEVICE, "hipGetDevice failed: %s", hipGetErrorString(he)));
+
+    const int ladders = 2 * n_realizations;
+    // tables
+    std::vector<uint32_t> fthr((size_t)n_T * kThrCols, 0u);
+    for (int k = 0; k < n_T; ++k)
+        for (int col = 0; col < kThrCols; ++col) {
+            const int E = col >> 1;
+            fthr[(size_t)k * kThrCols + col] = E < 3 ? flip_thr(betas[k], E) : 0u;
+        }
+    std::vector<int32_t> soff(kMaxTemps, 0), slen(kMaxTemps, 0), ssgn(kMaxTemps, 0);
+    std::vector<uint32_t> sthr;
+    for (int k = 0; k + 1 < n_T; ++k) {
+        const double db = betas[k] - betas[k + 1];
+        ssgn[k] = (db > 0.0) - (db < 0.0);
+        soff[k] = (int32_t)sthr.size();
+        if (ssgn[k] == 0) continue;
+        const double dabs = std::fabs(db);
+        const int64_t cap = 3 * (int64_t)N;   // |U_a - U_b| <= 3N
+        int64_t n = 0;
+        for (; n <= cap; ++n) {
+            const uint32_t v = swap_thr(dabs, n);
+            if (v == 0) break;
+            sthr.push_back(v);
+        }
+        // the thresholds decrease with n; check that the zero tail stays zero
+        for (int64_t m = n; m <= std::min(cap, n + 64); ++m)
+            if (swap_thr(dabs, m) != 0) return bail(fail(EA_EINVAL, "non-monotone swap table for pair %d", k));
+        slen[k] = (int32_t)(sthr.size() - soff[k]);
+    }
+    // couplings as 6 incidence bits per site
+    std::vector<uint8_t> j6((size_t)n_realizations * N);
+    for (int r = 0; r < n_realizations; ++r) {
+        const int8_t *J = couplings + (size_t)r * N * 3;
+        for (int z = 0; z < L; ++z)
+            for (int y = 0; y < L; ++y)
+                for (int x = 0; x < L; ++x) {
+                    const int i = x + L * (y + L * z);
+                    const int im[3] = {((x + L - 1) % L) + L * (y + L * z), x + L * (((y + L - 1) % L) + L * z),
+                                       x + L * (y + L * ((z + L - 1) % L))};
+                    uint8_t b = 0;
+                    for (int mu = 0; mu < 3; ++mu) {
+                        if (J[3 * i + mu] < 0) b |= (uint8_t)(1u << (2 * mu));
+                        if (J[3 * im[mu] + mu] < 0) b |= (uint8_t)(1u << (2 * mu + 1));
+                    }
+                    j6[(size_t)r * N + i] = b;
+                }
+    }
+    std::vector<uint32_t> sites;
+    int32_t class_off[4];
+    int n_classes = 0;
+    colour_classes(L, sites, class_off, &n_classes);
+
+    JobDesc &h = s->h;
+    int rc = EA_OK;
+    void *p = nullptr;
+    if ((rc = dev_alloc(s, (size_t)ladders * NW * N * 4, &p))) return bail(rc);
+    h.spins = (uint32_t *)p;
+    uint8_t *dj6 = nullptr;
+    if ((rc = upload(s, j6, &dj6))) return bail(rc);
+    h.j6 = dj6;
+    std::vector<int32_t> perm((size_t)ladders * kMaxTemps, 0);
+    for (int l = 0; l < ladders; ++l)
+        for (int k = 0; k < n_T; ++k) perm[(size_t)l * kMaxTemps + k] = k;
+    if ((rc = upload(s, perm, &h.temp_of_slot))) return bail(rc);
+    uint32_t *dft = nullptr, *dst = nullptr, *dsites = nullptr;
+    int32_t *doff = nullptr, *dlen = nullptr, *dsgn = nullptr;
+    if ((rc = upload(s, fthr, &dft)) || (rc = upload(s, sthr, &dst)) || (rc = upload(s, soff, &doff)) ||
+        (rc = upload(s, slen, &dlen)) || (rc = upload(s, ssgn, &dsgn)) || (rc = upload(s, sites, &dsites)))
+        return bail(rc);
+    h.flip_thr = dft; h.swap_thr = dst; h.swap_off = doff; h.swap_len = dlen; h.swap_sgn = dsgn; h.sites = dsites;
+    std::vector<uint32_t> counters(2, 0u);
+    if ((rc = upload(s, counters, &s->d_counters))) return bail(rc);
+    h.sweep_ctr = s->d_counters;
+    std::vector<uint32_t> acc((size_t)ladders * kMaxTemps, 0u);
+    if ((rc = upload(s, acc, &h.swap_acc))) return bail(rc);
+    std::vector<uint32_t> units(ladders);
+    for (int l = 0; l < ladders; ++l) units[l] = (uint32_t)l;   // job 0 of a lone launch
+    if ((rc = upload(s, units, &s->d_units))) return bail(rc);
+    for (int c = 0; c < 4; ++c) h.class_off[c] = class_off[c];
+    h.key0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    h.key1 = (uint32_t)(seed >> 32);
+    h.L = L; h.N = N; h.n_T = n_T; h.NW = NW; h.n_classes = n_classes; h.words_resident = wr;
+    h.n_sweeps = 0; h.swap_every = 0; h.ladders = ladders; h.block_threads = bt;
+    s->swap_total = (int64_t)sthr.size();
+    std::vector<JobDesc> hv(1, h);
+    if ((rc = upload(s, hv, &s->d_job))) return bail(rc);
+    he = launch_init_spins(s->d_job, h, s->layout, s->stream);
+    if (he != hipSuccess) return bail(fail(EA_EDEVICE, "init kernel launch failed: %s", hipGetErrorString(he)));
+    he = hipStreamSynchronize(s->stream);
+    if (he != hipSuccess) return bail(fail(EA_EDEVICE, "init kernel failed: %s", hipGetErrorString(he)));
+    *out = s;
+    return EA_OK;
+}
+
+void ea_destroy(ea_sim *s)
+{
+    if (!s) return;
+    (void)hipSetDevice(s->device);
+    (void)hipStreamSynchronize(s->stream);
+    release_all(s);
+    delete s;
+}
+
+int ea_get_dims(const ea_sim *s, int *L, int *n_T, int *R, int *layout)
+{
+    if (!s) return fail(EA_EINVAL, "ea_get_dims: NULL handle");
+    if (L) *L = s->L;
+    if (n_T) *n_T = s->n_T;
+    if (R) *R = s->R;
+    if (layout) *layout = s->layout;
+    return EA_OK;
+}
+
+int ea_sweep(ea_sim *s, int64_t n_sweeps, int swap_every)
+{
+    return ea_sweep_batch(&s, 1, &n_sweeps, &swap_every);
+}
+
+int ea_sweep_batch(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps, const int *swap_every)
+{
+    if (!sims || n_sims < 1 || !n_sweeps || !swap_every) return fail(EA_EINVAL, "ea_sweep_batch: bad arguments");
+    if (n_sims > 4095) return fail(EA_EINVAL, "at most 4095 jobs per launch");
+    const int layout = sims[0] ? sims[0]->layout : 0;
+    int64_t total_units = 0;
+    for (int j = 0; j < n_sims; ++j) {
+        ea_sim *s = sims[j];
+        if (!s) return fail(EA_EINVAL, "sims[%d] is NULL", j);
+        if (s->layout != layout) return fail(EA_EINVAL, "sims[%d] has a different layout", j);
+        if (s->device != sims[0]->device) return fail(EA_EINVAL, "sims[%d] lives on another device", j);
+        if (n_sweeps[j] < 0 || n_sweeps[j] > 0x7FFFFFFF) return fail(EA_EINVAL, "n_sweeps[%d] out of range", j);
+        if (swap_every[j] < 0) return fail(EA_EINVAL, "swap_every[%d] < 0", j);
+        if (s->t + n_sweeps[j] >= ((int64_t)1 << 32))
+            return fail(EA_ESTATE, "sweep counter of sims[%d] would reach 2^32", j);
+        for (int i = 0; i < j; ++i)
+            if (sims[i] == s) return fail(EA_EINVAL, "sims[%d] appears twice", j);
+        total_units += n_sweeps[j] > 0 ? s->h.ladders : 0;
+    }
+    if (total_units == 0) return EA_OK;
+    ea_sim *s0 = sims[0];
+    EA_HIP(hipSetDevice(s0->device));
+    hipStream_t st = s0->stream;
+
+    if (n_sims == 1) {
+        ea_sim *s = s0;
+        s->h.n_sweeps = (int32_t)n_sweeps[0];
+        s->h.swap_every = swap_every[0];
+        EA_HIP(hipMemcpyAsync(&s->d_job->n_sweeps, &s->h.n_sweeps, 2 * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        const size_t lds = lds_bytes(s->N, s->words_resident, s->block_threads);
+        int grid = 0;
+        if (int rc = device_grid(layout, s->block_threads, lds, s->h.ladders, &grid)) return rc;
+        EA_HIP(launch_sweep(s->d_job, 1, s->d_units, s->h.ladders, s->d_counters + 1, layout, s->block_threads, lds,
+                            grid, st));
+        s->t += n_sweeps[0];
+        return sync_if_needed(s);
+    }
+
+    // several jobs: one descriptor per job, units sorted by work (largest first)
+    std::vector<JobDesc> descs(n_sims);
+    std::vector<std::pair<double, uint32_t>> order;
+    int bt = 0;
+    size_t lds = 0;
+    for (int j = 0; j < n_sims; ++j) {
+        ea_sim *s = sims[j];
+        descs[j] = s->h;
+        descs[j].n_sweeps = (int32_t)n_sweeps[j];
+        descs[j].swap_every = swap_every[j];
+        if (n_sweeps[j] == 0) continue;
+        bt = std::max(bt, s->block_threads);
+        lds = std::max(lds, lds_bytes(s->N, s->words_resident, s->block_threads));
+        const double work = (double)s->N * s->n_T * (double)n_sweeps[j];
+        for (int l = 0; l < s->h.ladders; ++l) order.push_back({-work, ((uint32_t)j << 20) | (uint32_t)l});
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<double, uint32_t> &a, const std::pair<double, uint32_t> &b) { return a.first < b.first; });
+    std::vector<uint32_t> units(order.size());
+    for (size_t k = 0; k < order.size(); ++k) units[k] = order[k].second;
+    // one queue counter, shared by the launch
+    JobDesc *d_descs = nullptr;
+    uint32_t *d_units = nullptr, *d_queue = nullptr;
+    EA_HIP(hipMalloc(&d_descs, descs.size() * sizeof(JobDesc)));
+    auto cleanup = [&]() {
+        (void)hipFree(d_descs);
+        if (d_units) (void)hipFree(d_units);
+        if (d_queue) (void)hipFree(d_queue);
+    };
+    hipError_t e = hipMalloc(&d_units, units.size() * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&d_queue, sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemcpyAsync(d_descs, descs.data(), descs.size() * sizeof(JobDesc), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_units, units.data(), units.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(d_queue, 0, sizeof(uint32_t), st);
+    int grid = 0;
+    if (e == hipSuccess) {
+        if (int rc = device_grid(layout, bt, lds, (int)units.size(), &grid)) {
+            cleanup();
+            return rc;
+        }
+        e = launch_sweep(d_descs, n_sims, d_units, (int)units.size(), d_queue, layout, bt, lds, grid, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    cleanup();
+    if (e != hipSuccess) return fail(EA_EDEVICE, "batched sweep failed: %s", hipGetErrorString(e));
+    for (int j = 0; j < n_sims; ++j) sims[j]->t += n_sweeps[j];
+    return EA_OK;
+}
+
+int ea_observables(ea_sim *s, int32_t *energy, int32_t *overlap)
+{
+    if (!s) return fail(EA_EINVAL, "ea_observables: NULL handle");
+    EA_HIP(hipSetDevice(s->device));
+    const size_t ne = (size_t)s->R * 2 * s->n_T, nq = (size_t)s->R * s->n_T;
+    int32_t *d = nullptr;
+    EA_HIP(hipMalloc(&d, (ne + nq) * sizeof(int32_t)));
+    hipError_t e = launch_observables(s->d_job, s->h, s->layout, d, d + ne, s->stream);
+    if (e == hipSuccess && energy) e = hipMemcpyAsync(energy, d, ne * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess && overlap) e = hipMemcpyAsync(overlap, d + ne, nq * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(EA_EDEVICE, "observables failed: %s", hipGetErrorString(e));
+    return EA_OK;
+}
+
+int ea_state(ea_sim *s, int8_t *spins, int32_t *temp_of_slot, int64_t *sweeps_done)
+{
+    if (!s) return fail(EA_EINVAL, "ea_state: NULL handle");
+    EA_HIP(hipSetDevice(s->device));
+    const int ladders = 2 * s->R;
+    hipError_t e = hipSuccess;
+    if (spins) {
+        const size_t n = (size_t)ladders * s->n_T * s->N;
+        int8_t *d = nullptr;
+        EA_HIP(hipMalloc(&d, n));
+        e = launch_unpack(s->d_job, s->h, s->layout, d, s->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(spins, d, n, hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        (void)hipFree(d);
+        if (e != hipSuccess) return fail(EA_EDEVICE, "state readout failed: %s", hipGetErrorString(e));
+    }
+    if (temp_of_slot) {
+        std::vector<int32_t> perm((size_t)ladders * kMaxTemps);
+        EA_HIP(hipMemcpyAsync(perm.data(), s->h.temp_of_slot, perm.size() * 4, hipMemcpyDeviceToHost, s->stream));
+        EA_HIP(hipStreamSynchronize(s->stream));
+        for (int l = 0; l < ladders; ++l)
+            for (int k = 0; k < s->n_T; ++k) temp_of_slot[(size_t)l * s->n_T + k] = perm[(size_t)l * kMaxTemps + k];
+    }
+    if (sweeps_done) {
+        uint32_t t = 0;
+        EA_HIP(hipMemcpyAsync(&t, s->d_counters, sizeof t, hipMemcpyDeviceToHost, s->stream));
+        EA_HIP(hipStreamSynchronize(s->stream));
+        *sweeps_done = (int64_t)t;
+    }
+    return EA_OK;
+}
+
+int ea_set_state(ea_sim *s, const int8_t *spins, const int32_t *temp_of_slot, int64_t sweeps_done)
+{
+    if (!s || !spins || !temp_of_slot) return fail(EA_EINVAL, "ea_set_state: NULL argument");
+    if (sweeps_done < 0 || sweeps_done >= ((int64_t)1 << 32)) return fail(EA_EINVAL, "sweeps_done out of range");
+    const int ladders = 2 * s->R;
+    const size_t n = (size_t)ladders * s->n_T * s->N;
+    for (size_t b = 0; b < n; ++b)
+        if (spins[b] != 1 && spins[b] != -1) return fail(EA_EINVAL, "spins[%zu]=%d is not +1 or -1", b, (int)spins[b]);
+    std::vector<int32_t> perm((size_t)ladders * kMaxTemps, 0);
+    for (int l = 0; l < ladders; ++l) {
+        std::vector<int> seen(s->n_T, 0);
+        for (int k = 0; k < s->n_T; ++k) {
+            const int32_t v = temp_of_slot[(size_t)l * s->n_T + k];
+            if (v < 0 || v >= s->n_T || seen[v]) return fail(EA_EINVAL, "temp_of_slot of ladder %d is not a permutation", l);
+            seen[v] = 1;
+            perm[(size_t)l * kMaxTemps + k] = v;
+        }
+    }
+    EA_HIP(hipSetDevice(s->device));
+    int8_t *d = nullptr;
+    EA_HIP(hipMalloc(&d, n));
+    const uint32_t t = (uint32_t)sweeps_done;
+    hipError_t e = hipMemcpyAsync(d, spins, n, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = launch_pack(s->d_job, s->h, s->layout, d, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->h.temp_of_slot, perm.data(), perm.size() * 4, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(s->d_counters, &t, sizeof t, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(EA_EDEVICE, "state upload failed: %s", hipGetErrorString(e));
+    s->t = sweeps_done;
+    return EA_OK;
+}
+
+int ea_swap_acceptance(ea_sim *s, uint64_t *accepted)
+{
+    if (!s || !accepted) return fail(EA_EINVAL, "ea_swap_acceptance: NULL argument");
+    EA_HIP(hipSetDevice(s->device));
+    const int ladders = 2 * s->R;
+    std::vector<uint32_t> acc((size_t)ladders * kMaxTemps);
+    EA_HIP(hipMemcpyAsync(acc.data(), s->h.swap_acc, acc.size() * 4, hipMemcpyDeviceToHost, s->stream));
+    EA_HIP(hipStreamSynchronize(s->stream));
+    for (int l = 0; l < ladders; ++l)
+        for (int k = 0; k + 1 < s->n_T; ++k)
+            accepted[(size_t)l * (s->n_T - 1) + k] = acc[(size_t)l * kMaxTemps + k];
+    return EA_OK;
+}
+
+}  // extern "C"

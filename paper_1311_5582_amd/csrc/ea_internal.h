@@ -1,0 +1,83 @@
+// Internal declarations shared by the host side (ea_api.cpp) and the HIP
+// kernels (ea_kernels.hip) of the library.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ea {
+
+// Philox4x32 constants (Salmon et al., SC'11): multipliers and Weyl key bumps.
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+constexpr int kPhiloxRounds = 10;
+
+// Stream domains, counter word 3 bits 28..31.
+constexpr uint32_t kDomainFlip = 0u;
+constexpr uint32_t kDomainSwap = 1u;
+constexpr uint32_t kDomainInit = 2u;
+
+constexpr int kMaxTemps = 64;
+constexpr int kThrCols = 16;          // threshold row: column 2E+S, E in 0..6, S in 0..1
+constexpr int kMaxBlock = 1024;
+constexpr int kMaxWaves = kMaxBlock / 64;
+
+// Layout parameters: slots per 32-bit word and the bit stride between slots.
+template <int LAYOUT> struct Layout;
+template <> struct Layout<0> { static constexpr int kSlotsPerWord = 32; static constexpr int kStride = 1; };
+template <> struct Layout<1> { static constexpr int kSlotsPerWord = 8;  static constexpr int kStride = 4; };
+
+inline int slots_per_word(int layout) { return layout == 0 ? 32 : 8; }
+
+// One job (an ea_sim) as the kernels see it.  Lives in device memory.
+struct JobDesc {
+    uint32_t *spins;          // [ladders][NW][N] packed words, ladder = 2r + copy
+    const uint8_t *j6;        // [R][N] bit d set iff incidence d has J = -1;
+                              // d = 0:+x 1:-x 2:+y 3:-y 4:+z 5:-z
+    int32_t *temp_of_slot;    // [ladders][kMaxTemps]
+    const uint32_t *flip_thr; // [n_T][kThrCols] by column 2E+S (columns >= 6 are 0)
+    const uint32_t *swap_thr; // concatenated per-pair tables, entry n = |U_a - U_b|
+    const int32_t *swap_off;  // [kMaxTemps] start of pair k's table in swap_thr
+    const int32_t *swap_len;  // [kMaxTemps] entries of pair k (beyond: threshold 0)
+    const int32_t *swap_sgn;  // [kMaxTemps] sign of beta_k - beta_{k+1}
+    const uint32_t *sites;    // [N] packed x | y<<8 | z<<16, grouped by colour class
+    uint32_t *sweep_ctr;      // sweeps done (next sweep index); advanced after each launch
+    uint32_t *swap_acc;       // [ladders][kMaxTemps] accepted swaps per pair
+    int32_t class_off[4];     // colour class c = sites[class_off[c] .. class_off[c+1])
+    uint32_t key0, key1;      // Philox key
+    int32_t L, N, n_T, NW;    // NW = words per site
+    int32_t n_classes;
+    int32_t words_resident;   // words held in LDS at once (== NW: load once per launch)
+    int32_t n_sweeps;         // sweeps in this launch
+    int32_t swap_every;       // 0 = no PT
+    int32_t ladders;          // 2R
+    int32_t block_threads;    // workgroup size this job was planned for
+};
+
+// Dynamic LDS bytes a workgroup needs for a job with `words` resident words.
+inline size_t lds_bytes(int N, int words, int block_threads)
+{
+    (void)block_threads;
+    size_t b = (size_t)words * N * 4;              // spin words
+    b += ((size_t)N + 15) / 16 * 16;               // j6 bytes
+    b += (size_t)kMaxTemps * kThrCols * 4;         // threshold rows by slot
+    b += (size_t)kMaxTemps * 4 * 4;                // U, temp_of_slot, slot_of_temp, draws
+    b += (size_t)kMaxTemps * 8;                    // speculative accept masks
+    return b;
+}
+
+// Host-side launchers (ea_kernels.hip).  Each returns the first HIP error.
+hipError_t launch_init_spins(const JobDesc *d_job, const JobDesc &h_job, int layout, hipStream_t s);
+hipError_t launch_sweep(const JobDesc *d_jobs, int n_jobs, const uint32_t *d_units, int n_units,
+                        uint32_t *d_queue, int layout, int block_threads, size_t lds, int grid,
+                        hipStream_t s);
+hipError_t launch_observables(const JobDesc *d_job, const JobDesc &h_job, int layout, int32_t *d_energy,
+                              int32_t *d_overlap, hipStream_t s);
+hipError_t launch_unpack(const JobDesc *d_job, const JobDesc &h_job, int layout, int8_t *d_spins, hipStream_t s);
+hipError_t launch_pack(const JobDesc *d_job, const JobDesc &h_job, int layout, const int8_t *d_spins, hipStream_t s);
+hipError_t sweep_kernel_attributes(int layout, int *max_threads, int *num_regs);
+int sweep_max_blocks_per_cu(int layout, int block_threads, size_t lds);
+
+}  // namespace ea

@@ -1,0 +1,98 @@
+"""C-ABI checks that need no GPU: the library loads and exports every
+function include/ea.h declares, the host-side threshold tables agree with the
+oracle's (two independent implementations of Sec. 4.3.1-4.3.2), and invalid
+arguments are rejected before any device call."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+from paper_1311_5582_amd import binding as B
+from paper_1311_5582_amd import inputs
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return B.lib()
+
+
+def test_exports_every_declared_function(lib):
+    names = B.header_functions()
+    assert "ea_create" in names and "ea_sweep" in names and "ea_observables" in names and "ea_state" in names
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in include/ea.h but not exported"
+
+
+def test_version_string(lib):
+    assert b"gfx950" in lib.ea_version()
+
+
+def test_flip_thresholds_match_oracle(lib, oracle_lib):
+    betas = np.concatenate([inputs.geometric_betas(48, 0.35, 2.0), [1e-9, 0.01, 0.25, math.log(2) / 4, 5.5, 5.6, 40.0]])
+    for chunk in (betas[:48], betas[48:]):
+        thr = B.flip_thresholds(chunk)
+        for k, b in enumerate(chunk):
+            for u in range(3):
+                assert int(thr[k, u]) == oracle_lib.flip_threshold(b, u), (b, u)
+
+
+def test_swap_thresholds_match_oracle(lib, oracle_lib):
+    rng = np.random.default_rng(0)
+    for db in list(rng.uniform(1e-4, 1.0, 40)) + [math.log(2) / 2, 1e-9]:
+        for n in list(range(0, 70)) + list(rng.integers(0, 3 * 24 ** 3, 30)):
+            assert B.swap_threshold(db, n) == oracle_lib.swap_threshold(db, n), (db, n)
+
+
+def _create(lib, L=4, n_T=4, R=1, J=None, betas=None, layout=0, block_threads=0, words_resident=0):
+    if J is None:
+        J = inputs.couplings(L, R, seed=1) if L >= 2 else np.ones((R, max(L, 1) ** 3, 3), np.int8)
+    if betas is None:
+        betas = inputs.geometric_betas(max(n_T, 1), 0.5, 2.0)[:max(n_T, 0)] if n_T > 0 else np.zeros(1)
+    J = np.ascontiguousarray(J, dtype=np.int8)
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    opt = B.Options()
+    lib.ea_default_options(ctypes.byref(opt))
+    opt.layout, opt.block_threads, opt.words_resident = layout, block_threads, words_resident
+    h = ctypes.c_void_p()
+    rc = lib.ea_create(L, J.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                       b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n_T, R, 7, ctypes.byref(opt),
+                       ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("case", [
+    dict(L=1), dict(L=33), dict(n_T=0), dict(n_T=65, betas=np.full(65, 1.0)), dict(R=0),
+    dict(layout=2), dict(block_threads=100), dict(block_threads=2048), dict(block_threads=64, L=24),
+    dict(betas=[1.0, 0.0, 0.5, 0.2]), dict(betas=[1.0, -1.0, 0.5, 0.2]), dict(betas=[1.0, float("nan"), 0.5, 0.2]),
+    dict(betas=[1.0, float("inf"), 0.5, 0.2]), dict(words_resident=-1),
+    dict(L=32, n_T=64, words_resident=2, J=np.ones((1, 32 ** 3, 3), np.int8)),
+])
+def test_create_rejects_invalid_arguments(lib, case):
+    if "J" not in case and case.get("L", 4) in (1, 33):
+        L = case["L"]
+        case = dict(case, J=np.ones((1, L ** 3, 3), np.int8))
+    rc, h = _create(lib, **case)
+    assert rc == B.EA_EINVAL, (case, rc, B.last_error())
+    assert h.value is None
+    assert B.last_error()
+
+
+def test_create_rejects_bad_couplings(lib):
+    J = inputs.couplings(4, 2, seed=3)
+    J[1, 17, 2] = 0
+    rc, _ = _create(lib, L=4, R=2, J=J)
+    assert rc == B.EA_EINVAL and "couplings" in B.last_error()
+
+
+def test_null_arguments(lib):
+    out = ctypes.c_void_p()
+    assert lib.ea_create(4, None, None, 4, 1, 0, None, ctypes.byref(out)) == B.EA_EINVAL
+    assert lib.ea_create(4, None, None, 4, 1, 0, None, None) == B.EA_EINVAL
+    assert lib.ea_sweep(None, 1, 1) == B.EA_EINVAL
+    assert lib.ea_observables(None, None, None) == B.EA_EINVAL
+    assert lib.ea_state(None, None, None, None) == B.EA_EINVAL
+    assert lib.ea_set_state(None, None, None, 0) == B.EA_EINVAL
+    assert lib.ea_swap_acceptance(None, None) == B.EA_EINVAL
+    lib.ea_destroy(None)
+    assert lib.ea_flip_thresholds(None, 3, None) == B.EA_EINVAL
