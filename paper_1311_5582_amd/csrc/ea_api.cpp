@@ -160,6 +160,9 @@ constexpr size_t kLdsBudget = 160 * 1024 - 1024;   // dynamic LDS; the rest is s
 int plan_launch(int N, int NW, const ea_options &opt, int *block_threads, int *words_resident)
 {
     // words resident in LDS
+    const LdsLayout lay = lds_layout(N, 1);
+    if (lay.mask % 8 != 0 || lay.spin % 16 != 0 || lay.thr % 16 != 0)
+        return fail(EA_EINVAL, "internal LDS layout misaligned for %d sites", N);
     const size_t fixed = lds_bytes(N, 0, 0);
     if (fixed + (size_t)N * 4 > kLdsBudget)
         return fail(EA_EINVAL, "lattice of %d sites does not fit one spin word in LDS", N);

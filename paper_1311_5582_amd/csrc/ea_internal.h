@@ -56,16 +56,39 @@ struct JobDesc {
     int32_t block_threads;    // workgroup size this job was planned for
 };
 
-// Dynamic LDS bytes a workgroup needs for a job with `words` resident words.
-inline size_t lds_bytes(int N, int words, int block_threads)
+// Dynamic LDS carve-up of the sweep kernel, one definition for host and
+// device.  The fixed-size tables come first so that every region is naturally
+// aligned whatever N is (the 64-bit accept masks need 8-byte alignment).
+struct LdsLayout {
+    uint32_t thr;     // [kMaxTemps][kThrCols] u32 threshold rows by slot
+    uint32_t U;       // [kMaxTemps] i32 unsatisfied bonds per slot
+    uint32_t perm;    // [kMaxTemps] i32 temp_of_slot
+    uint32_t sot;     // [kMaxTemps] i32 slot_of_temp
+    uint32_t draw;    // [kMaxTemps] u32 swap draws
+    uint32_t mask;    // [kMaxTemps] u64 speculative accept bits
+    uint32_t spin;    // [words][N] u32 spin words
+    uint32_t j6;      // [N] u8 coupling bits
+    uint32_t total;
+};
+
+__host__ __device__ inline LdsLayout lds_layout(int N, int words)
 {
-    (void)block_threads;
-    size_t b = (size_t)words * N * 4;              // spin words
-    b += ((size_t)N + 15) / 16 * 16;               // j6 bytes
-    b += (size_t)kMaxTemps * kThrCols * 4;         // threshold rows by slot
-    b += (size_t)kMaxTemps * 4 * 4;                // U, temp_of_slot, slot_of_temp, draws
-    b += (size_t)kMaxTemps * 8;                    // speculative accept masks
-    return b;
+    LdsLayout l;
+    l.thr = 0;
+    l.U = l.thr + kMaxTemps * kThrCols * 4;
+    l.perm = l.U + kMaxTemps * 4;
+    l.sot = l.perm + kMaxTemps * 4;
+    l.draw = l.sot + kMaxTemps * 4;
+    l.mask = l.draw + kMaxTemps * 4;
+    l.spin = l.mask + kMaxTemps * 8;
+    l.j6 = l.spin + (uint32_t)words * (uint32_t)N * 4u;
+    l.total = l.j6 + ((uint32_t)N + 15u) / 16u * 16u;
+    return l;
+}
+
+inline size_t lds_bytes(int N, int words, int /*block_threads*/)
+{
+    return lds_layout(N, words).total;
 }
 
 // Host-side launchers (ea_kernels.hip).  Each returns the first HIP error.

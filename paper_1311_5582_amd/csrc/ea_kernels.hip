@@ -96,7 +96,7 @@ __device__ __forceinline__ Nbrs neighbours(uint32_t xyz, int L)
     return n;
 }
 
-// LDS carve-up; must match lds_bytes().
+// LDS regions of the sweep kernel (offsets from lds_layout()).
 struct Smem {
     uint32_t *spin;   // [words_resident][N]
     uint8_t *j6;      // [N]
@@ -110,19 +110,16 @@ struct Smem {
 
 __device__ __forceinline__ Smem carve(uint8_t *base, int N, int words)
 {
+    const LdsLayout l = lds_layout(N, words);
     Smem s;
-    s.spin = (uint32_t *)base;
-    base += (size_t)words * N * 4;
-    s.j6 = base;
-    base += ((size_t)N + 15) / 16 * 16;
-    s.thr = (uint32_t *)base;
-    base += (size_t)kMaxTemps * kThrCols * 4;
-    s.U = (int32_t *)base;
-    s.perm = s.U + kMaxTemps;
-    s.sot = s.perm + kMaxTemps;
-    s.draw = (uint32_t *)(s.sot + kMaxTemps);
-    base += (size_t)kMaxTemps * 4 * 4;
-    s.mask = (uint64_t *)base;
+    s.thr = (uint32_t *)(base + l.thr);
+    s.U = (int32_t *)(base + l.U);
+    s.perm = (int32_t *)(base + l.perm);
+    s.sot = (int32_t *)(base + l.sot);
+    s.draw = (uint32_t *)(base + l.draw);
+    s.mask = (uint64_t *)(base + l.mask);
+    s.spin = (uint32_t *)(base + l.spin);
+    s.j6 = base + l.j6;
     return s;
 }
 
