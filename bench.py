@@ -65,8 +65,12 @@ def main():
     ap.add_argument("--workload", default="L16_R64")
     ap.add_argument("--layout", default="camsc", choices=["camsc", "amsc4"])
     ap.add_argument("--block-threads", type=int, default=0)
+    ap.add_argument("--swap-every", type=int, default=-1, help="override the workload's PT interval")
     ap.add_argument("--cpu-sweeps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before timing, run one plain device-to-device copy of this many MiB "
+                         "(reference kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -85,7 +89,7 @@ def main():
     J = inputs.couplings(L, R, cfg["seed"])
     betas = inputs.geometric_betas(n_T, cfg["t_min"], cfg["t_max"])
     sim = B.Sim(L, J, betas, cfg["seed"], layout=args.layout, block_threads=args.block_threads, stream=stream)
-    S, se = args.sweeps_per_step, cfg["swap_every"]
+    S, se = args.sweeps_per_step, (cfg["swap_every"] if args.swap_every < 0 else args.swap_every)
 
     def step(events=None):
         if events is not None:
@@ -95,6 +99,14 @@ def main():
             events[1].record(stream)
         return sim.observables()
 
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20)
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()

@@ -88,6 +88,7 @@ struct ea_sim {
     uint32_t *d_units = nullptr;      // ladders of this job for a lone launch
     uint32_t *d_counters = nullptr;   // [0] sweep counter, [1] work queue
     int64_t swap_total = 0;           // entries in the swap tables
+    size_t lds = 0;                   // dynamic LDS bytes of this job's sweep workgroups
 };
 
 namespace {
@@ -156,14 +157,37 @@ void colour_classes(int L, std::vector<uint32_t> &sites, int32_t off[4], int *n_
 }
 
 constexpr size_t kLdsBudget = 160 * 1024 - 1024;   // dynamic LDS; the rest is static
+constexpr size_t kLdsPerCu = 160 * 1024;
+constexpr int kThreadsPerCu = 2048;
+
+// Workgroups of `bt` threads and `lds` bytes that fit on one CU.
+int wgs_per_cu(size_t lds, int bt)
+{
+    const int by_lds = (int)(kLdsPerCu / (lds + 1024));
+    return std::max(0, std::min(by_lds, kThreadsPerCu / bt));
+}
+
+// Optional LDS copies (swap tables, odd-L site list) are taken only when they
+// fit and do not lower the number of workgroups a CU can hold.
+void plan_optional_lds(int N, int wr, int bt, bool odd, int64_t swap_entries, int *swap_lds, int *sites_lds)
+{
+    *swap_lds = 0;
+    *sites_lds = 0;
+    auto total = [&](int sw, int si) { return (size_t)lds_layout(N, wr, sw, si).total; };
+    const int base = wgs_per_cu(total(0, 0), bt);
+    if (odd && total(0, N) <= kLdsBudget && wgs_per_cu(total(0, N), bt) >= base) *sites_lds = N;
+    if (swap_entries > 0 && swap_entries < (1 << 20) && total((int)swap_entries, *sites_lds) <= kLdsBudget &&
+        wgs_per_cu(total((int)swap_entries, *sites_lds), bt) >= base)
+        *swap_lds = (int)swap_entries;
+}
 
 int plan_launch(int N, int NW, const ea_options &opt, int *block_threads, int *words_resident)
 {
     // words resident in LDS
-    const LdsLayout lay = lds_layout(N, 1);
-    if (lay.mask % 8 != 0 || lay.spin % 16 != 0 || lay.thr % 16 != 0)
+    const LdsLayout lay = lds_layout(N, 1, 1, 1);
+    if (lay.mask % 8 != 0 || lay.spin % 16 != 0 || lay.thr % 16 != 0 || lay.stab % 4 != 0 || lay.sites % 4 != 0)
         return fail(EA_EINVAL, "internal LDS layout misaligned for %d sites", N);
-    const size_t fixed = lds_bytes(N, 0, 0);
+    const size_t fixed = lds_layout(N, 0, 0, 0).total;
     if (fixed + (size_t)N * 4 > kLdsBudget)
         return fail(EA_EINVAL, "lattice of %d sites does not fit one spin word in LDS", N);
     int wr_max = (int)((kLdsBudget - fixed) / ((size_t)N * 4));
@@ -354,7 +378,12 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
     h.key1 = (uint32_t)(seed >> 32);
     h.L = L; h.N = N; h.n_T = n_T; h.NW = NW; h.n_classes = n_classes; h.words_resident = wr;
     h.n_sweeps = 0; h.swap_every = 0; h.ladders = ladders; h.block_threads = bt;
+    h.seg_bits = 4;
+    h.invL = 1.0f / (float)L;
+    h.invH = 1.0f / (float)(L / 2 > 0 ? L / 2 : 1);
     s->swap_total = (int64_t)sthr.size();
+    plan_optional_lds(N, wr, bt, L % 2 != 0, s->swap_total, &h.swap_lds, &h.sites_lds);
+    s->lds = lds_layout(N, wr, h.swap_lds, h.sites_lds).total;
     std::vector<JobDesc> hv(1, h);
     if ((rc = upload(s, hv, &s->d_job))) return bail(rc);
     he = launch_init_spins(s->d_job, h, s->layout, s->stream);
@@ -418,7 +447,7 @@ int ea_sweep_batch(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps, con
         s->h.n_sweeps = (int32_t)n_sweeps[0];
         s->h.swap_every = swap_every[0];
         EA_HIP(hipMemcpyAsync(&s->d_job->n_sweeps, &s->h.n_sweeps, 2 * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        const size_t lds = lds_bytes(s->N, s->words_resident, s->block_threads);
+        const size_t lds = s->lds;
         int grid = 0;
         if (int rc = device_grid(layout, s->block_threads, lds, s->h.ladders, &grid)) return rc;
         EA_HIP(launch_sweep(s->d_job, 1, s->d_units, s->h.ladders, s->d_counters + 1, layout, s->block_threads, lds,
@@ -439,7 +468,7 @@ int ea_sweep_batch(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps, con
         descs[j].swap_every = swap_every[j];
         if (n_sweeps[j] == 0) continue;
         bt = std::max(bt, s->block_threads);
-        lds = std::max(lds, lds_bytes(s->N, s->words_resident, s->block_threads));
+        lds = std::max(lds, s->lds);
         const double work = (double)s->N * s->n_T * (double)n_sweeps[j];
         for (int l = 0; l < s->h.ladders; ++l) order.push_back({-work, ((uint32_t)j << 20) | (uint32_t)l});
     }

@@ -54,6 +54,11 @@ struct JobDesc {
     int32_t swap_every;       // 0 = no PT
     int32_t ladders;          // 2R
     int32_t block_threads;    // workgroup size this job was planned for
+    int32_t swap_lds;         // swap-table entries copied to LDS (0: read from HBM)
+    int32_t sites_lds;        // odd L: site list entries copied to LDS (0: read from HBM)
+    float invL, invH;         // 1/L and 1/(L/2), exact quotients for indices < 2^15
+    uint32_t seg_bits;        // 4: width of a 2E+S segment (a runtime value on purpose: a
+                              // constant width lets the compiler split v_bfe_u32 into shift+mask)
 };
 
 // Dynamic LDS carve-up of the sweep kernel, one definition for host and
@@ -61,34 +66,43 @@ struct JobDesc {
 // aligned whatever N is (the 64-bit accept masks need 8-byte alignment).
 struct LdsLayout {
     uint32_t thr;     // [kMaxTemps][kThrCols] u32 threshold rows by slot
+    uint32_t fthr;    // [kMaxTemps][kThrCols] u32 threshold rows by temperature
     uint32_t U;       // [kMaxTemps] i32 unsatisfied bonds per slot
     uint32_t perm;    // [kMaxTemps] i32 temp_of_slot
     uint32_t sot;     // [kMaxTemps] i32 slot_of_temp
     uint32_t draw;    // [kMaxTemps] u32 swap draws
+    uint32_t soff;    // [kMaxTemps] i32 swap table offsets
+    uint32_t slen;    // [kMaxTemps] i32 swap table lengths
+    uint32_t ssgn;    // [kMaxTemps] i32 sign of beta_k - beta_{k+1}
+    uint32_t acc;     // [kMaxTemps] u32 accepted swaps of this unit
     uint32_t mask;    // [kMaxTemps] u64 speculative accept bits
     uint32_t spin;    // [words][N] u32 spin words
+    uint32_t stab;    // [swap_entries] u32 swap tables (optional)
+    uint32_t sites;   // [site_entries] u32 packed coordinates (optional)
     uint32_t j6;      // [N] u8 coupling bits
     uint32_t total;
 };
 
-__host__ __device__ inline LdsLayout lds_layout(int N, int words)
+__host__ __device__ inline LdsLayout lds_layout(int N, int words, int swap_entries, int site_entries)
 {
     LdsLayout l;
     l.thr = 0;
-    l.U = l.thr + kMaxTemps * kThrCols * 4;
+    l.fthr = l.thr + kMaxTemps * kThrCols * 4;
+    l.U = l.fthr + kMaxTemps * kThrCols * 4;
     l.perm = l.U + kMaxTemps * 4;
     l.sot = l.perm + kMaxTemps * 4;
     l.draw = l.sot + kMaxTemps * 4;
-    l.mask = l.draw + kMaxTemps * 4;
+    l.soff = l.draw + kMaxTemps * 4;
+    l.slen = l.soff + kMaxTemps * 4;
+    l.ssgn = l.slen + kMaxTemps * 4;
+    l.acc = l.ssgn + kMaxTemps * 4;
+    l.mask = l.acc + kMaxTemps * 4;
     l.spin = l.mask + kMaxTemps * 8;
-    l.j6 = l.spin + (uint32_t)words * (uint32_t)N * 4u;
+    l.stab = l.spin + (uint32_t)words * (uint32_t)N * 4u;
+    l.sites = l.stab + (uint32_t)swap_entries * 4u;
+    l.j6 = l.sites + (uint32_t)site_entries * 4u;
     l.total = l.j6 + ((uint32_t)N + 15u) / 16u * 16u;
     return l;
-}
-
-inline size_t lds_bytes(int N, int words, int /*block_threads*/)
-{
-    return lds_layout(N, words).total;
 }
 
 // Host-side launchers (ea_kernels.hip).  Each returns the first HIP error.

@@ -66,24 +66,19 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
     return {c0, c1, c2, c3};
 }
 
-// 4-bit field of a segment word, as a plain v_bfe_u32 (kept out of the
-// compiler's shift/mask canonicalisation so that the scaled LDS address is
-// one v_lshl_add_u32 away).
-__device__ __forceinline__ uint32_t field4(uint32_t x, int shift)
+// Segment field of a 2E+S word: v_bfe_u32 with the width in a register.
+__device__ __forceinline__ uint32_t field4(uint32_t x, int shift, uint32_t width)
 {
-    uint32_t r;
-    asm("v_bfe_u32 %0, %1, %2, 4" : "=v"(r) : "v"(x), "i"(shift));
-    return r;
+    return __builtin_amdgcn_ubfe(x, (uint32_t)shift, width);
 }
 
-// Site index and the six neighbour indices (periodic) from packed coordinates.
+// Site index and the six neighbour indices (periodic).
 struct Nbrs {
     int i, xp, xm, yp, ym, zp, zm;
 };
 
-__device__ __forceinline__ Nbrs neighbours(uint32_t xyz, int L)
+__device__ __forceinline__ Nbrs neighbours(int x, int y, int z, int L)
 {
-    const int x = xyz & 0xFF, y = (xyz >> 8) & 0xFF, z = xyz >> 16;
     const int LL = L * L;
     Nbrs n;
     n.i = x + L * y + LL * z;
@@ -96,29 +91,71 @@ __device__ __forceinline__ Nbrs neighbours(uint32_t xyz, int L)
     return n;
 }
 
+__device__ __forceinline__ Nbrs neighbours_packed(uint32_t xyz, int L)
+{
+    return neighbours(xyz & 0xFF, (xyz >> 8) & 0xFF, xyz >> 16, L);
+}
+
+// floor(j / d) for 0 <= j < 2^15 and d <= 32 given inv = 1.0f / d: the
+// float product of j + 1/2 and inv lands strictly inside (q, q + 1).
+__device__ __forceinline__ int qdiv(int j, float inv)
+{
+    return (int)(((float)j + 0.5f) * inv);
+}
+
+// Item j of checkerboard class c (even L): rows (y, z) hold L/2 class sites
+// at x = 2 xh + ((c + y + z) & 1).
+__device__ __forceinline__ Nbrs checker_site(int j, int c, int L, float invH, float invL)
+{
+    const int w = qdiv(j, invH);
+    const int xh = j - w * (L >> 1);
+    const int z = qdiv(w, invL);
+    const int y = w - z * L;
+    return neighbours(2 * xh + ((c + y + z) & 1), y, z, L);
+}
+
+__device__ __forceinline__ Nbrs natural_site(int i, int L, float invL)
+{
+    const int w = qdiv(i, invL);
+    const int z = qdiv(w, invL);
+    return neighbours(i - w * L, w - z * L, z, L);
+}
+
 // LDS regions of the sweep kernel (offsets from lds_layout()).
 struct Smem {
-    uint32_t *spin;   // [words_resident][N]
-    uint8_t *j6;      // [N]
     uint32_t *thr;    // [kMaxTemps][kThrCols] rows by slot
-    int32_t *U;       // [kMaxTemps]
+    uint32_t *fthr;   // [kMaxTemps][kThrCols] rows by temperature
+    int32_t *U;       // unsatisfied bonds per slot
     int32_t *perm;    // temp_of_slot
     int32_t *sot;     // slot_of_temp
-    uint32_t *draw;   // swap draws per pair
+    uint32_t *draw;   // (spare)
+    int32_t *soff, *slen, *ssgn;   // swap tables: offset, length, sign of dbeta
+    uint32_t *acc;    // accepted swaps per pair in this unit
     uint64_t *mask;   // speculative accept bits per pair
+    uint32_t *spin;   // [words_resident][N]
+    uint32_t *stab;   // swap tables (when cached)
+    uint32_t *sites;  // odd-L site list (when cached)
+    uint8_t *j6;      // [N]
 };
 
-__device__ __forceinline__ Smem carve(uint8_t *base, int N, int words)
+__device__ __forceinline__ Smem carve(uint8_t *base, int N, int words, int swap_entries, int site_entries)
 {
-    const LdsLayout l = lds_layout(N, words);
+    const LdsLayout l = lds_layout(N, words, swap_entries, site_entries);
     Smem s;
     s.thr = (uint32_t *)(base + l.thr);
+    s.fthr = (uint32_t *)(base + l.fthr);
     s.U = (int32_t *)(base + l.U);
     s.perm = (int32_t *)(base + l.perm);
     s.sot = (int32_t *)(base + l.sot);
     s.draw = (uint32_t *)(base + l.draw);
+    s.soff = (int32_t *)(base + l.soff);
+    s.slen = (int32_t *)(base + l.slen);
+    s.ssgn = (int32_t *)(base + l.ssgn);
+    s.acc = (uint32_t *)(base + l.acc);
     s.mask = (uint64_t *)(base + l.mask);
     s.spin = (uint32_t *)(base + l.spin);
+    s.stab = (uint32_t *)(base + l.stab);
+    s.sites = (uint32_t *)(base + l.sites);
     s.j6 = base + l.j6;
     return s;
 }
@@ -130,6 +167,7 @@ __device__ __forceinline__ Smem carve(uint8_t *base, int N, int words)
 // ---------------------------------------------------------------------------
 struct Ctr {
     uint32_t t, r, c3, k0, k1;   // sweep, realization, domain|copy|group base, key
+    uint32_t w;                  // segment width (4)
 };
 
 // CAMSC: X[k] holds 2E+S of slot 4j+k in segment j.  Returns the flip bits of
@@ -143,10 +181,10 @@ __device__ __forceinline__ uint32_t camsc_decide(const uint32_t X[4], const uint
     for (int g = NG - 1; g >= 0; --g) {
         const U4 rr = philox10(site, c.t, c.r, c.c3 | (uint32_t)g, c.k0, c.k1);
         const uint32_t *row = rows + 4 * g * kThrCols;
-        F = (F << 1) | (rr.w < row[3 * kThrCols + field4(X[3], 4 * g)] ? 1u : 0u);
-        F = (F << 1) | (rr.z < row[2 * kThrCols + field4(X[2], 4 * g)] ? 1u : 0u);
-        F = (F << 1) | (rr.y < row[1 * kThrCols + field4(X[1], 4 * g)] ? 1u : 0u);
-        F = (F << 1) | (rr.x < row[0 * kThrCols + field4(X[0], 4 * g)] ? 1u : 0u);
+        F = (F << 1) | (rr.w < row[3 * kThrCols + field4(X[3], 4 * g, c.w)] ? 1u : 0u);
+        F = (F << 1) | (rr.z < row[2 * kThrCols + field4(X[2], 4 * g, c.w)] ? 1u : 0u);
+        F = (F << 1) | (rr.y < row[1 * kThrCols + field4(X[1], 4 * g, c.w)] ? 1u : 0u);
+        F = (F << 1) | (rr.x < row[0 * kThrCols + field4(X[0], 4 * g, c.w)] ? 1u : 0u);
     }
     return F;
 }
@@ -160,10 +198,10 @@ __device__ __forceinline__ uint32_t amsc4_decide(uint32_t X, const uint32_t *row
     for (int g = NG - 1; g >= 0; --g) {
         const U4 rr = philox10(site, c.t, c.r, c.c3 | (uint32_t)g, c.k0, c.k1);
         const uint32_t *row = rows + 4 * g * kThrCols;
-        F = (F << 4) | (rr.w < row[3 * kThrCols + field4(X, 16 * g + 12)] ? 1u : 0u);
-        F = (F << 4) | (rr.z < row[2 * kThrCols + field4(X, 16 * g + 8)] ? 1u : 0u);
-        F = (F << 4) | (rr.y < row[1 * kThrCols + field4(X, 16 * g + 4)] ? 1u : 0u);
-        F = (F << 4) | (rr.x < row[0 * kThrCols + field4(X, 16 * g)] ? 1u : 0u);
+        F = (F << 4) | (rr.w < row[3 * kThrCols + field4(X, 16 * g + 12, c.w)] ? 1u : 0u);
+        F = (F << 4) | (rr.z < row[2 * kThrCols + field4(X, 16 * g + 8, c.w)] ? 1u : 0u);
+        F = (F << 4) | (rr.y < row[1 * kThrCols + field4(X, 16 * g + 4, c.w)] ? 1u : 0u);
+        F = (F << 4) | (rr.x < row[0 * kThrCols + field4(X, 16 * g, c.w)] ? 1u : 0u);
     }
     return F;
 }
@@ -173,7 +211,8 @@ __device__ __forceinline__ uint32_t amsc4_decide(uint32_t X, const uint32_t *row
 // ---------------------------------------------------------------------------
 template <int LAYOUT>
 __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int N, int gw, int g0, int n_T,
-                                            uint32_t t, uint32_t r, uint32_t c3base, uint32_t k0, uint32_t k1)
+                                            uint32_t t, uint32_t r, uint32_t c3base, uint32_t k0, uint32_t k1,
+                                            uint32_t segw)
 {
     constexpr uint32_t M = 0x11111111u;
     const uint32_t j6 = sm.j6[nb.i];
@@ -213,7 +252,7 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
             const int ngr = left >= 32 ? 8 : (left + 3) >> 2;
             const uint32_t valid = left >= 32 ? 0xFFFFFFFFu : ((1u << left) - 1u);
             const uint32_t *rows = sm.thr + slot0 * kThrCols;
-            const Ctr c{t, r, c3base | (uint32_t)(wg * 8), k0, k1};
+            const Ctr c{t, r, c3base | (uint32_t)(wg * 8), k0, k1, segw};
             uint32_t F;
             switch (ngr) {
                 case 8: F = camsc_decide<8>(X, rows, nb.i, c); break;
@@ -235,7 +274,7 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
             const int left = n_T - slot0;
             const uint32_t valid = left >= 8 ? M : (M & ((1u << (4 * left)) - 1u));
             const uint32_t *rows = sm.thr + slot0 * kThrCols;
-            const Ctr c{t, r, c3base | (uint32_t)(wg * 2), k0, k1};
+            const Ctr c{t, r, c3base | (uint32_t)(wg * 2), k0, k1, segw};
             const uint32_t F = left > 4 ? amsc4_decide<2>(X, rows, nb.i, c) : amsc4_decide<1>(X, rows, nb.i, c);
             sw[nb.i] = S ^ ((F | always) & valid);
         }
@@ -244,51 +283,93 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
 
 // ---------------------------------------------------------------------------
 // Unsatisfied-bond counts per slot for one word (forward bonds of every site),
-// added into U[slot0 + b].  Each lane keeps vertical bit-plane counters; the
-// planes are reduced across the wave with ballot + popcount.
+// added into U[slot0 + b].
+//
+// Each lane sums its sites' bond bits in NP vertical bit planes (plane p holds
+// bit p of every slot's count).  The wave then adds the lanes' plane counters
+// with DPP: row_shr 1, 2, 4, 8 leave each row's total in its lane 15, and
+// row_bcast 15 / 31 fold the rows into lane 63; every step is a vertical
+// ripple add, two bitop3 per plane.  Finally the planes are broadcast from
+// lane 63 and lane b assembles slot b's count, so the whole reduction is
+// vector work plus one LDS atomic per wave.
 // ---------------------------------------------------------------------------
-template <int LAYOUT>
-__device__ void count_unsat_word(const uint32_t *words, const uint8_t *j6, const uint32_t *sites, int N, int L,
-                                 int slot0, int n_T, int np, int *U)
+__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);   // truth table of majority(a, b, c)
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_src(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+
+// P += shifted copy of P (NQ planes in, carry grows the top plane).
+template <int NQ, int CTRL, int ROW_MASK>
+__device__ __forceinline__ void dpp_add_planes(uint32_t (&P)[14])
+{
+    uint32_t Q[NQ];
+#pragma unroll
+    for (int p = 0; p < NQ; ++p) Q[p] = dpp_src<CTRL, ROW_MASK>(P[p]);
+    uint32_t c = P[0] & Q[0];
+    P[0] ^= Q[0];
+#pragma unroll
+    for (int p = 1; p < NQ; ++p) {
+        const uint32_t sum = xor3(P[p], Q[p], c);
+        c = maj3(P[p], Q[p], c);
+        P[p] = sum;
+    }
+    P[NQ] = c;   // planes above NQ are zero before this step
+}
+
+template <int LAYOUT, int NP>
+__device__ void count_unsat_word_np(const uint32_t *words, const uint8_t *j6, int N, int L, float invL, int slot0,
+                                    int n_T, int *U)
 {
     constexpr int SPW = Layout<LAYOUT>::kSlotsPerWord;
     constexpr int STR = Layout<LAYOUT>::kStride;
     const uint32_t keep = LAYOUT == 0 ? 0xFFFFFFFFu : 0x11111111u;
-    uint32_t P[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t P[14];
+#pragma unroll
+    for (int p = 0; p < 14; ++p) P[p] = 0;
     for (int idx = threadIdx.x; idx < N; idx += blockDim.x) {
-        const Nbrs nb = neighbours(sites[idx], L);
+        const Nbrs nb = natural_site(idx, L, invL);
         const uint32_t S = words[nb.i];
         const uint32_t jb = j6[nb.i];
         const uint32_t ex = S ^ words[nb.xp] ^ ((0u - (jb & 1u)) & keep);
         const uint32_t ey = S ^ words[nb.yp] ^ ((0u - ((jb >> 2) & 1u)) & keep);
         const uint32_t ez = S ^ words[nb.zp] ^ ((0u - ((jb >> 4) & 1u)) & keep);
-        // full adder: ex + ey + ez = 2c + s
-        const uint32_t s = ex ^ ey ^ ez;
-        const uint32_t c = (ex & ey) | (ez & (ex ^ ey));
-        uint32_t carry = P[0] & s;
+        // ex + ey + ez = 2c + s, added into the planes
+        const uint32_t s = xor3(ex, ey, ez);
+        const uint32_t c = maj3(ex, ey, ez);
+        const uint32_t carry0 = P[0] & s;
         P[0] ^= s;
-        const uint32_t t1 = P[1] ^ c;
-        uint32_t c2 = (P[1] & c) | (carry & t1);
-        P[1] = t1 ^ carry;
+        uint32_t carry = maj3(P[1], c, carry0);
+        P[1] = xor3(P[1], c, carry0);
 #pragma unroll
-        for (int p = 2; p < 8; ++p) {
-            if (p < np) {
-                const uint32_t tt = P[p] & c2;
-                P[p] ^= c2;
-                c2 = tt;
-            }
+        for (int p = 2; p < NP; ++p) {
+            const uint32_t tt = P[p] & carry;
+            P[p] ^= carry;
+            carry = tt;
         }
     }
+    // wave sum into lane 63
+    dpp_add_planes<NP + 0, 0x111, 0xF>(P);   // row_shr:1
+    dpp_add_planes<NP + 1, 0x112, 0xF>(P);   // row_shr:2
+    dpp_add_planes<NP + 2, 0x114, 0xF>(P);   // row_shr:4
+    dpp_add_planes<NP + 3, 0x118, 0xF>(P);   // row_shr:8
+    dpp_add_planes<NP + 4, 0x142, 0xA>(P);   // row_bcast:15 into rows 1, 3
+    dpp_add_planes<NP + 5, 0x143, 0xC>(P);   // row_bcast:31 into rows 2, 3
     const int lane = threadIdx.x & 63;
     const int nslots = min(SPW, n_T - slot0);
-    for (int b = 0; b < nslots; ++b) {
-        int cnt = 0;
+    const int shift = (lane < nslots ? lane : 0) * STR;
+    int cnt = 0;
 #pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            if (p < np) cnt += __popcll(__ballot((P[p] >> (b * STR)) & 1u)) << p;
-        }
-        if (lane == 0 && cnt) atomicAdd(&U[slot0 + b], cnt);
+    for (int p = 0; p < NP + 6; ++p) {
+        const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)P[p], 63);
+        cnt += (int)((w >> shift) & 1u) << p;
     }
+    if (lane < nslots && cnt) atomicAdd(&U[slot0 + lane], cnt);
 }
 
 // Bit planes needed so that no lane's per-slot count overflows.
@@ -298,6 +379,21 @@ __device__ __forceinline__ int planes_for(int N, int nthr)
     int np = 2;
     while ((1 << np) <= per_lane) ++np;
     return np;
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ void count_unsat_word(const uint32_t *words, const uint8_t *j6, int N, int L, float invL,
+                                                 int slot0, int n_T, int np, int *U)
+{
+    switch (np) {
+        case 2: count_unsat_word_np<LAYOUT, 2>(words, j6, N, L, invL, slot0, n_T, U); break;
+        case 3: count_unsat_word_np<LAYOUT, 3>(words, j6, N, L, invL, slot0, n_T, U); break;
+        case 4: count_unsat_word_np<LAYOUT, 4>(words, j6, N, L, invL, slot0, n_T, U); break;
+        case 5: count_unsat_word_np<LAYOUT, 5>(words, j6, N, L, invL, slot0, n_T, U); break;
+        case 6: count_unsat_word_np<LAYOUT, 6>(words, j6, N, L, invL, slot0, n_T, U); break;
+        case 7: count_unsat_word_np<LAYOUT, 7>(words, j6, N, L, invL, slot0, n_T, U); break;
+        default: count_unsat_word_np<LAYOUT, 8>(words, j6, N, L, invL, slot0, n_T, U); break;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -311,11 +407,12 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
     constexpr int SPW = Layout<LAYOUT>::kSlotsPerWord;
     extern __shared__ __align__(16) uint8_t smem_raw[];
     __shared__ uint32_t s_next;
-    __shared__ int32_t s_fin[kMaxTemps];
-    __shared__ uint32_t s_acc[kMaxTemps];
 
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int nwaves = nthr >> 6;
 
     for (;;) {
         if (tid == 0) s_next = atomicAdd(queue, 1u);
@@ -327,36 +424,50 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
         const JobDesc &jd = jobs[unit >> 20];
         const int ladder = unit & 0xFFFFF;
         const int N = jd.N, L = jd.L, NW = jd.NW, WR = jd.words_resident, n_T = jd.n_T;
-        const int n_classes = jd.n_classes;
+        const bool even = (L & 1) == 0;
+        const float invL = jd.invL, invH = jd.invH;
         const uint32_t r = (uint32_t)(ladder >> 1);
         const uint32_t copy = (uint32_t)(ladder & 1);
         const uint32_t c3flip = (kDomainFlip << 28) | (copy << 24);
+        const uint32_t c3swap = (kDomainSwap << 28) | (copy << 24);
         const uint32_t k0 = jd.key0, k1 = jd.key1;
-        const Smem sm = carve(smem_raw, N, WR);
+        const uint32_t segw = jd.seg_bits;
+        const int n_swap_lds = jd.swap_lds, n_sites_lds = jd.sites_lds;
+        const Smem sm = carve(smem_raw, N, WR, n_swap_lds, n_sites_lds);
         uint32_t *g_spin = jd.spins + (size_t)ladder * NW * N;
+        const int n_groups = (NW + WR - 1) / WR;
 
-        // couplings, permutation and threshold rows of this ladder
+        // couplings, tables and permutation of this ladder
         const uint8_t *g_j6 = jd.j6 + (size_t)r * N;
         for (int idx = tid; idx < N; idx += nthr) sm.j6[idx] = g_j6[idx];
+        for (int idx = tid; idx < n_T * kThrCols; idx += nthr) sm.fthr[idx] = jd.flip_thr[idx];
+        for (int idx = tid; idx < n_swap_lds; idx += nthr) sm.stab[idx] = jd.swap_thr[idx];
+        for (int idx = tid; idx < n_sites_lds; idx += nthr) sm.sites[idx] = jd.sites[idx];
         if (tid < kMaxTemps) {
             sm.perm[tid] = tid < n_T ? jd.temp_of_slot[ladder * kMaxTemps + tid] : 0;
-            s_acc[tid] = 0;
+            sm.acc[tid] = 0;
+            sm.U[tid] = 0;
+            sm.soff[tid] = jd.swap_off[tid];
+            sm.slen[tid] = jd.swap_len[tid];
+            sm.ssgn[tid] = jd.swap_sgn[tid];
         }
+        if (n_groups == 1)
+            for (int idx = tid; idx < NW * N; idx += nthr) sm.spin[idx] = g_spin[idx];
         __syncthreads();
         if (tid < n_T) sm.sot[sm.perm[tid]] = tid;
         for (int idx = tid; idx < kMaxTemps * kThrCols; idx += nthr) {
             const int slot = idx / kThrCols;
-            sm.thr[idx] = slot < n_T ? jd.flip_thr[sm.perm[slot] * kThrCols + (idx % kThrCols)] : 0u;
+            sm.thr[idx] = slot < n_T ? sm.fthr[sm.perm[slot] * kThrCols + (idx % kThrCols)] : 0u;
         }
-        const int n_groups = (NW + WR - 1) / WR;
-        if (n_groups == 1)
-            for (int idx = tid; idx < NW * N; idx += nthr) sm.spin[idx] = g_spin[idx];
         __syncthreads();
+        const uint32_t *stab = n_swap_lds ? sm.stab : jd.swap_thr;
+        const uint32_t *slist = n_sites_lds ? sm.sites : jd.sites;
 
         uint32_t t = __builtin_amdgcn_readfirstlane(*jd.sweep_ctr);
         int remaining = jd.n_sweeps;
         const int se = jd.swap_every;
         const int np = planes_for(N, nthr);
+        const int half = N >> 1;
         while (remaining > 0) {
             int chunk = remaining;
             bool swap_now = false;
@@ -367,10 +478,6 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                     swap_now = true;
                 }
             }
-            if (swap_now) {
-                if (tid < kMaxTemps) sm.U[tid] = 0;
-                __syncthreads();
-            }
             for (int g0 = 0; g0 < NW; g0 += WR) {
                 const int gw = min(WR, NW - g0);
                 if (n_groups > 1) {
@@ -379,19 +486,27 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                 }
                 for (int s = 0; s < chunk; ++s) {
                     const uint32_t ts = t + (uint32_t)s;
-                    for (int c = 0; c < n_classes; ++c) {
-                        const int end = jd.class_off[c + 1];
-                        for (int it = jd.class_off[c] + tid; it < end; it += nthr) {
-                            const Nbrs nb = neighbours(jd.sites[it], L);
-                            update_site<LAYOUT>(sm, nb, N, gw, g0, n_T, ts, r, c3flip, k0, k1);
+                    if (even) {
+                        for (int c = 0; c < 2; ++c) {
+                            for (int j = tid; j < half; j += nthr)
+                                update_site<LAYOUT>(sm, checker_site(j, c, L, invH, invL), N, gw, g0, n_T, ts, r,
+                                                    c3flip, k0, k1, segw);
+                            __syncthreads();
                         }
-                        __syncthreads();
+                    } else {
+                        for (int c = 0; c < jd.n_classes; ++c) {
+                            const int end = jd.class_off[c + 1];
+                            for (int it = jd.class_off[c] + tid; it < end; it += nthr)
+                                update_site<LAYOUT>(sm, neighbours_packed(slist[it], L), N, gw, g0, n_T, ts, r,
+                                                    c3flip, k0, k1, segw);
+                            __syncthreads();
+                        }
                     }
                 }
                 if (swap_now) {
                     for (int w = 0; w < gw; ++w)
-                        count_unsat_word<LAYOUT>(sm.spin + (size_t)w * N, sm.j6, jd.sites, N, L, (g0 + w) * SPW,
-                                                 n_T, np, sm.U);
+                        count_unsat_word<LAYOUT>(sm.spin + (size_t)w * N, sm.j6, N, L, invL, (g0 + w) * SPW, n_T, np,
+                                                 sm.U);
                 }
                 if (n_groups > 1) {
                     __syncthreads();
@@ -402,48 +517,63 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                 // ---- replica-exchange pass after sweep t + chunk - 1 ----
                 const uint32_t tswap = t + (uint32_t)chunk - 1u;
                 const int pairs = n_T - 1;
-                if (tid < pairs)
-                    sm.draw[tid] = philox10((uint32_t)tid, tswap, r, (kDomainSwap << 28) | (copy << 24), k0, k1).x;
-                if (tid < kMaxTemps) sm.mask[tid] = 0;
-                __syncthreads();
-                // acceptance of "configuration now at position j reaches pair k"
-                for (int p = tid; p < pairs * 64; p += nthr) {
-                    const int k = p >> 6, j = p & 63;
-                    if (j > k) continue;
-                    const int d = sm.U[sm.sot[j]] - sm.U[sm.sot[k + 1]];
-                    const int sg = jd.swap_sgn[k];
-                    bool acc = (sg == 0) || (d == 0) || ((sg > 0) == (d > 0));
-                    if (!acc) {
-                        const int n = d < 0 ? -d : d;
-                        const uint32_t thr = n < jd.swap_len[k] ? jd.swap_thr[jd.swap_off[k] + n] : 0u;
-                        acc = sm.draw[k] < thr;
+                if (wave == 0 && lane < pairs)
+                    sm.draw[lane] = philox10((uint32_t)lane, tswap, r, c3swap, k0, k1).x;
+                __syncthreads();   // slot energies U and swap draws are in
+                // Bit j of mask[k]: would pair k swap if the configuration that
+                // sat at position j before the pass had been carried up to k?
+                for (int k = wave; k < pairs; k += nwaves) {
+                    bool acc = false;
+                    if (lane <= k) {
+                        const int d = sm.U[sm.sot[lane]] - sm.U[sm.sot[k + 1]];
+                        const int sg = sm.ssgn[k];
+                        acc = (sg == 0) || (d == 0) || ((sg > 0) == (d > 0));
+                        if (!acc) {
+                            const int n = d < 0 ? -d : d;
+                            const uint32_t thr = n < sm.slen[k] ? stab[sm.soff[k] + n] : 0u;
+                            acc = sm.draw[k] < thr;
+                        }
                     }
-                    if (acc) atomicOr((unsigned long long *)&sm.mask[k], 1ull << j);
+                    const uint64_t m = __ballot(acc);
+                    if (lane == 0) sm.mask[k] = m;
                 }
                 __syncthreads();
-                if (tid == 0) {
-                    int cj = 0;   // position (in the old order) of the configuration carried upwards
+                if (wave == 0) {
+                    // walk the pairs in ascending order; lane k learns which old
+                    // position ends at temperature index k
+                    const uint64_t mine = lane < pairs ? sm.mask[lane] : 0ull;
+                    const uint32_t mlo = (uint32_t)mine, mhi = (uint32_t)(mine >> 32);
+                    int cj = 0;
+                    int src = 0;
                     for (int k = 0; k < pairs; ++k) {
-                        if ((sm.mask[k] >> cj) & 1ull) {
-                            s_fin[k] = sm.sot[k + 1];
-                            s_acc[k] += 1;
+                        // readlane returns int: zero-extend both halves
+                        const uint64_t mk = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mhi, k) << 32) |
+                                            (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mlo, k);
+                        if ((mk >> cj) & 1ull) {
+                            if (lane == k) src = k + 1;
                         } else {
-                            s_fin[k] = sm.sot[cj];
+                            if (lane == k) src = cj;
                             cj = k + 1;
                         }
                     }
-                    s_fin[pairs] = sm.sot[cj];
-                }
-                __syncthreads();
-                if (tid < n_T) {
-                    sm.sot[tid] = s_fin[tid];
-                    sm.perm[s_fin[tid]] = tid;
+                    if (lane == pairs) src = cj;
+                    const int newslot = lane < n_T ? sm.sot[src] : 0;
+                    if (lane < pairs && src == lane + 1) sm.acc[lane] += 1u;
+                    if (lane < n_T) {
+                        sm.sot[lane] = newslot;
+                        sm.perm[newslot] = lane;
+                    }
+                    sm.U[lane] = 0;   // consumed; ready for the next swap point
                 }
                 __syncthreads();
                 for (int idx = tid; idx < kMaxTemps * kThrCols; idx += nthr) {
                     const int slot = idx / kThrCols;
-                    sm.thr[idx] = slot < n_T ? jd.flip_thr[sm.perm[slot] * kThrCols + (idx % kThrCols)] : 0u;
+                    sm.thr[idx] = slot < n_T ? sm.fthr[sm.perm[slot] * kThrCols + (idx % kThrCols)] : 0u;
                 }
+                __syncthreads();
+            } else if (swap_now) {
+                __syncthreads();
+                if (tid < kMaxTemps) sm.U[tid] = 0;
                 __syncthreads();
             }
             t += (uint32_t)chunk;
@@ -453,7 +583,7 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
             for (int idx = tid; idx < NW * N; idx += nthr) g_spin[idx] = sm.spin[idx];
         if (tid < n_T) {
             jd.temp_of_slot[ladder * kMaxTemps + tid] = sm.perm[tid];
-            if (tid < n_T - 1) jd.swap_acc[ladder * kMaxTemps + tid] += s_acc[tid];
+            if (tid < n_T - 1) jd.swap_acc[ladder * kMaxTemps + tid] += sm.acc[tid];
         }
         __syncthreads();
     }
@@ -525,7 +655,7 @@ __global__ void __launch_bounds__(512) observables_kernel(const JobDesc *__restr
     const uint8_t *j6 = jd.j6 + (size_t)r * N;
     for (int c = 0; c < 2; ++c)
         for (int w = 0; w < NW; ++w)
-            count_unsat_word<LAYOUT>(jd.spins + ((size_t)(2 * r + c) * NW + w) * N, j6, jd.sites, N, jd.L, w * SPW,
+            count_unsat_word<LAYOUT>(jd.spins + ((size_t)(2 * r + c) * NW + w) * N, j6, N, jd.L, jd.invL, w * SPW,
                                      n_T, np, s_U[c]);
     // overlap between the copies at equal temperature index
     const uint32_t *s0 = jd.spins + (size_t)(2 * r) * NW * N;
