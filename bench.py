@@ -26,14 +26,35 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ps per spin-flip attempt (1 GPU, batched vs plain) + p50/p99 job latency"
 
-# Integer issue slots per spin-flip attempt the method itself needs (derived
-# in the design notes): a quarter of a Philox4x32-10 block (10 rounds x (2
-# quarter-rate 32x32->64 multiplies + 2 three-input xors) / 4 = 25 slots),
-# the table column, address, compare and insert (4 slots), and the share of
-# the bit-parallel bond energy (about 1 slot).
-ALG_SLOTS_PER_FLIP = 30
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = int32 issue slots per second
-PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+# int32 operations per spin-flip attempt that the method itself needs (the
+# count is derived in the design notes): a quarter of a Philox4x32-10 block
+# (10 rounds x (2 v_mad_u64_u32 + 2 three-input xors) / 4 = 10), the table
+# column, address, compare and insert (4), and the share of the bit-parallel
+# bond energies (2).  On gfx950 every one of these issues at full rate
+# (measured: v_mad_u64_u32 33.4 T/s, v_bitop3 36.1 T/s on 256 CUs).
+ALG_OPS_PER_FLIP = 16
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz int32 lane-operations per second
+PEAK_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+KERNEL_SRC = os.path.join(ROOT, "paper_1311_5582_amd", "csrc", "ea_kernels.hip")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash():
+    import hashlib
+    return hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()[:12]
+
+
+def measured_traffic(workload, layout):
+    """HBM bytes per sweep launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, only if it was taken on the current kernel source."""
+    import re
+    path = os.path.join(PROFILES, f"sweep_kernel_{workload}_{layout}.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"traffic_bytes_per_launch:\s*(\d+)\s+kernel_sha1:\s*([0-9a-f]+)", open(path).read())
+    if not m or m.group(2) != kernel_source_hash():
+        return None
+    return int(m.group(1))
 
 
 def cpu_baseline(L, n_T, t_min, t_max, seed, sweeps, threads):
@@ -123,8 +144,8 @@ def main():
     total_flips = flips_per_step * args.steps
     ps_per_flip = wall / total_flips * 1e12
     avg_launch_s = float(np.mean(kernel_ms)) / 1e3
-    achieved = ALG_SLOTS_PER_FLIP * flips_per_step / avg_launch_s / 1e12
-    peak = PEAK_SLOTS_PER_S / 1e12
+    achieved = ALG_OPS_PER_FLIP * flips_per_step / avg_launch_s / 1e12
+    peak = PEAK_OPS_PER_S / 1e12
     out = {
         "metric": METRIC,
         "value": round(ps_per_flip, 4),
@@ -144,8 +165,8 @@ def main():
                    "kernel_ps_per_flip": round(avg_launch_s / flips_per_step * 1e12, 4),
                    "paper_ps_per_flip_gtx580": 33.5},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
-                     "ops_per_flip": ALG_SLOTS_PER_FLIP,
+                     "frac": round(achieved / peak, 4), "traffic": measured_traffic(args.workload, args.layout),
+                     "ops_per_flip": ALG_OPS_PER_FLIP, "kernel_sha1": kernel_source_hash(),
                      "kernel": "sweep_kernel<%s>" % ("CAMSC" if args.layout == "camsc" else "AMSC4")},
     }
     sim.close()
