@@ -77,6 +77,72 @@ def cpu_baseline(L, n_T, t_min, t_max, seed, sweeps, threads):
                       f"PT every sweep ({flips:.3g} flip attempts, {dt:.1f} s wall)"}
 
 
+def flips_of(job, sweeps):
+    return sweeps * job["L"] ** 3 * job["n_T"] * job["R"] * 2
+
+
+def bench_batched(B, inputs, torch, sweeps, steps):
+    """The uneven job set in one graph-captured launch per step vs the same
+    jobs launched one after another (plain path), same sweeps."""
+    jobs = inputs.BATCHED_JOBS
+
+    def make():
+        return [B.Sim(j["L"], inputs.couplings(j["L"], j["R"], j["seed"]),
+                      inputs.geometric_betas(j["n_T"], j["t_min"], j["t_max"]), j["seed"]) for j in jobs]
+
+    flips = sum(flips_of(j, sweeps) for j in jobs) * steps
+    # plain: each job alone, back to back
+    sims = make()
+    for s, j in zip(sims, jobs):
+        s.sweep(1, j["swap_every"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for s, j in zip(sims, jobs):
+            s.sweep(sweeps, j["swap_every"])
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    for s in sims:
+        s.close()
+    # batched: one plan, graph replay
+    sims = make()
+    plan = B.Plan(sims, sweeps, [j["swap_every"] for j in jobs], autotune=True)
+    plan.run(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run(steps)
+    torch.cuda.synchronize()
+    batched_s = time.perf_counter() - t0
+    info = plan.info()
+    plan.close()
+    for s in sims:
+        s.close()
+    return {"workload": "5 jobs L=8,10,12,16,20 x 128 realizations x 2 copies, 16-40 temperatures, PT every sweep",
+            "sweeps_per_step": sweeps, "steps": steps, "flips": flips,
+            "batched_ps_per_flip": round(batched_s / flips * 1e12, 4),
+            "plain_ps_per_flip": round(plain_s / flips * 1e12, 4),
+            "speedup": round(plain_s / batched_s, 3), "block_threads": info["block_threads"],
+            "units": info["units"], "uses_graph": info["uses_graph"]}
+
+
+def bench_serving(B, inputs, n_jobs, rate, quantum, sweep_scale=1.0):
+    """Poisson job trace through the continuous-batching server."""
+    from paper_1311_5582_amd import serve
+    trace = inputs.serving_trace(n_jobs=n_jobs, rate_per_s=rate)
+    for j in trace:
+        j["sweeps"] = max(1, int(j["sweeps"] * sweep_scale))
+    srv = B.Server(quantum_sweeps=quantum)
+    recs, wall = serve.run_trace(trace, srv)
+    st = srv.stats()
+    srv.close()
+    summ = serve.latency_summary(recs)
+    return {"jobs": n_jobs, "rate_per_s": round(rate, 3), "quantum_sweeps": quantum, "sweep_scale": sweep_scale,
+            "p50_latency_s": round(summ["p50_s"], 4), "p99_latency_s": round(summ["p99_s"], 4),
+            "mean_latency_s": round(summ["mean_s"], 4), "wall_s": round(wall, 3),
+            "aggregate_ps_per_flip": round(wall / summ["flips"] * 1e12, 4), "steps": st["steps"],
+            "plans_built": st["plans_built"], "launches_replayed": st["launches_replayed"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +155,14 @@ def main():
     ap.add_argument("--swap-every", type=int, default=-1, help="override the workload's PT interval")
     ap.add_argument("--cpu-sweeps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-sweeps", type=int, default=250)
+    ap.add_argument("--batched-steps", type=int, default=4)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-jobs", type=int, default=64)
+    ap.add_argument("--serving-quantum", type=int, default=200)
+    ap.add_argument("--serving-scale", type=float, default=1.0,
+                    help="multiply every job's sweep count (1.0 = the lognormal trace as drawn)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before timing, run one plain device-to-device copy of this many MiB "
                          "(reference kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -170,6 +244,14 @@ def main():
                      "kernel": "sweep_kernel<%s>" % ("CAMSC" if args.layout == "camsc" else "AMSC4")},
     }
     sim.close()
+    if not args.no_batched:
+        out["batched"] = bench_batched(B, inputs, torch, args.batched_sweeps, args.batched_steps)
+    if not args.no_serving:
+        out["serving"] = bench_serving(B, inputs, args.serving_jobs, 20.0, args.serving_quantum, args.serving_scale)
+        # the same trace shape at 0.8 x the measured service capacity (jobs/s)
+        cap = out["serving"]["jobs"] / max(out["serving"]["wall_s"], 1e-9)
+        out["serving_at_0.8_capacity"] = bench_serving(B, inputs, args.serving_jobs, 0.8 * cap,
+                                                      args.serving_quantum, args.serving_scale)
     if not args.no_cpu_baseline:
         threads = max(1, min(os.cpu_count() or 1, 16))
         out["cpu_baseline"] = cpu_baseline(L, n_T, cfg["t_min"], cfg["t_max"], cfg["seed"], args.cpu_sweeps, threads)

@@ -119,6 +119,83 @@ int ea_sweep(ea_sim *sim, int64_t n_sweeps, int swap_every);
 int ea_sweep_batch(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps,
                    const int *swap_every);
 
+/* ---- Launch plans: one step over several jobs, captured once and replayed ----
+ * A plan freezes a job list and a step (sweeps_per_step sweeps of every job,
+ * with swap_every[j] for job j, as ea_sweep would run them) into one
+ * persistent launch whose ladders are ordered largest first, and captures the
+ * step in a hipGraph; ea_plan_run replays it.  The jobs' sweep counters live
+ * in device memory, so every replay continues each job's random stream: the
+ * results equal those of ea_sweep on each job alone.  The workgroup size is
+ * opt->block_threads, or picked by timing candidates on scratch copies of the
+ * jobs (results never depend on it).  The jobs must outlive the plan and must
+ * not be swept through other calls while a plan run is in flight. */
+typedef struct ea_plan ea_plan;
+typedef struct ea_plan_options {
+    int block_threads;   /* 0 = autotune (or, with autotune = 0, the largest planned size) */
+    int autotune;        /* 1 = time 256/512/768/1024 threads on scratch copies, cache the best */
+    int use_graph;       /* 1 = replay a captured hipGraph (default); 0 = plain launches */
+    int reserved_;
+    void *stream;        /* hipStream_t; NULL = a stream owned by the plan, runs synchronous */
+} ea_plan_options;
+
+void ea_default_plan_options(ea_plan_options *opt);
+int ea_plan_create(ea_sim *const *sims, int n_sims, int sweeps_per_step, const int *swap_every,
+                   const ea_plan_options *opt, ea_plan **out);
+/* Run n_steps >= 0 steps.  EA_ESTATE if a sweep counter would reach 2^32. */
+int ea_plan_run(ea_plan *plan, int64_t n_steps);
+int ea_plan_info(const ea_plan *plan, int *block_threads, int *grid, int *n_units, size_t *lds_bytes,
+                 int *uses_graph);
+void ea_plan_destroy(ea_plan *plan);
+
+/* ---- Serving: continuous batching of jobs on one GPU ----
+ * Jobs are submitted with host inputs and wait in arrival order.  Each
+ * ea_server_step admits waiting jobs (first fit in arrival order) while their
+ * device footprint (ea_job_footprint) fits the budget, runs one launch over
+ * every admitted job for min(quantum, sweeps any job has left) sweeps -
+ * replaying a graph-captured plan while the job set is unchanged - and retires
+ * finished jobs: energies and overlaps are measured, device state is freed.
+ * A job's results are the same alone and in any mix. */
+#define EA_JOB_QUEUED    0
+#define EA_JOB_RUNNING   1
+#define EA_JOB_DONE      2
+#define EA_JOB_CANCELLED 3
+#define EA_JOB_FAILED    4
+
+typedef struct ea_server ea_server;
+typedef struct ea_server_options {
+    size_t hbm_budget_bytes;  /* device bytes for job state; 0 = 80% of free memory at creation */
+    int quantum_sweeps;       /* sweeps per step (default 200)                                   */
+    int layout;               /* EA_LAYOUT_* of every job                                         */
+    int max_active;           /* admitted jobs at once, <= 4095 (0 = 4095)                        */
+    int autotune;             /* 1 = tune each job mix's workgroup size (cached by shape); default 0 */
+    int keep_state;           /* keep each finished job's spins and permutation on the host       */
+    int reserved_;
+    void *stream;             /* hipStream_t; NULL = a stream owned by the server                 */
+} ea_server_options;
+
+void ea_default_server_options(ea_server_options *opt);
+int ea_server_create(const ea_server_options *opt, ea_server **out);
+/* Queue a job (inputs as ea_create; copied).  EA_ENOMEM if it alone exceeds the budget. */
+int ea_server_submit(ea_server *sv, int L, const int8_t *couplings, const double *betas, int n_T,
+                     int n_realizations, uint64_t seed, int64_t n_sweeps, int swap_every, int64_t *job_id);
+/* Admit, run one quantum, retire.  Synchronous.  Counts after the step. */
+int ea_server_step(ea_server *sv, int *n_running, int *n_queued, int *n_finished);
+int ea_server_status(ea_server *sv, int64_t job_id, int *status, int64_t *sweeps_done);
+/* Results of a DONE job: energy int32 [R][2][n_T], overlap int32 [R][n_T] (as ea_observables). */
+int ea_server_result(ea_server *sv, int64_t job_id, int32_t *energy, int32_t *overlap);
+/* Final spins [R][2][n_T][L^3] and temp_of_slot [R][2][n_T] of a DONE job (needs keep_state). */
+int ea_server_final_state(ea_server *sv, int64_t job_id, int8_t *spins, int32_t *temp_of_slot);
+int ea_server_cancel(ea_server *sv, int64_t job_id);    /* queued or running; frees its memory */
+int ea_server_release(ea_server *sv, int64_t job_id);   /* forget a finished job's results     */
+int ea_server_stats(const ea_server *sv, size_t *hbm_used, size_t *hbm_budget, int64_t *steps,
+                    int64_t *plans_built, int64_t *launches_replayed);
+void ea_server_destroy(ea_server *sv);
+
+/* Device bytes ea_create allocates for such a job (host-only computation). */
+int ea_job_footprint(int L, const double *betas, int n_T, int n_realizations, int layout, size_t *bytes);
+/* Device bytes a live job holds. */
+int ea_sim_footprint(const ea_sim *sim, size_t *bytes);
+
 /* Measurement (Sec. 4.1, separate kernel): energy int32 [R][2][n_T] indexed by
  * temperature index, E = 2U - 3N; overlap int32 [R][n_T]:
  * q_k = sum_i s_i(copy 0 at temperature k) s_i(copy 1 at temperature k).

@@ -35,6 +35,20 @@ class Options(ctypes.Structure):
     ]
 
 
+class PlanOptions(ctypes.Structure):
+    _fields_ = [("block_threads", ctypes.c_int), ("autotune", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("reserved_", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("quantum_sweeps", ctypes.c_int), ("layout", ctypes.c_int),
+                ("max_active", ctypes.c_int), ("autotune", ctypes.c_int), ("keep_state", ctypes.c_int),
+                ("reserved_", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_CANCELLED, JOB_FAILED = 0, 1, 2, 3, 4
+
+
 class EAError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"[{code}] {msg}")
@@ -70,6 +84,28 @@ def lib():
             "ea_flip_thresholds": (ctypes.c_int, [f64p, ctypes.c_int, u32p]),
             "ea_swap_threshold": (ctypes.c_uint32, [ctypes.c_double, ctypes.c_int64]),
             "ea_version": (ctypes.c_char_p, []),
+            "ea_default_plan_options": (None, [ctypes.POINTER(PlanOptions)]),
+            "ea_plan_create": (ctypes.c_int, [ctypes.POINTER(P), ctypes.c_int, ctypes.c_int, i32p,
+                                              ctypes.POINTER(PlanOptions), ctypes.POINTER(P)]),
+            "ea_plan_run": (ctypes.c_int, [P, ctypes.c_int64]),
+            "ea_plan_info": (ctypes.c_int, [P, i32p, i32p, i32p, ctypes.POINTER(ctypes.c_size_t), i32p]),
+            "ea_plan_destroy": (None, [P]),
+            "ea_default_server_options": (None, [ctypes.POINTER(ServerOptions)]),
+            "ea_server_create": (ctypes.c_int, [ctypes.POINTER(ServerOptions), ctypes.POINTER(P)]),
+            "ea_server_submit": (ctypes.c_int, [P, ctypes.c_int, i8p, f64p, ctypes.c_int, ctypes.c_int,
+                                                ctypes.c_uint64, ctypes.c_int64, ctypes.c_int, i64p]),
+            "ea_server_step": (ctypes.c_int, [P, i32p, i32p, i32p]),
+            "ea_server_status": (ctypes.c_int, [P, ctypes.c_int64, i32p, i64p]),
+            "ea_server_result": (ctypes.c_int, [P, ctypes.c_int64, i32p, i32p]),
+            "ea_server_final_state": (ctypes.c_int, [P, ctypes.c_int64, i8p, i32p]),
+            "ea_server_cancel": (ctypes.c_int, [P, ctypes.c_int64]),
+            "ea_server_release": (ctypes.c_int, [P, ctypes.c_int64]),
+            "ea_server_stats": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                                               i64p, i64p, i64p]),
+            "ea_server_destroy": (None, [P]),
+            "ea_job_footprint": (ctypes.c_int, [ctypes.c_int, f64p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                ctypes.POINTER(ctypes.c_size_t)]),
+            "ea_sim_footprint": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_size_t)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -208,6 +244,11 @@ class Sim:
         p = np.ascontiguousarray(temp_of_slot, dtype=np.int32)
         check(lib().ea_set_state(self._h, _p(s, ctypes.c_int8), _p(p, ctypes.c_int32), int(sweeps_done)))
 
+    def footprint(self):
+        b = ctypes.c_size_t()
+        check(lib().ea_sim_footprint(self._h, ctypes.byref(b)))
+        return int(b.value)
+
     def swap_acceptance(self):
         a = np.zeros((self.R, 2, max(self.n_T - 1, 0)), dtype=np.uint64)
         check(lib().ea_swap_acceptance(self._h, _p(a, ctypes.c_uint64)))
@@ -221,3 +262,123 @@ def sweep_batch(sims, n_sweeps, swap_every):
     ns = np.ascontiguousarray(n_sweeps, dtype=np.int64)
     se = np.ascontiguousarray(swap_every, dtype=np.int32)
     check(lib().ea_sweep_batch(hs, n, _p(ns, ctypes.c_int64), _p(se, ctypes.c_int32)))
+
+
+def job_footprint(L, betas, n_realizations, layout="camsc"):
+    """Device bytes a job of this shape needs (host-only)."""
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    out = ctypes.c_size_t()
+    lay = LAYOUTS[layout] if isinstance(layout, str) else int(layout)
+    check(lib().ea_job_footprint(int(L), _p(b, ctypes.c_double), len(b), int(n_realizations), lay, ctypes.byref(out)))
+    return int(out.value)
+
+
+class Plan:
+    """One step (sweeps_per_step sweeps of every job) captured in a hipGraph and replayed."""
+
+    def __init__(self, sims, sweeps_per_step, swap_every, block_threads=0, autotune=True, use_graph=True,
+                 stream=None):
+        self.sims = list(sims)
+        n = len(self.sims)
+        hs = (ctypes.c_void_p * n)(*[x.handle.value for x in self.sims])
+        se = np.ascontiguousarray(swap_every if np.ndim(swap_every) else [swap_every] * n, dtype=np.int32)
+        opt = PlanOptions()
+        lib().ea_default_plan_options(ctypes.byref(opt))
+        opt.block_threads, opt.autotune, opt.use_graph = int(block_threads), int(bool(autotune)), int(bool(use_graph))
+        if stream is not None:
+            opt.stream = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+        self._h = ctypes.c_void_p()
+        check(lib().ea_plan_create(hs, n, int(sweeps_per_step), _p(se, ctypes.c_int32), ctypes.byref(opt),
+                                   ctypes.byref(self._h)))
+
+    def run(self, n_steps=1):
+        check(lib().ea_plan_run(self._h, int(n_steps)))
+
+    def info(self):
+        bt, grid, units, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        lds = ctypes.c_size_t()
+        check(lib().ea_plan_info(self._h, ctypes.byref(bt), ctypes.byref(grid), ctypes.byref(units),
+                                 ctypes.byref(lds), ctypes.byref(g)))
+        return dict(block_threads=bt.value, grid=grid.value, units=units.value, lds_bytes=int(lds.value),
+                    uses_graph=bool(g.value))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().ea_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    __del__ = close
+
+
+class Server:
+    """Continuous-batching job server (see ea_server_* in include/ea.h)."""
+
+    def __init__(self, hbm_budget_bytes=0, quantum_sweeps=200, layout="camsc", max_active=0, autotune=False,
+                 keep_state=False):
+        opt = ServerOptions()
+        lib().ea_default_server_options(ctypes.byref(opt))
+        opt.hbm_budget_bytes = int(hbm_budget_bytes)
+        opt.quantum_sweeps = int(quantum_sweeps)
+        opt.layout = LAYOUTS[layout] if isinstance(layout, str) else int(layout)
+        opt.max_active = int(max_active)
+        opt.autotune = int(bool(autotune))
+        opt.keep_state = int(bool(keep_state))
+        self._h = ctypes.c_void_p()
+        self.shapes = {}
+        check(lib().ea_server_create(ctypes.byref(opt), ctypes.byref(self._h)))
+
+    def submit(self, L, couplings, betas, seed, n_sweeps, swap_every=1):
+        J = np.ascontiguousarray(couplings, dtype=np.int8)
+        b = np.ascontiguousarray(betas, dtype=np.float64)
+        jid = ctypes.c_int64()
+        check(lib().ea_server_submit(self._h, int(L), _p(J, ctypes.c_int8), _p(b, ctypes.c_double), len(b),
+                                     J.shape[0], ctypes.c_uint64(int(seed) & (2 ** 64 - 1)), int(n_sweeps),
+                                     int(swap_every), ctypes.byref(jid)))
+        self.shapes[jid.value] = (int(L), J.shape[0], len(b))
+        return jid.value
+
+    def step(self):
+        r, q, f = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check(lib().ea_server_step(self._h, ctypes.byref(r), ctypes.byref(q), ctypes.byref(f)))
+        return r.value, q.value, f.value
+
+    def status(self, jid):
+        st, done = ctypes.c_int(), ctypes.c_int64()
+        check(lib().ea_server_status(self._h, int(jid), ctypes.byref(st), ctypes.byref(done)))
+        return st.value, done.value
+
+    def result(self, jid):
+        L, R, n_T = self.shapes[jid]
+        E = np.zeros((R, 2, n_T), dtype=np.int32)
+        q = np.zeros((R, n_T), dtype=np.int32)
+        check(lib().ea_server_result(self._h, int(jid), _p(E, ctypes.c_int32), _p(q, ctypes.c_int32)))
+        return E, q
+
+    def final_state(self, jid):
+        L, R, n_T = self.shapes[jid]
+        s = np.zeros((R, 2, n_T, L ** 3), dtype=np.int8)
+        p = np.zeros((R, 2, n_T), dtype=np.int32)
+        check(lib().ea_server_final_state(self._h, int(jid), _p(s, ctypes.c_int8), _p(p, ctypes.c_int32)))
+        return s, p
+
+    def cancel(self, jid):
+        check(lib().ea_server_cancel(self._h, int(jid)))
+
+    def release(self, jid):
+        check(lib().ea_server_release(self._h, int(jid)))
+        self.shapes.pop(jid, None)
+
+    def stats(self):
+        used, budget = ctypes.c_size_t(), ctypes.c_size_t()
+        steps, plans, replays = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        check(lib().ea_server_stats(self._h, ctypes.byref(used), ctypes.byref(budget), ctypes.byref(steps),
+                                    ctypes.byref(plans), ctypes.byref(replays)))
+        return dict(hbm_used=int(used.value), hbm_budget=int(budget.value), steps=steps.value,
+                    plans_built=plans.value, launches_replayed=replays.value)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().ea_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    __del__ = close

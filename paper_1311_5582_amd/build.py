@@ -10,7 +10,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libea_mi355x.so")
-SOURCES = [os.path.join(PKG, "csrc", f) for f in ("ea_kernels.hip", "ea_api.cpp")]
+SOURCES = [os.path.join(PKG, "csrc", f) for f in ("ea_kernels.hip", "ea_api.cpp", "ea_runtime.cpp", "ea_server.cpp")]
 ARCH = os.environ.get("EA_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -11,14 +11,12 @@
 #include <vector>
 
 #include "ea.h"
+#include "ea_host.h"
 #include "ea_internal.h"
 
 using namespace ea;
 
-// ---------------------------------------------------------------------------
-// Errors
-// ---------------------------------------------------------------------------
-namespace {
+namespace ea {
 
 thread_local std::string g_error;
 
@@ -32,12 +30,6 @@ int fail(int code, const char *fmt, ...)
     g_error = buf;
     return code;
 }
-
-#define EA_HIP(call)                                                                                   \
-    do {                                                                                               \
-        hipError_t e_ = (call);                                                                        \
-        if (e_ != hipSuccess) return fail(EA_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
-    } while (0)
 
 // ---------------------------------------------------------------------------
 // Integer probability tables
@@ -62,36 +54,9 @@ uint32_t swap_thr(double dbeta_abs, int64_t n)
     return prob_to_u32(std::exp(-(2.0 * dbeta_abs * (double)n)));
 }
 
-struct DeviceAlloc {
-    void *(*alloc)(size_t, void *) = nullptr;
-    void (*release)(void *, void *) = nullptr;
-    void *ctx = nullptr;
-};
+}  // namespace ea
 
-}  // namespace
-
-// ---------------------------------------------------------------------------
-// Handle
-// ---------------------------------------------------------------------------
-struct ea_sim {
-    int L = 0, N = 0, n_T = 0, R = 0, layout = 0, NW = 0;
-    int block_threads = 0, words_resident = 0;
-    int device = 0;
-    uint64_t seed = 0;
-    int64_t t = 0;                    // host shadow of the sweep counter
-    hipStream_t stream = nullptr;
-    bool user_stream = false;
-    DeviceAlloc da;
-    std::vector<void *> owned;        // device buffers to release
-    JobDesc h{};                      // host copy of the descriptor
-    JobDesc *d_job = nullptr;
-    uint32_t *d_units = nullptr;      // ladders of this job for a lone launch
-    uint32_t *d_counters = nullptr;   // [0] sweep counter, [1] work queue
-    int64_t swap_total = 0;           // entries in the swap tables
-    size_t lds = 0;                   // dynamic LDS bytes of this job's sweep workgroups
-};
-
-namespace {
+namespace ea {
 
 int dev_alloc(ea_sim *s, size_t bytes, void **out)
 {
@@ -105,6 +70,7 @@ int dev_alloc(ea_sim *s, size_t bytes, void **out)
         if (e != hipSuccess) return fail(EA_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     }
     s->owned.push_back(p);
+    s->footprint += bytes;
     *out = p;
     return EA_OK;
 }
@@ -156,9 +122,6 @@ void colour_classes(int L, std::vector<uint32_t> &sites, int32_t off[4], int *n_
     *n_classes = nc;
 }
 
-constexpr size_t kLdsBudget = 160 * 1024 - 1024;   // dynamic LDS; the rest is static
-constexpr size_t kLdsPerCu = 160 * 1024;
-constexpr int kThreadsPerCu = 2048;
 
 // Workgroups of `bt` threads and `lds` bytes that fit on one CU.
 int wgs_per_cu(size_t lds, int bt)
@@ -225,7 +188,52 @@ int device_grid(int layout, int bt, size_t lds, int n_units, int *grid)
     return EA_OK;
 }
 
-}  // namespace
+// Swap tables per pair k: entries n = 0.. while the threshold is non-zero
+// (|U_a - U_b| <= 3N caps the length).  sthr may be NULL to size only.
+int build_swap_tables(const double *betas, int n_T, int N, std::vector<uint32_t> *sthr, std::vector<int32_t> *soff,
+                      std::vector<int32_t> *slen, std::vector<int32_t> *ssgn, int64_t *total)
+{
+    if (soff) soff->assign(kMaxTemps, 0);
+    if (slen) slen->assign(kMaxTemps, 0);
+    if (ssgn) ssgn->assign(kMaxTemps, 0);
+    if (sthr) sthr->clear();
+    int64_t count = 0;
+    for (int k = 0; k + 1 < n_T; ++k) {
+        const double db = betas[k] - betas[k + 1];
+        const int sg = (db > 0.0) - (db < 0.0);
+        if (ssgn) (*ssgn)[k] = sg;
+        if (soff) (*soff)[k] = (int32_t)count;
+        if (sg == 0) continue;
+        const double dabs = std::fabs(db);
+        const int64_t cap = 3 * (int64_t)N;
+        int64_t n = 0;
+        for (; n <= cap; ++n) {
+            const uint32_t v = swap_thr(dabs, n);
+            if (v == 0) break;
+            if (sthr) sthr->push_back(v);
+        }
+        // the thresholds decrease with n; check that the zero tail stays zero
+        for (int64_t m = n; m <= std::min(cap, n + 64); ++m)
+            if (swap_thr(dabs, m) != 0) return fail(EA_EINVAL, "non-monotone swap table for pair %d", k);
+        if (slen) (*slen)[k] = (int32_t)n;
+        count += n;
+    }
+    if (total) *total = count;
+    return EA_OK;
+}
+
+// Device bytes ea_create allocates for a job (one term per allocation).
+size_t job_footprint_bytes(int L, int n_T, int R, int layout, int64_t swap_entries)
+{
+    auto a = [](size_t b) { return std::max<size_t>(b, 16); };
+    const size_t N = (size_t)L * L * L, ladders = 2 * (size_t)R;
+    const size_t NW = (size_t)(n_T + slots_per_word(layout) - 1) / slots_per_word(layout);
+    return a(ladders * NW * N * 4) + a((size_t)R * N) + a(ladders * kMaxTemps * 4) + a((size_t)n_T * kThrCols * 4) +
+           a((size_t)swap_entries * 4) + 3 * a(kMaxTemps * 4) + a(N * 4) + a(2 * 4) + a(ladders * kMaxTemps * 4) +
+           a(ladders * 4) + a(sizeof(JobDesc));
+}
+
+}  // namespace ea
 
 // ---------------------------------------------------------------------------
 // ABI
@@ -304,26 +312,9 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
             const int E = col >> 1;
             fthr[(size_t)k * kThrCols + col] = E < 3 ? flip_thr(betas[k], E) : 0u;
         }
-    std::vector<int32_t> soff(kMaxTemps, 0), slen(kMaxTemps, 0), ssgn(kMaxTemps, 0);
+    std::vector<int32_t> soff, slen, ssgn;
     std::vector<uint32_t> sthr;
-    for (int k = 0; k + 1 < n_T; ++k) {
-        const double db = betas[k] - betas[k + 1];
-        ssgn[k] = (db > 0.0) - (db < 0.0);
-        soff[k] = (int32_t)sthr.size();
-        if (ssgn[k] == 0) continue;
-        const double dabs = std::fabs(db);
-        const int64_t cap = 3 * (int64_t)N;   // |U_a - U_b| <= 3N
-        int64_t n = 0;
-        for (; n <= cap; ++n) {
-            const uint32_t v = swap_thr(dabs, n);
-            if (v == 0) break;
-            sthr.push_back(v);
-        }
-        // the thresholds decrease with n; check that the zero tail stays zero
-        for (int64_t m = n; m <= std::min(cap, n + 64); ++m)
-            if (swap_thr(dabs, m) != 0) return bail(fail(EA_EINVAL, "non-monotone swap table for pair %d", k));
-        slen[k] = (int32_t)(sthr.size() - soff[k]);
-    }
+    if (int rc = build_swap_tables(betas, n_T, N, &sthr, &soff, &slen, &ssgn, nullptr)) return bail(rc);
     // couplings as 6 incidence bits per site
     std::vector<uint8_t> j6((size_t)n_realizations * N);
     for (int r = 0; r < n_realizations; ++r) {
@@ -394,6 +385,24 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
     return EA_OK;
 }
 
+int ea_job_footprint(int L, const double *betas, int n_T, int n_realizations, int layout, size_t *bytes)
+{
+    if (!betas || !bytes || L < 2 || L > EA_MAX_L || n_T < 1 || n_T > EA_MAX_TEMPS || n_realizations < 1 ||
+        (layout != EA_LAYOUT_CAMSC && layout != EA_LAYOUT_AMSC4))
+        return fail(EA_EINVAL, "ea_job_footprint: bad arguments");
+    int64_t total = 0;
+    if (int rc = build_swap_tables(betas, n_T, L * L * L, nullptr, nullptr, nullptr, nullptr, &total)) return rc;
+    *bytes = job_footprint_bytes(L, n_T, n_realizations, layout, total);
+    return EA_OK;
+}
+
+int ea_sim_footprint(const ea_sim *s, size_t *bytes)
+{
+    if (!s || !bytes) return fail(EA_EINVAL, "ea_sim_footprint: NULL argument");
+    *bytes = s->footprint;
+    return EA_OK;
+}
+
 void ea_destroy(ea_sim *s)
 {
     if (!s) return;
@@ -416,93 +425,6 @@ int ea_get_dims(const ea_sim *s, int *L, int *n_T, int *R, int *layout)
 int ea_sweep(ea_sim *s, int64_t n_sweeps, int swap_every)
 {
     return ea_sweep_batch(&s, 1, &n_sweeps, &swap_every);
-}
-
-int ea_sweep_batch(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps, const int *swap_every)
-{
-    if (!sims || n_sims < 1 || !n_sweeps || !swap_every) return fail(EA_EINVAL, "ea_sweep_batch: bad arguments");
-    if (n_sims > 4095) return fail(EA_EINVAL, "at most 4095 jobs per launch");
-    const int layout = sims[0] ? sims[0]->layout : 0;
-    int64_t total_units = 0;
-    for (int j = 0; j < n_sims; ++j) {
-        ea_sim *s = sims[j];
-        if (!s) return fail(EA_EINVAL, "sims[%d] is NULL", j);
-        if (s->layout != layout) return fail(EA_EINVAL, "sims[%d] has a different layout", j);
-        if (s->device != sims[0]->device) return fail(EA_EINVAL, "sims[%d] lives on another device", j);
-        if (n_sweeps[j] < 0 || n_sweeps[j] > 0x7FFFFFFF) return fail(EA_EINVAL, "n_sweeps[%d] out of range", j);
-        if (swap_every[j] < 0) return fail(EA_EINVAL, "swap_every[%d] < 0", j);
-        if (s->t + n_sweeps[j] >= ((int64_t)1 << 32))
-            return fail(EA_ESTATE, "sweep counter of sims[%d] would reach 2^32", j);
-        for (int i = 0; i < j; ++i)
-            if (sims[i] == s) return fail(EA_EINVAL, "sims[%d] appears twice", j);
-        total_units += n_sweeps[j] > 0 ? s->h.ladders : 0;
-    }
-    if (total_units == 0) return EA_OK;
-    ea_sim *s0 = sims[0];
-    EA_HIP(hipSetDevice(s0->device));
-    hipStream_t st = s0->stream;
-
-    if (n_sims == 1) {
-        ea_sim *s = s0;
-        s->h.n_sweeps = (int32_t)n_sweeps[0];
-        s->h.swap_every = swap_every[0];
-        EA_HIP(hipMemcpyAsync(&s->d_job->n_sweeps, &s->h.n_sweeps, 2 * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        const size_t lds = s->lds;
-        int grid = 0;
-        if (int rc = device_grid(layout, s->block_threads, lds, s->h.ladders, &grid)) return rc;
-        EA_HIP(launch_sweep(s->d_job, 1, s->d_units, s->h.ladders, s->d_counters + 1, layout, s->block_threads, lds,
-                            grid, st));
-        s->t += n_sweeps[0];
-        return sync_if_needed(s);
-    }
-
-    // several jobs: one descriptor per job, units sorted by work (largest first)
-    std::vector<JobDesc> descs(n_sims);
-    std::vector<std::pair<double, uint32_t>> order;
-    int bt = 0;
-    size_t lds = 0;
-    for (int j = 0; j < n_sims; ++j) {
-        ea_sim *s = sims[j];
-        descs[j] = s->h;
-        descs[j].n_sweeps = (int32_t)n_sweeps[j];
-        descs[j].swap_every = swap_every[j];
-        if (n_sweeps[j] == 0) continue;
-        bt = std::max(bt, s->block_threads);
-        lds = std::max(lds, s->lds);
-        const double work = (double)s->N * s->n_T * (double)n_sweeps[j];
-        for (int l = 0; l < s->h.ladders; ++l) order.push_back({-work, ((uint32_t)j << 20) | (uint32_t)l});
-    }
-    std::stable_sort(order.begin(), order.end(),
-                     [](const std::pair<double, uint32_t> &a, const std::pair<double, uint32_t> &b) { return a.first < b.first; });
-    std::vector<uint32_t> units(order.size());
-    for (size_t k = 0; k < order.size(); ++k) units[k] = order[k].second;
-    // one queue counter, shared by the launch
-    JobDesc *d_descs = nullptr;
-    uint32_t *d_units = nullptr, *d_queue = nullptr;
-    EA_HIP(hipMalloc(&d_descs, descs.size() * sizeof(JobDesc)));
-    auto cleanup = [&]() {
-        (void)hipFree(d_descs);
-        if (d_units) (void)hipFree(d_units);
-        if (d_queue) (void)hipFree(d_queue);
-    };
-    hipError_t e = hipMalloc(&d_units, units.size() * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMalloc(&d_queue, sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMemcpyAsync(d_descs, descs.data(), descs.size() * sizeof(JobDesc), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_units, units.data(), units.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemsetAsync(d_queue, 0, sizeof(uint32_t), st);
-    int grid = 0;
-    if (e == hipSuccess) {
-        if (int rc = device_grid(layout, bt, lds, (int)units.size(), &grid)) {
-            cleanup();
-            return rc;
-        }
-        e = launch_sweep(d_descs, n_sims, d_units, (int)units.size(), d_queue, layout, bt, lds, grid, st);
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    cleanup();
-    if (e != hipSuccess) return fail(EA_EDEVICE, "batched sweep failed: %s", hipGetErrorString(e));
-    for (int j = 0; j < n_sims; ++j) sims[j]->t += n_sweeps[j];
-    return EA_OK;
 }
 
 int ea_observables(ea_sim *s, int32_t *energy, int32_t *overlap)

@@ -1,0 +1,66 @@
+// Host-side internals shared by the ABI (ea_api.cpp) and the runtime
+// (ea_runtime.cpp: launch plans with hipGraph, autotuner, serving loop).
+// Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "ea.h"
+#include "ea_internal.h"
+
+namespace ea {
+
+constexpr size_t kLdsBudget = 160 * 1024 - 1024;   // dynamic LDS per workgroup; the rest is static
+constexpr size_t kLdsPerCu = 160 * 1024;
+constexpr int kThreadsPerCu = 2048;
+
+extern thread_local std::string g_error;
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+#define EA_HIP(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess) return ::ea::fail(EA_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+uint32_t prob_to_u32(double p);
+uint32_t flip_thr(double beta, int u);
+uint32_t swap_thr(double dbeta_abs, int64_t n);
+
+struct DeviceAlloc {
+    void *(*alloc)(size_t, void *) = nullptr;
+    void (*release)(void *, void *) = nullptr;
+    void *ctx = nullptr;
+};
+
+int wgs_per_cu(size_t lds, int bt);
+int build_swap_tables(const double *betas, int n_T, int N, std::vector<uint32_t> *sthr, std::vector<int32_t> *soff,
+                      std::vector<int32_t> *slen, std::vector<int32_t> *ssgn, int64_t *total);
+size_t job_footprint_bytes(int L, int n_T, int R, int layout, int64_t swap_entries);
+int device_grid(int layout, int bt, size_t lds, int n_units, int *grid);
+
+}  // namespace ea
+
+// One job: R realizations x 2 copies x n_T slots, resident in HBM.
+struct ea_sim {
+    int L = 0, N = 0, n_T = 0, R = 0, layout = 0, NW = 0;
+    int block_threads = 0, words_resident = 0;
+    int device = 0;
+    uint64_t seed = 0;
+    int64_t t = 0;                    // host shadow of the sweep counter
+    hipStream_t stream = nullptr;
+    bool user_stream = false;
+    ea::DeviceAlloc da;
+    std::vector<void *> owned;        // device buffers to release
+    ea::JobDesc h{};                  // host copy of the descriptor
+    ea::JobDesc *d_job = nullptr;
+    uint32_t *d_units = nullptr;      // ladders of this job for a lone launch
+    uint32_t *d_counters = nullptr;   // [0] sweep counter, [1] work queue
+    int64_t swap_total = 0;           // entries in the swap tables
+    size_t lds = 0;                   // dynamic LDS bytes of this job's sweep workgroups
+    size_t footprint = 0;             // device bytes owned by this job
+};

@@ -114,7 +114,7 @@ hipError_t launch_observables(const JobDesc *d_job, const JobDesc &h_job, int la
                               int32_t *d_overlap, hipStream_t s);
 hipError_t launch_unpack(const JobDesc *d_job, const JobDesc &h_job, int layout, int8_t *d_spins, hipStream_t s);
 hipError_t launch_pack(const JobDesc *d_job, const JobDesc &h_job, int layout, const int8_t *d_spins, hipStream_t s);
-hipError_t sweep_kernel_attributes(int layout, int *max_threads, int *num_regs);
+hipError_t sweep_set_lds(int layout, size_t lds);
 int sweep_max_blocks_per_cu(int layout, int block_threads, size_t lds);
 
 }  // namespace ea

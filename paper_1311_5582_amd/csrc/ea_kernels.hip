@@ -22,6 +22,8 @@
 // is reduced (bit-plane counters + wave ballots) and the ascending swap pass
 // is evaluated: all acceptance bits that the sequential pass could need are
 // computed in parallel, then one lane walks the pairs in order.
+#include <atomic>
+
 #include "ea_internal.h"
 
 namespace ea {
@@ -741,23 +743,36 @@ hipError_t launch_init_spins(const JobDesc *d_job, const JobDesc &h, int layout,
     return hipGetLastError();
 }
 
+hipError_t sweep_set_lds(int layout, size_t lds)
+{
+    // the attribute is process-wide per kernel; raise it only when a launch needs more
+    static std::atomic<size_t> set_max[2] = {{0}, {0}};
+    std::atomic<size_t> &cur = set_max[layout ? 1 : 0];
+    if (lds <= cur.load()) return hipSuccess;
+    hipError_t e = layout == 0 ? hipFuncSetAttribute((const void *)sweep_kernel<0>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
+                               : hipFuncSetAttribute((const void *)sweep_kernel<1>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) {
+        size_t prev = cur.load();
+        while (prev < lds && !cur.compare_exchange_weak(prev, lds)) {
+        }
+    }
+    return e;
+}
+
 hipError_t launch_sweep(const JobDesc *d_jobs, int n_jobs, const uint32_t *d_units, int n_units, uint32_t *d_queue,
                         int layout, int block_threads, size_t lds, int grid, hipStream_t s)
 {
-    if (layout == 0) {
-        hipError_t e = hipFuncSetAttribute((const void *)sweep_kernel<0>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
+    hipError_t e = sweep_set_lds(layout, lds);
+    if (e != hipSuccess) return e;
+    if (layout == 0)
         hipLaunchKernelGGL(sweep_kernel<0>, dim3(grid), dim3(block_threads), lds, s, d_jobs, d_units, n_units,
                            d_queue);
-    } else {
-        hipError_t e = hipFuncSetAttribute((const void *)sweep_kernel<1>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
+    else
         hipLaunchKernelGGL(sweep_kernel<1>, dim3(grid), dim3(block_threads), lds, s, d_jobs, d_units, n_units,
                            d_queue);
-    }
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(advance_kernel, dim3((n_jobs + 255) / 256), dim3(256), 0, s, d_jobs, n_jobs, d_queue);
     return hipGetLastError();

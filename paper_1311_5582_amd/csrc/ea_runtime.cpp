@@ -1,0 +1,443 @@
+// Runtime around the sweep kernel: launch sets over several jobs of uneven
+// size (one persistent launch, largest ladders first), launch plans whose
+// step is captured once in a hipGraph and replayed, and an autotuner that
+// picks the workgroup size by timing candidates on scratch copies of the jobs.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ea.h"
+#include "ea_host.h"
+#include "ea_internal.h"
+
+namespace ea {
+
+// Device arrays of one launch: descriptors, unit list, work-queue counter.
+struct LaunchSet {
+    int layout = 0;
+    int n_jobs = 0;
+    int n_units = 0;
+    int bt = 0;
+    int grid = 0;
+    size_t lds = 0;
+    JobDesc *d_descs = nullptr;
+    uint32_t *d_units = nullptr;
+    uint32_t *d_queue = nullptr;
+    std::vector<JobDesc> descs;
+};
+
+static void launchset_free(LaunchSet &ls)
+{
+    if (ls.d_descs) (void)hipFree(ls.d_descs);
+    if (ls.d_units) (void)hipFree(ls.d_units);
+    if (ls.d_queue) (void)hipFree(ls.d_queue);
+    ls.d_descs = nullptr;
+    ls.d_units = nullptr;
+    ls.d_queue = nullptr;
+}
+
+static int min_block_threads(int N)
+{
+    return ((N + 84) / 85 + 63) / 64 * 64;
+}
+
+// descs[j] describes job j for this launch (n_sweeps/swap_every already set).
+// bt = 0 takes the largest planned size among the jobs.
+static int launchset_build(LaunchSet &ls, const std::vector<JobDesc> &descs, const std::vector<size_t> &lds_per_job,
+                           int layout, int bt, hipStream_t st)
+{
+    ls.layout = layout;
+    ls.n_jobs = (int)descs.size();
+    ls.descs = descs;
+    std::vector<std::pair<double, uint32_t>> order;
+    int want_bt = 0, need_bt = 64;
+    size_t lds = 0;
+    for (int j = 0; j < ls.n_jobs; ++j) {
+        const JobDesc &d = descs[j];
+        if (d.n_sweeps == 0) continue;
+        want_bt = std::max(want_bt, d.block_threads);
+        need_bt = std::max(need_bt, min_block_threads(d.N));
+        lds = std::max(lds, lds_per_job[j]);
+        const double work = (double)d.N * d.n_T * (double)d.n_sweeps;
+        for (int l = 0; l < d.ladders; ++l) order.push_back({-work, ((uint32_t)j << 20) | (uint32_t)l});
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<double, uint32_t> &a, const std::pair<double, uint32_t> &b) {
+                         return a.first < b.first;
+                     });
+    ls.bt = bt > 0 ? bt : want_bt;
+    if (ls.bt < need_bt) return fail(EA_EINVAL, "block_threads=%d is below %d needed by a job", ls.bt, need_bt);
+    ls.lds = lds;
+    ls.n_units = (int)order.size();
+    if (ls.n_units == 0) return EA_OK;
+    std::vector<uint32_t> units(order.size());
+    for (size_t k = 0; k < order.size(); ++k) units[k] = order[k].second;
+    if (int rc = device_grid(layout, ls.bt, ls.lds, ls.n_units, &ls.grid)) return rc;
+    EA_HIP(sweep_set_lds(layout, ls.lds));   // before any capture: not a stream operation
+    EA_HIP(hipMalloc(&ls.d_descs, descs.size() * sizeof(JobDesc)));
+    EA_HIP(hipMalloc(&ls.d_units, units.size() * sizeof(uint32_t)));
+    EA_HIP(hipMalloc(&ls.d_queue, sizeof(uint32_t)));
+    EA_HIP(hipMemcpyAsync(ls.d_descs, descs.data(), descs.size() * sizeof(JobDesc), hipMemcpyHostToDevice, st));
+    EA_HIP(hipMemcpyAsync(ls.d_units, units.data(), units.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    EA_HIP(hipMemsetAsync(ls.d_queue, 0, sizeof(uint32_t), st));   // armed once; the launch re-arms it
+    EA_HIP(hipStreamSynchronize(st));
+    return EA_OK;
+}
+
+static int launchset_launch(const LaunchSet &ls, hipStream_t st)
+{
+    if (ls.n_units == 0) return EA_OK;
+    EA_HIP(launch_sweep(ls.d_descs, ls.n_jobs, ls.d_units, ls.n_units, ls.d_queue, ls.layout, ls.bt, ls.lds, ls.grid,
+                        st));
+    return EA_OK;
+}
+
+static int validate_jobs(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps, const int *swap_every)
+{
+    if (!sims || n_sims < 1 || !n_sweeps || !swap_every) return fail(EA_EINVAL, "bad job list");
+    if (n_sims > 4095) return fail(EA_EINVAL, "at most 4095 jobs per launch");
+    for (int j = 0; j < n_sims; ++j) {
+        const ea_sim *s = sims[j];
+        if (!s) return fail(EA_EINVAL, "sims[%d] is NULL", j);
+        if (s->layout != sims[0]->layout) return fail(EA_EINVAL, "sims[%d] has a different layout", j);
+        if (s->device != sims[0]->device) return fail(EA_EINVAL, "sims[%d] lives on another device", j);
+        if (n_sweeps[j] < 0 || n_sweeps[j] > 0x7FFFFFFF) return fail(EA_EINVAL, "n_sweeps[%d] out of range", j);
+        if (swap_every[j] < 0) return fail(EA_EINVAL, "swap_every[%d] < 0", j);
+        for (int i = 0; i < j; ++i)
+            if (sims[i] == s) return fail(EA_EINVAL, "sims[%d] appears twice", j);
+    }
+    return EA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: workgroup size for a set of jobs, timed on scratch copies.
+// ---------------------------------------------------------------------------
+static std::mutex g_tune_mu;
+static std::map<std::string, int> g_tune_cache;
+static bool g_tune_loaded = false;
+
+static std::string tune_key(const std::vector<JobDesc> &descs, int layout)
+{
+    // shape classes: (L, words, swap on/off) multiset; realization counts do not change the best size
+    std::vector<std::string> parts;
+    for (const JobDesc &d : descs) {
+        char b[64];
+        std::snprintf(b, sizeof b, "%d.%d.%d", d.L, d.NW, d.swap_every > 0 ? 1 : 0);
+        parts.push_back(b);
+    }
+    std::sort(parts.begin(), parts.end());
+    parts.erase(std::unique(parts.begin(), parts.end()), parts.end());
+    std::string k = "gfx950:" + std::to_string(layout);
+    for (const std::string &p : parts) k += ":" + p;
+    return k;
+}
+
+static void tune_cache_load()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("EA_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char key[512];
+    int bt = 0;
+    while (std::fscanf(f, "%511s %d", key, &bt) == 2) g_tune_cache[key] = bt;
+    std::fclose(f);
+}
+
+static void tune_cache_store(const std::string &key, int bt)
+{
+    g_tune_cache[key] = bt;
+    const char *path = std::getenv("EA_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d\n", key.c_str(), bt);
+    std::fclose(f);
+}
+
+// Time each candidate on scratch copies of the jobs' mutable state (spins,
+// permutation, counters, swap counts); the jobs themselves are untouched.
+static int autotune_bt(const std::vector<JobDesc> &descs, const std::vector<size_t> &lds_per_job, int layout,
+                       hipStream_t st, int *best_bt)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_cache_load();
+    const std::string key = tune_key(descs, layout);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+        *best_bt = it->second;
+        return EA_OK;
+    }
+    int need = 64;
+    for (const JobDesc &d : descs) need = std::max(need, min_block_threads(d.N));
+    std::vector<JobDesc> scratch = descs;
+    std::vector<void *> bufs;
+    auto cleanup = [&]() {
+        for (void *p : bufs) (void)hipFree(p);
+    };
+    int64_t work = 0;
+    for (JobDesc &d : scratch) {
+        const size_t spin_bytes = (size_t)d.ladders * d.NW * d.N * 4;
+        void *sp = nullptr, *pm = nullptr, *ac = nullptr, *ct = nullptr;
+        hipError_t e = hipMalloc(&sp, spin_bytes);
+        if (e == hipSuccess) bufs.push_back(sp), e = hipMalloc(&pm, (size_t)d.ladders * kMaxTemps * 4);
+        if (e == hipSuccess) bufs.push_back(pm), e = hipMalloc(&ac, (size_t)d.ladders * kMaxTemps * 4);
+        if (e == hipSuccess) bufs.push_back(ac), e = hipMalloc(&ct, 8);
+        if (e == hipSuccess) bufs.push_back(ct);
+        if (e == hipSuccess) e = hipMemcpyAsync(sp, d.spins, spin_bytes, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(pm, d.temp_of_slot, (size_t)d.ladders * kMaxTemps * 4, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemsetAsync(ac, 0, (size_t)d.ladders * kMaxTemps * 4, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(ct, d.sweep_ctr, 4, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) {
+            cleanup();
+            return fail(EA_ENOMEM, "autotune scratch: %s", hipGetErrorString(e));
+        }
+        d.spins = (uint32_t *)sp;
+        d.temp_of_slot = (int32_t *)pm;
+        d.swap_acc = (uint32_t *)ac;
+        d.sweep_ctr = (uint32_t *)ct;
+        work += (int64_t)d.ladders * d.N * d.n_T;
+    }
+    // a few sweeps, enough for ~50 ms-equivalent of the largest config at 1 ps/flip
+    const int sweeps = (int)std::max<int64_t>(2, std::min<int64_t>(20, 50000000000LL / std::max<int64_t>(work, 1)));
+    for (JobDesc &d : scratch) {
+        d.n_sweeps = sweeps;
+        d.swap_every = d.swap_every > 0 ? 1 : 0;   // tune with the most PT work
+    }
+    const int candidates[] = {256, 512, 768, 1024};
+    float best_ms = 1e30f;
+    int best = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(EA_EDEVICE, "autotune: hipEventCreate failed");
+    }
+    int rc = EA_OK;
+    for (int bt : candidates) {
+        if (bt < need) continue;
+        LaunchSet ls;
+        rc = launchset_build(ls, scratch, lds_per_job, layout, bt, st);
+        if (rc) break;
+        float ms = 0;
+        hipError_t e = hipSuccess;
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {   // first run warms up
+            e = hipEventRecord(e0, st);
+            if (e == hipSuccess && launchset_launch(ls, st) != EA_OK) e = hipErrorUnknown;
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        }
+        launchset_free(ls);
+        if (e != hipSuccess) {
+            rc = fail(EA_EDEVICE, "autotune run failed: %s", hipGetErrorString(e));
+            break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = bt;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    cleanup();
+    if (rc) return rc;
+    if (best == 0) return fail(EA_EINVAL, "no workgroup size fits these jobs");
+    tune_cache_store(key, best);
+    *best_bt = best;
+    return EA_OK;
+}
+
+}  // namespace ea
+
+using namespace ea;
+
+// ---------------------------------------------------------------------------
+// Launch plans
+// ---------------------------------------------------------------------------
+struct ea_plan {
+    LaunchSet ls;
+    std::vector<ea_sim *> sims;
+    int sweeps_per_step = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool user_stream = false;
+    bool use_graph = true;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int ea_sweep_batch(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps, const int *swap_every)
+{
+    if (int rc = validate_jobs(sims, n_sims, n_sweeps, swap_every)) return rc;
+    for (int j = 0; j < n_sims; ++j)
+        if (sims[j]->t + n_sweeps[j] >= ((int64_t)1 << 32))
+            return fail(EA_ESTATE, "sweep counter of sims[%d] would reach 2^32", j);
+    ea_sim *s0 = sims[0];
+    EA_HIP(hipSetDevice(s0->device));
+    hipStream_t st = s0->stream;
+    if (n_sims == 1) {
+        ea_sim *s = s0;
+        if (n_sweeps[0] == 0) return EA_OK;
+        s->h.n_sweeps = (int32_t)n_sweeps[0];
+        s->h.swap_every = swap_every[0];
+        EA_HIP(hipMemcpyAsync(&s->d_job->n_sweeps, &s->h.n_sweeps, 2 * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        int grid = 0;
+        if (int rc = device_grid(s->layout, s->block_threads, s->lds, s->h.ladders, &grid)) return rc;
+        EA_HIP(launch_sweep(s->d_job, 1, s->d_units, s->h.ladders, s->d_counters + 1, s->layout, s->block_threads,
+                            s->lds, grid, st));
+        s->t += n_sweeps[0];
+        if (!s->user_stream) EA_HIP(hipStreamSynchronize(st));
+        return EA_OK;
+    }
+    std::vector<JobDesc> descs(n_sims);
+    std::vector<size_t> lds(n_sims);
+    for (int j = 0; j < n_sims; ++j) {
+        descs[j] = sims[j]->h;
+        descs[j].n_sweeps = (int32_t)n_sweeps[j];
+        descs[j].swap_every = swap_every[j];
+        lds[j] = sims[j]->lds;
+    }
+    LaunchSet ls;
+    int rc = launchset_build(ls, descs, lds, s0->layout, 0, st);
+    if (rc == EA_OK) rc = launchset_launch(ls, st);
+    if (rc == EA_OK) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = fail(EA_EDEVICE, "batched sweep failed: %s", hipGetErrorString(e));
+    }
+    launchset_free(ls);
+    if (rc) return rc;
+    for (int j = 0; j < n_sims; ++j) sims[j]->t += n_sweeps[j];
+    return EA_OK;
+}
+
+void ea_default_plan_options(ea_plan_options *opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof *opt);
+    opt->autotune = 1;
+    opt->use_graph = 1;
+}
+
+int ea_plan_create(ea_sim *const *sims, int n_sims, int sweeps_per_step, const int *swap_every,
+                   const ea_plan_options *opt_in, ea_plan **out)
+{
+    if (!out) return fail(EA_EINVAL, "ea_plan_create: out is NULL");
+    *out = nullptr;
+    if (sweeps_per_step < 1) return fail(EA_EINVAL, "sweeps_per_step=%d < 1", sweeps_per_step);
+    ea_plan_options opt;
+    ea_default_plan_options(&opt);
+    if (opt_in) opt = *opt_in;
+    std::vector<int64_t> ns(n_sims > 0 ? n_sims : 1, sweeps_per_step);
+    if (int rc = validate_jobs(sims, n_sims, ns.data(), swap_every)) return rc;
+    if (opt.block_threads != 0 && (opt.block_threads < 64 || opt.block_threads > kMaxBlock || opt.block_threads % 64))
+        return fail(EA_EINVAL, "block_threads=%d must be a multiple of 64 in [64, %d]", opt.block_threads, kMaxBlock);
+    EA_HIP(hipSetDevice(sims[0]->device));
+    ea_plan *p = new (std::nothrow) ea_plan;
+    if (!p) return fail(EA_ENOMEM, "host allocation failed");
+    p->sims.assign(sims, sims + n_sims);
+    p->sweeps_per_step = sweeps_per_step;
+    p->device = sims[0]->device;
+    p->use_graph = opt.use_graph != 0;
+    p->user_stream = opt.stream != nullptr;
+    auto bail = [p](int rc) {
+        launchset_free(p->ls);
+        if (p->exec) (void)hipGraphExecDestroy(p->exec);
+        if (p->graph) (void)hipGraphDestroy(p->graph);
+        if (p->own_stream) (void)hipStreamDestroy(p->stream);
+        delete p;
+        return rc;
+    };
+    if (p->user_stream) {
+        p->stream = (hipStream_t)opt.stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return bail(fail(EA_EDEVICE, "hipStreamCreate failed: %s", hipGetErrorString(e)));
+        p->own_stream = true;
+    }
+    std::vector<JobDesc> descs(n_sims);
+    std::vector<size_t> lds(n_sims);
+    for (int j = 0; j < n_sims; ++j) {
+        descs[j] = sims[j]->h;
+        descs[j].n_sweeps = sweeps_per_step;
+        descs[j].swap_every = swap_every[j];
+        lds[j] = sims[j]->lds;
+    }
+    // all prior work on the jobs' own streams must land before the plan reads them
+    for (ea_sim *s : p->sims) {
+        hipError_t e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return bail(fail(EA_EDEVICE, "job stream failed: %s", hipGetErrorString(e)));
+    }
+    int bt = opt.block_threads;
+    if (bt == 0 && opt.autotune) {
+        if (int rc = autotune_bt(descs, lds, sims[0]->layout, p->stream, &bt)) return bail(rc);
+    }
+    if (int rc = launchset_build(p->ls, descs, lds, sims[0]->layout, bt, p->stream)) return bail(rc);
+    if (p->use_graph && p->ls.n_units > 0) {
+        hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            const int rc = launchset_launch(p->ls, p->stream);
+            hipError_t e2 = hipStreamEndCapture(p->stream, &p->graph);
+            if (rc) return bail(rc);
+            e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return bail(fail(EA_EDEVICE, "graph capture failed: %s", hipGetErrorString(e)));
+    }
+    *out = p;
+    return EA_OK;
+}
+
+int ea_plan_run(ea_plan *p, int64_t n_steps)
+{
+    if (!p) return fail(EA_EINVAL, "ea_plan_run: NULL plan");
+    if (n_steps < 0) return fail(EA_EINVAL, "n_steps < 0");
+    const int64_t add = n_steps * p->sweeps_per_step;
+    for (ea_sim *s : p->sims)
+        if (s->t + add >= ((int64_t)1 << 32)) return fail(EA_ESTATE, "a job's sweep counter would reach 2^32");
+    EA_HIP(hipSetDevice(p->device));
+    for (int64_t k = 0; k < n_steps; ++k) {
+        if (p->exec)
+            EA_HIP(hipGraphLaunch(p->exec, p->stream));
+        else if (int rc = launchset_launch(p->ls, p->stream))
+            return rc;
+    }
+    for (ea_sim *s : p->sims) s->t += add;
+    if (!p->user_stream) EA_HIP(hipStreamSynchronize(p->stream));
+    return EA_OK;
+}
+
+int ea_plan_info(const ea_plan *p, int *block_threads, int *grid, int *n_units, size_t *lds_bytes, int *uses_graph)
+{
+    if (!p) return fail(EA_EINVAL, "ea_plan_info: NULL plan");
+    if (block_threads) *block_threads = p->ls.bt;
+    if (grid) *grid = p->ls.grid;
+    if (n_units) *n_units = p->ls.n_units;
+    if (lds_bytes) *lds_bytes = p->ls.lds;
+    if (uses_graph) *uses_graph = p->exec != nullptr;
+    return EA_OK;
+}
+
+void ea_plan_destroy(ea_plan *p)
+{
+    if (!p) return;
+    (void)hipSetDevice(p->device);
+    (void)hipStreamSynchronize(p->stream);
+    launchset_free(p->ls);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->own_stream) (void)hipStreamDestroy(p->stream);
+    delete p;
+}
+
+}  // extern "C"

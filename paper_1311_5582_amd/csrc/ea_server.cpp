@@ -1,0 +1,336 @@
+// Serving loop: continuous batching of simulation jobs on one GPU.
+//
+// Jobs are submitted with host inputs and wait in arrival order.  Each step
+// (1) admits waiting jobs, first fit in arrival order, while their exact HBM
+// footprint fits the budget, (2) runs one launch over every admitted job for a
+// quantum of sweeps (replaying a graph-captured plan while the job set is
+// unchanged), and (3) retires finished jobs: their energies and overlaps are
+// measured, their device state is released, and the memory admits the next
+// jobs.  Results are a pure function of each job's inputs (counter-based
+// stream, device-resident sweep counters), so a job's result is the same alone
+// and in any mix.
+#include <algorithm>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <vector>
+
+#include "ea.h"
+#include "ea_host.h"
+
+using namespace ea;
+
+namespace {
+
+struct Job {
+    int64_t id = 0;
+    int status = EA_JOB_QUEUED;
+    int L = 0, n_T = 0, R = 0, swap_every = 0;
+    uint64_t seed = 0;
+    int64_t n_sweeps = 0, done = 0;
+    size_t footprint = 0;
+    std::vector<int8_t> J;
+    std::vector<double> betas;
+    ea_sim *sim = nullptr;
+    std::vector<int32_t> energy, overlap;      // results once DONE
+    std::vector<int8_t> spins;                 // final state (keep_state)
+    std::vector<int32_t> perm;
+    std::string error;
+};
+
+}  // namespace
+
+struct ea_server {
+    ea_server_options opt{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t used = 0;
+    int64_t next_id = 1;
+    std::map<int64_t, std::unique_ptr<Job>> jobs;
+    std::deque<int64_t> queue;        // waiting, arrival order
+    std::vector<int64_t> active;      // admitted, running
+    // plan cache: valid while the active set and the per-job sweep counts are unchanged
+    ea_plan *plan = nullptr;
+    std::vector<int64_t> plan_ids;
+    int plan_sweeps = 0;
+    int64_t steps = 0, launches_replayed = 0, plans_built = 0;
+};
+
+static void drop_plan(ea_server *sv)
+{
+    if (sv->plan) ea_plan_destroy(sv->plan);
+    sv->plan = nullptr;
+    sv->plan_ids.clear();
+    sv->plan_sweeps = 0;
+}
+
+static void release_job_device(ea_server *sv, Job *j)
+{
+    if (j->sim) {
+        ea_destroy(j->sim);
+        j->sim = nullptr;
+        sv->used -= j->footprint;
+    }
+}
+
+extern "C" {
+
+void ea_default_server_options(ea_server_options *opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof *opt);
+    opt->quantum_sweeps = 200;
+    opt->layout = EA_LAYOUT_CAMSC;
+    opt->autotune = 0;   // the job mix changes at every arrival; tuning each mix would cost more than it saves
+}
+
+int ea_server_create(const ea_server_options *opt_in, ea_server **out)
+{
+    if (!out) return fail(EA_EINVAL, "ea_server_create: out is NULL");
+    *out = nullptr;
+    ea_server_options opt;
+    ea_default_server_options(&opt);
+    if (opt_in) opt = *opt_in;
+    if (opt.quantum_sweeps < 1) return fail(EA_EINVAL, "quantum_sweeps < 1");
+    if (opt.layout != EA_LAYOUT_CAMSC && opt.layout != EA_LAYOUT_AMSC4) return fail(EA_EINVAL, "unknown layout");
+    if (opt.max_active < 0 || opt.max_active > 4095) return fail(EA_EINVAL, "max_active outside [0, 4095]");
+    ea_server *sv = new (std::nothrow) ea_server;
+    if (!sv) return fail(EA_ENOMEM, "host allocation failed");
+    sv->opt = opt;
+    if (sv->opt.max_active == 0) sv->opt.max_active = 4095;
+    hipError_t e = hipGetDevice(&sv->device);
+    if (e == hipSuccess && sv->opt.hbm_budget_bytes == 0) {
+        size_t free_b = 0, total_b = 0;
+        e = hipMemGetInfo(&free_b, &total_b);
+        sv->opt.hbm_budget_bytes = free_b / 10 * 8;
+    }
+    if (e == hipSuccess && opt.stream == nullptr) e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete sv;
+        return fail(EA_EDEVICE, "server set-up failed: %s", hipGetErrorString(e));
+    }
+    if (opt.stream) sv->stream = (hipStream_t)opt.stream;
+    *out = sv;
+    return EA_OK;
+}
+
+int ea_server_submit(ea_server *sv, int L, const int8_t *couplings, const double *betas, int n_T, int R, uint64_t seed,
+                     int64_t n_sweeps, int swap_every, int64_t *job_id)
+{
+    if (!sv || !job_id) return fail(EA_EINVAL, "ea_server_submit: NULL argument");
+    if (n_sweeps < 0 || n_sweeps >= ((int64_t)1 << 32)) return fail(EA_EINVAL, "n_sweeps out of range");
+    if (swap_every < 0) return fail(EA_EINVAL, "swap_every < 0");
+    size_t fp = 0;
+    if (int rc = ea_job_footprint(L, betas, n_T, R, sv->opt.layout, &fp)) return rc;
+    if (fp > sv->opt.hbm_budget_bytes)
+        return fail(EA_ENOMEM, "job needs %zu device bytes, more than the whole budget %zu", fp,
+                    sv->opt.hbm_budget_bytes);
+    if (!couplings) return fail(EA_EINVAL, "couplings is NULL");
+    const size_t nJ = (size_t)R * L * L * L * 3;
+    for (size_t b = 0; b < nJ; ++b)
+        if (couplings[b] != 1 && couplings[b] != -1) return fail(EA_EINVAL, "couplings[%zu] is not +-1", b);
+    std::unique_ptr<Job> j(new (std::nothrow) Job);
+    if (!j) return fail(EA_ENOMEM, "host allocation failed");
+    j->id = sv->next_id++;
+    j->L = L; j->n_T = n_T; j->R = R; j->seed = seed; j->n_sweeps = n_sweeps; j->swap_every = swap_every;
+    j->footprint = fp;
+    j->J.assign(couplings, couplings + nJ);
+    j->betas.assign(betas, betas + n_T);
+    *job_id = j->id;
+    sv->queue.push_back(j->id);
+    sv->jobs[j->id] = std::move(j);
+    return EA_OK;
+}
+
+int ea_server_step(ea_server *sv, int *n_running, int *n_queued, int *n_finished)
+{
+    if (!sv) return fail(EA_EINVAL, "ea_server_step: NULL server");
+    EA_HIP(hipSetDevice(sv->device));
+    int finished = 0;
+    // 1. admission: first fit in arrival order
+    for (auto it = sv->queue.begin(); it != sv->queue.end();) {
+        Job *j = sv->jobs[*it].get();
+        if ((int)sv->active.size() >= sv->opt.max_active) break;
+        if (sv->used + j->footprint > sv->opt.hbm_budget_bytes) {
+            ++it;
+            continue;
+        }
+        ea_options o;
+        ea_default_options(&o);
+        o.layout = sv->opt.layout;
+        o.stream = sv->stream;
+        const int rc = ea_create(j->L, j->J.data(), j->betas.data(), j->n_T, j->R, j->seed, &o, &j->sim);
+        if (rc != EA_OK) {
+            j->status = EA_JOB_FAILED;
+            j->error = ea_last_error();
+            it = sv->queue.erase(it);
+            ++finished;
+            continue;
+        }
+        sv->used += j->footprint;
+        j->status = EA_JOB_RUNNING;
+        j->J.clear();
+        j->J.shrink_to_fit();
+        sv->active.push_back(j->id);
+        it = sv->queue.erase(it);
+    }
+    // jobs with nothing left to run finish without a launch
+    auto retire_done = [&](void) -> int {
+        std::vector<int64_t> still;
+        for (int64_t id : sv->active) {
+            Job *j = sv->jobs[id].get();
+            if (j->done < j->n_sweeps) {
+                still.push_back(id);
+                continue;
+            }
+            j->energy.assign((size_t)j->R * 2 * j->n_T, 0);
+            j->overlap.assign((size_t)j->R * j->n_T, 0);
+            int rc = ea_observables(j->sim, j->energy.data(), j->overlap.data());
+            if (rc == EA_OK && sv->opt.keep_state) {
+                j->spins.assign((size_t)j->R * 2 * j->n_T * j->L * j->L * j->L, 0);
+                j->perm.assign((size_t)j->R * 2 * j->n_T, 0);
+                rc = ea_state(j->sim, j->spins.data(), j->perm.data(), nullptr);
+            }
+            if (rc != EA_OK) {
+                j->status = EA_JOB_FAILED;
+                j->error = ea_last_error();
+            } else {
+                j->status = EA_JOB_DONE;
+            }
+            drop_plan(sv);   // the cached plan references this job's buffers
+            release_job_device(sv, j);
+            ++finished;
+        }
+        sv->active.swap(still);
+        return EA_OK;
+    };
+    retire_done();
+    // 2. one launch over every running job: the quantum never exceeds what any job has left
+    if (!sv->active.empty()) {
+        int q = sv->opt.quantum_sweeps;
+        for (int64_t id : sv->active) {
+            const Job *j = sv->jobs[id].get();
+            q = (int)std::min<int64_t>(q, j->n_sweeps - j->done);
+        }
+        if (sv->plan == nullptr || sv->plan_ids != sv->active || sv->plan_sweeps != q) {
+            drop_plan(sv);
+            std::vector<ea_sim *> sims;
+            std::vector<int> se;
+            for (int64_t id : sv->active) {
+                sims.push_back(sv->jobs[id]->sim);
+                se.push_back(sv->jobs[id]->swap_every);
+            }
+            ea_plan_options po;
+            ea_default_plan_options(&po);
+            po.autotune = sv->opt.autotune;
+            po.stream = sv->stream;
+            if (int rc = ea_plan_create(sims.data(), (int)sims.size(), q, se.data(), &po, &sv->plan)) return rc;
+            sv->plan_ids = sv->active;
+            sv->plan_sweeps = q;
+            ++sv->plans_built;
+        } else {
+            ++sv->launches_replayed;
+        }
+        if (int rc = ea_plan_run(sv->plan, 1)) return rc;
+        EA_HIP(hipStreamSynchronize(sv->stream));
+        for (int64_t id : sv->active) sv->jobs[id]->done += q;
+        ++sv->steps;
+        // 3. retire finished jobs
+        retire_done();
+    }
+    if (n_running) *n_running = (int)sv->active.size();
+    if (n_queued) *n_queued = (int)sv->queue.size();
+    if (n_finished) *n_finished = finished;
+    return EA_OK;
+}
+
+int ea_server_status(ea_server *sv, int64_t id, int *status, int64_t *sweeps_done)
+{
+    if (!sv) return fail(EA_EINVAL, "ea_server_status: NULL server");
+    auto it = sv->jobs.find(id);
+    if (it == sv->jobs.end()) return fail(EA_EINVAL, "unknown job %lld", (long long)id);
+    if (status) *status = it->second->status;
+    if (sweeps_done) *sweeps_done = it->second->done;
+    return EA_OK;
+}
+
+int ea_server_result(ea_server *sv, int64_t id, int32_t *energy, int32_t *overlap)
+{
+    if (!sv) return fail(EA_EINVAL, "ea_server_result: NULL server");
+    auto it = sv->jobs.find(id);
+    if (it == sv->jobs.end()) return fail(EA_EINVAL, "unknown job %lld", (long long)id);
+    const Job *j = it->second.get();
+    if (j->status != EA_JOB_DONE) return fail(EA_ESTATE, "job %lld is not done", (long long)id);
+    if (energy) std::memcpy(energy, j->energy.data(), j->energy.size() * sizeof(int32_t));
+    if (overlap) std::memcpy(overlap, j->overlap.data(), j->overlap.size() * sizeof(int32_t));
+    return EA_OK;
+}
+
+int ea_server_final_state(ea_server *sv, int64_t id, int8_t *spins, int32_t *temp_of_slot)
+{
+    if (!sv) return fail(EA_EINVAL, "ea_server_final_state: NULL server");
+    auto it = sv->jobs.find(id);
+    if (it == sv->jobs.end()) return fail(EA_EINVAL, "unknown job %lld", (long long)id);
+    const Job *j = it->second.get();
+    if (j->status != EA_JOB_DONE || j->spins.empty()) return fail(EA_ESTATE, "no final state kept for job %lld", (long long)id);
+    if (spins) std::memcpy(spins, j->spins.data(), j->spins.size());
+    if (temp_of_slot) std::memcpy(temp_of_slot, j->perm.data(), j->perm.size() * sizeof(int32_t));
+    return EA_OK;
+}
+
+int ea_server_cancel(ea_server *sv, int64_t id)
+{
+    if (!sv) return fail(EA_EINVAL, "ea_server_cancel: NULL server");
+    auto it = sv->jobs.find(id);
+    if (it == sv->jobs.end()) return fail(EA_EINVAL, "unknown job %lld", (long long)id);
+    Job *j = it->second.get();
+    if (j->status == EA_JOB_QUEUED) {
+        sv->queue.erase(std::find(sv->queue.begin(), sv->queue.end(), id));
+    } else if (j->status == EA_JOB_RUNNING) {
+        drop_plan(sv);
+        EA_HIP(hipStreamSynchronize(sv->stream));
+        release_job_device(sv, j);
+        sv->active.erase(std::find(sv->active.begin(), sv->active.end(), id));
+    } else {
+        return fail(EA_ESTATE, "job %lld already finished", (long long)id);
+    }
+    j->status = EA_JOB_CANCELLED;
+    return EA_OK;
+}
+
+int ea_server_release(ea_server *sv, int64_t id)
+{
+    if (!sv) return fail(EA_EINVAL, "ea_server_release: NULL server");
+    auto it = sv->jobs.find(id);
+    if (it == sv->jobs.end()) return fail(EA_EINVAL, "unknown job %lld", (long long)id);
+    const int st = it->second->status;
+    if (st == EA_JOB_QUEUED || st == EA_JOB_RUNNING) return fail(EA_ESTATE, "job %lld has not finished", (long long)id);
+    sv->jobs.erase(it);
+    return EA_OK;
+}
+
+int ea_server_stats(const ea_server *sv, size_t *hbm_used, size_t *hbm_budget, int64_t *steps, int64_t *plans_built,
+                    int64_t *launches_replayed)
+{
+    if (!sv) return fail(EA_EINVAL, "ea_server_stats: NULL server");
+    if (hbm_used) *hbm_used = sv->used;
+    if (hbm_budget) *hbm_budget = sv->opt.hbm_budget_bytes;
+    if (steps) *steps = sv->steps;
+    if (plans_built) *plans_built = sv->plans_built;
+    if (launches_replayed) *launches_replayed = sv->launches_replayed;
+    return EA_OK;
+}
+
+void ea_server_destroy(ea_server *sv)
+{
+    if (!sv) return;
+    (void)hipSetDevice(sv->device);
+    drop_plan(sv);
+    (void)hipStreamSynchronize(sv->stream);
+    for (auto &kv : sv->jobs) release_job_device(sv, kv.second.get());
+    if (sv->opt.stream == nullptr) (void)hipStreamDestroy(sv->stream);
+    delete sv;
+}
+
+}  // extern "C"

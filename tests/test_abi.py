@@ -96,3 +96,31 @@ def test_null_arguments(lib):
     assert lib.ea_swap_acceptance(None, None) == B.EA_EINVAL
     lib.ea_destroy(None)
     assert lib.ea_flip_thresholds(None, 3, None) == B.EA_EINVAL
+
+
+def test_server_and_plan_validation_without_device(lib):
+    opt = B.ServerOptions()
+    lib.ea_default_server_options(ctypes.byref(opt))
+    assert opt.quantum_sweeps > 0 and opt.layout == 0
+    h = ctypes.c_void_p()
+    for field, value in (("quantum_sweeps", 0), ("layout", 5), ("max_active", 5000), ("max_active", -1)):
+        bad = B.ServerOptions()
+        lib.ea_default_server_options(ctypes.byref(bad))
+        setattr(bad, field, value)
+        assert lib.ea_server_create(ctypes.byref(bad), ctypes.byref(h)) == B.EA_EINVAL, field
+    assert lib.ea_plan_create(None, 0, 1, None, None, ctypes.byref(h)) == B.EA_EINVAL
+    assert lib.ea_plan_run(None, 1) == B.EA_EINVAL
+    assert lib.ea_server_step(None, None, None, None) == B.EA_EINVAL
+    lib.ea_plan_destroy(None)
+    lib.ea_server_destroy(None)
+
+
+def test_job_footprint_host_only(lib):
+    betas = inputs.geometric_betas(32, 0.4, 2.0)
+    small = B.job_footprint(8, betas, 4)
+    big = B.job_footprint(16, betas, 4)
+    more = B.job_footprint(16, betas, 8)
+    assert 0 < small < big < more
+    # the spin words dominate: 2R ladders x words x N x 4 bytes
+    assert more - big >= 2 * 4 * 16 ** 3 * 4
+    assert B.job_footprint(16, betas, 4, "amsc4") > big

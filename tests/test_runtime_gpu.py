@@ -1,0 +1,159 @@
+"""Batching runtime and serving loop on the GPU: graph-captured plans against
+eager runs, and the server's results alone vs in a mix, bit for bit."""
+import numpy as np
+import pytest
+
+from paper_1311_5582_amd import binding as B
+from paper_1311_5582_amd import inputs
+from paper_1311_5582_amd import serve
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.lib()
+
+
+JOBS = [  # L, R, n_T, seed, swap_every
+    (6, 3, 16, 11, 1), (5, 2, 22, 12, 2), (8, 2, 40, 13, 0), (4, 4, 7, 14, 3), (10, 1, 33, 15, 1),
+]
+
+
+def _make(L, R, n_T, seed, layout="camsc", words_resident=0):
+    return B.Sim(L, inputs.couplings(L, R, seed), inputs.geometric_betas(n_T, 0.4, 2.0), seed, layout=layout,
+                 words_resident=words_resident)
+
+
+@pytest.mark.parametrize("use_graph,autotune", [(True, True), (False, False), (True, False)])
+def test_plan_replays_equal_eager(use_graph, autotune):
+    sims = [_make(L, R, n_T, seed) for L, R, n_T, seed, _ in JOBS]
+    refs = [_make(L, R, n_T, seed) for L, R, n_T, seed, _ in JOBS]
+    se = [j[4] for j in JOBS]
+    plan = B.Plan(sims, 3, se, autotune=autotune, use_graph=use_graph)
+    info = plan.info()
+    print(f"[runtime] plan info {info}", flush=True)
+    assert info["uses_graph"] == use_graph
+    assert info["units"] == sum(2 * j[1] for j in JOBS)
+    for rep in range(4):
+        plan.run(1)
+        for ref, (_, _, _, _, s) in zip(refs, JOBS):
+            ref.sweep(3, s)
+        for sim, ref in zip(sims, refs):
+            a, b = sim.state(), ref.state()
+            assert a[2] == b[2] == 3 * (rep + 1)
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), f"replay {rep}"
+            # eager work on the planned jobs between replays
+            assert np.array_equal(sim.observables()[0], ref.observables()[0])
+    plan.run(2)
+    for ref, (_, _, _, _, s) in zip(refs, JOBS):
+        ref.sweep(6, s)
+    for sim, ref in zip(sims, refs):
+        assert np.array_equal(sim.state()[0], ref.state()[0])
+    plan.close()
+
+
+def test_plan_amsc4_staged_equal_eager():
+    # the first job keeps 2 of its 6 AMSC4 words in LDS and stages the rest
+    jobs = [(8, 2, 48, 21, 2), (6, 3, 20, 22, 0)]
+    sims = [_make(L, R, n_T, s, layout="amsc4", words_resident=w) for L, R, n_T, s, w in jobs]
+    refs = [_make(L, R, n_T, s, layout="amsc4") for L, R, n_T, s, _ in jobs]
+    plan = B.Plan(sims, 4, [2, 1], autotune=True)
+    plan.run(3)
+    refs[0].sweep(12, 2)
+    refs[1].sweep(12, 1)
+    for a, b in zip(sims, refs):
+        assert np.array_equal(a.state()[0], b.state()[0]) and np.array_equal(a.state()[1], b.state()[1])
+
+
+def test_footprint_matches_allocation():
+    for L, R, n_T, seed, _ in JOBS:
+        for layout in ("camsc", "amsc4"):
+            betas = inputs.geometric_betas(n_T, 0.4, 2.0)
+            sim = B.Sim(L, inputs.couplings(L, R, seed), betas, seed, layout=layout)
+            assert sim.footprint() == B.job_footprint(L, betas, R, layout)
+            sim.close()
+
+
+def _trace(n, seed=9):
+    rng = np.random.default_rng(seed)
+    out, t = [], 0.0
+    for j in range(n):
+        t += rng.exponential(0.002)
+        out.append(dict(arrival_s=t, L=int(rng.integers(4, 9)), R=int(rng.integers(1, 5)),
+                        n_T=int(rng.integers(4, 40)), t_min=0.4, t_max=2.0,
+                        sweeps=int(rng.integers(5, 60)), swap_every=int(rng.integers(0, 4)), seed=1000 + j))
+    return out
+
+
+def test_server_results_alone_equal_mix():
+    """Jobs admitted under a budget that holds only a few at a time, with a
+    small quantum so they interleave: each final state equals the job run
+    alone, and the energies/overlaps equal ea_observables of that run."""
+    trace = _trace(8)
+    fps = [B.job_footprint(j["L"], inputs.geometric_betas(j["n_T"], 0.4, 2.0), j["R"]) for j in trace]
+    budget = sum(sorted(fps)[-3:])
+    srv = B.Server(hbm_budget_bytes=budget, quantum_sweeps=7, keep_state=True)
+
+    recs, wall = serve.run_trace(trace, srv, on_done=lambda jid, j, st: None)
+    assert len(recs) == len(trace)
+    for jid, rec in recs.items():
+        j = rec["job"]
+        assert rec["status"] == B.JOB_DONE, rec
+        spins, perm = srv.final_state(jid)
+        E, q = srv.result(jid)
+        alone = _make(j["L"], j["R"], j["n_T"], j["seed"])
+        alone.sweep(j["sweeps"], j["swap_every"])
+        s2, p2, t2 = alone.state()
+        assert t2 == j["sweeps"]
+        assert np.array_equal(spins, s2) and np.array_equal(perm, p2), f"job {jid} differs from alone"
+        E2, q2 = alone.observables()
+        assert np.array_equal(E, E2) and np.array_equal(q, q2)
+    st = srv.stats()
+    print(f"[runtime] server stats {st} wall {wall:.3f}s", flush=True)
+    assert st["hbm_used"] == 0
+    assert st["steps"] > len(trace) // 2
+    srv.close()
+
+
+def test_server_admission_respects_budget_and_cancel():
+    trace = _trace(6, seed=3)
+    betas = [inputs.geometric_betas(j["n_T"], 0.4, 2.0) for j in trace]
+    fps = [B.job_footprint(j["L"], b, j["R"]) for j, b in zip(trace, betas)]
+    budget = max(fps) + min(fps)
+    srv = B.Server(hbm_budget_bytes=budget, quantum_sweeps=5)
+    ids = [srv.submit(j["L"], inputs.couplings(j["L"], j["R"], j["seed"]), b, j["seed"], j["sweeps"], j["swap_every"])
+           for j, b in zip(trace, betas)]
+    srv.cancel(ids[-1])                               # cancel while queued
+    assert srv.status(ids[-1])[0] == B.JOB_CANCELLED
+    running_cancelled = False
+    for _ in range(1000):
+        running, queued, _ = srv.step()
+        st = srv.stats()
+        assert st["hbm_used"] <= budget
+        if not running_cancelled and srv.status(ids[0])[0] == B.JOB_RUNNING and srv.status(ids[0])[1] < trace[0]["sweeps"]:
+            srv.cancel(ids[0])                        # cancel while running
+            running_cancelled = True
+        if running == 0 and queued == 0:
+            break
+    assert srv.stats()["hbm_used"] == 0
+    for jid, j in zip(ids[1:-1], trace[1:-1]):
+        assert srv.status(jid)[0] == B.JOB_DONE
+        E, q = srv.result(jid)
+        alone = _make(j["L"], j["R"], j["n_T"], j["seed"])
+        alone.sweep(j["sweeps"], j["swap_every"])
+        E2, q2 = alone.observables()
+        assert np.array_equal(E, E2) and np.array_equal(q, q2)
+    with pytest.raises(B.EAError):
+        srv.result(ids[-1])
+    srv.close()
+
+
+def test_server_rejects_job_larger_than_budget():
+    srv = B.Server(hbm_budget_bytes=4096, quantum_sweeps=5)
+    with pytest.raises(B.EAError):
+        srv.submit(8, inputs.couplings(8, 2, 1), inputs.geometric_betas(8, 0.5, 2.0), 1, 10, 1)
+    srv.close()
