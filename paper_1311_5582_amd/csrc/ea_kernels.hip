@@ -208,13 +208,106 @@ __device__ __forceinline__ uint32_t amsc4_decide(uint32_t X, const uint32_t *row
     return F;
 }
 
+__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);   // truth table of majority(a, b, c)
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_src(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+
+// P += shifted copy of P (NQ planes in, carry grows the top plane).
+template <int NQ, int CTRL, int ROW_MASK>
+__device__ __forceinline__ void dpp_add_planes(uint32_t (&P)[14])
+{
+    uint32_t Q[NQ];
+#pragma unroll
+    for (int p = 0; p < NQ; ++p) Q[p] = dpp_src<CTRL, ROW_MASK>(P[p]);
+    uint32_t c = P[0] & Q[0];
+    P[0] ^= Q[0];
+#pragma unroll
+    for (int p = 1; p < NQ; ++p) {
+        const uint32_t sum = xor3(P[p], Q[p], c);
+        c = maj3(P[p], Q[p], c);
+        P[p] = sum;
+    }
+    P[NQ] = c;   // planes above NQ are zero before this step
+}
+
+// P += s0 + 2 s1 + 4 s2 per bit position (a per-slot count of 0..7), NP planes.
+__device__ __forceinline__ void planes_add3(uint32_t (&P)[8], uint32_t s0, uint32_t s1, uint32_t s2, int np)
+{
+    uint32_t carry = P[0] & s0;
+    P[0] ^= s0;
+    const uint32_t n1 = xor3(P[1], s1, carry);
+    carry = maj3(P[1], s1, carry);
+    P[1] = n1;
+    const uint32_t n2 = xor3(P[2], s2, carry);
+    carry = maj3(P[2], s2, carry);
+    P[2] = n2;
+#pragma unroll
+    for (int p = 3; p < 8; ++p) {
+        if (p < np) {
+            const uint32_t tt = P[p] & carry;
+            P[p] ^= carry;
+            carry = tt;
+        }
+    }
+}
+
+// Wave-sum NP plane counters (DPP) and add slot b's total into U[slot0 + b]
+// for the slots of one word (bit position b * STR).
+template <int NP, int STR>
+__device__ __forceinline__ void reduce_planes_add(uint32_t (&P)[14], int nslots, int *U)
+{
+    dpp_add_planes<NP + 0, 0x111, 0xF>(P);   // row_shr:1
+    dpp_add_planes<NP + 1, 0x112, 0xF>(P);   // row_shr:2
+    dpp_add_planes<NP + 2, 0x114, 0xF>(P);   // row_shr:4
+    dpp_add_planes<NP + 3, 0x118, 0xF>(P);   // row_shr:8
+    dpp_add_planes<NP + 4, 0x142, 0xA>(P);   // row_bcast:15 into rows 1, 3
+    dpp_add_planes<NP + 5, 0x143, 0xC>(P);   // row_bcast:31 into rows 2, 3
+    const int lane = threadIdx.x & 63;
+    const int shift = (lane < nslots ? lane : 0) * STR;
+    int cnt = 0;
+#pragma unroll
+    for (int p = 0; p < NP + 6; ++p) {
+        const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)P[p], 63);
+        cnt += (int)((w >> shift) & 1u) << p;
+    }
+    if (lane < nslots && cnt) atomicAdd(&U[lane], cnt);
+}
+
+template <int STR>
+__device__ __forceinline__ void reduce_planes8_add(const uint32_t (&P8)[8], int np, int nslots, int *U)
+{
+    uint32_t P[14];
+#pragma unroll
+    for (int p = 0; p < 14; ++p) P[p] = p < 8 ? P8[p] : 0u;
+    switch (np) {
+        case 2: reduce_planes_add<2, STR>(P, nslots, U); break;
+        case 3: reduce_planes_add<3, STR>(P, nslots, U); break;
+        case 4: reduce_planes_add<4, STR>(P, nslots, U); break;
+        case 5: reduce_planes_add<5, STR>(P, nslots, U); break;
+        case 6: reduce_planes_add<6, STR>(P, nslots, U); break;
+        case 7: reduce_planes_add<7, STR>(P, nslots, U); break;
+        default: reduce_planes_add<8, STR>(P, nslots, U); break;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Metropolis update of one site for the `gw` resident words (word index g0..).
 // ---------------------------------------------------------------------------
-template <int LAYOUT>
+// With ACC (CAMSC, even L, last colour class of a swap sweep) the six bond
+// bits of the site after the update are added into the per-lane plane counters
+// of its word: on a bipartite lattice every bond has exactly one endpoint in
+// that class, so these sums are the slots' unsatisfied-bond counts U.
+template <int LAYOUT, bool ACC = false>
 __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int N, int gw, int g0, int n_T,
                                             uint32_t t, uint32_t r, uint32_t c3base, uint32_t k0, uint32_t k1,
-                                            uint32_t segw)
+                                            uint32_t segw, uint32_t (*P)[8] = nullptr, int np = 0)
 {
     constexpr uint32_t M = 0x11111111u;
     const uint32_t j6 = sm.j6[nb.i];
@@ -266,7 +359,16 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
                 case 2: F = camsc_decide<2>(X, rows, nb.i, c); break;
                 default: F = camsc_decide<1>(X, rows, nb.i, c); break;
             }
-            sw[nb.i] = S ^ ((F | always) & valid);
+            const uint32_t flip = (F | always) & valid;
+            sw[nb.i] = S ^ flip;
+            if (ACC) {
+                const uint32_t a0 = e0 ^ flip, a1 = e1 ^ flip, a2 = e2 ^ flip;
+                const uint32_t a3 = e3 ^ flip, a4 = e4 ^ flip, a5 = e5 ^ flip;
+                const uint32_t s1 = xor3(a0, a1, a2), c1 = maj3(a0, a1, a2);
+                const uint32_t s2 = xor3(a3, a4, a5), c2 = maj3(a3, a4, a5);
+                const uint32_t b0 = s1 ^ s2, k = s1 & s2;
+                planes_add3(*P, b0, xor3(c1, c2, k), maj3(c1, c2, k), np);
+            }
         } else {
             // AMSC4: 4-bit segments throughout; 2E+S is formed for all slots at once.
             const uint32_t E = e0 + e1 + e2 + e3 + e4 + e5;
@@ -295,35 +397,6 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
 // lane 63 and lane b assembles slot b's count, so the whole reduction is
 // vector work plus one LDS atomic per wave.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c)
-{
-    return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);   // truth table of majority(a, b, c)
-}
-
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ uint32_t dpp_src(uint32_t v)
-{
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, false);
-}
-
-// P += shifted copy of P (NQ planes in, carry grows the top plane).
-template <int NQ, int CTRL, int ROW_MASK>
-__device__ __forceinline__ void dpp_add_planes(uint32_t (&P)[14])
-{
-    uint32_t Q[NQ];
-#pragma unroll
-    for (int p = 0; p < NQ; ++p) Q[p] = dpp_src<CTRL, ROW_MASK>(P[p]);
-    uint32_t c = P[0] & Q[0];
-    P[0] ^= Q[0];
-#pragma unroll
-    for (int p = 1; p < NQ; ++p) {
-        const uint32_t sum = xor3(P[p], Q[p], c);
-        c = maj3(P[p], Q[p], c);
-        P[p] = sum;
-    }
-    P[NQ] = c;   // planes above NQ are zero before this step
-}
-
 template <int LAYOUT, int NP>
 __device__ void count_unsat_word_np(const uint32_t *words, const uint8_t *j6, int N, int L, float invL, int slot0,
                                     int n_T, int *U)
@@ -355,23 +428,7 @@ __device__ void count_unsat_word_np(const uint32_t *words, const uint8_t *j6, in
             carry = tt;
         }
     }
-    // wave sum into lane 63
-    dpp_add_planes<NP + 0, 0x111, 0xF>(P);   // row_shr:1
-    dpp_add_planes<NP + 1, 0x112, 0xF>(P);   // row_shr:2
-    dpp_add_planes<NP + 2, 0x114, 0xF>(P);   // row_shr:4
-    dpp_add_planes<NP + 3, 0x118, 0xF>(P);   // row_shr:8
-    dpp_add_planes<NP + 4, 0x142, 0xA>(P);   // row_bcast:15 into rows 1, 3
-    dpp_add_planes<NP + 5, 0x143, 0xC>(P);   // row_bcast:31 into rows 2, 3
-    const int lane = threadIdx.x & 63;
-    const int nslots = min(SPW, n_T - slot0);
-    const int shift = (lane < nslots ? lane : 0) * STR;
-    int cnt = 0;
-#pragma unroll
-    for (int p = 0; p < NP + 6; ++p) {
-        const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)P[p], 63);
-        cnt += (int)((w >> shift) & 1u) << p;
-    }
-    if (lane < nslots && cnt) atomicAdd(&U[slot0 + lane], cnt);
+    reduce_planes_add<NP, STR>(P, min(SPW, n_T - slot0), U + slot0);
 }
 
 // Bit planes needed so that no lane's per-slot count overflows.
@@ -379,6 +436,15 @@ __device__ __forceinline__ int planes_for(int N, int nthr)
 {
     const int per_lane = 3 * ((N + nthr - 1) / nthr);
     int np = 2;
+    while ((1 << np) <= per_lane) ++np;
+    return np;
+}
+
+// Planes for per-lane sums of six bond bits over the sites of one colour class.
+__device__ __forceinline__ int planes_for_class(int n_sites, int nthr)
+{
+    const int per_lane = 6 * ((n_sites + nthr - 1) / nthr);
+    int np = 3;
     while ((1 << np) <= per_lane) ++np;
     return np;
 }
@@ -470,6 +536,10 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
         const int se = jd.swap_every;
         const int np = planes_for(N, nthr);
         const int half = N >> 1;
+        // CAMSC on a bipartite lattice with every word resident: the slot
+        // energies come out of the last colour class of the swap sweep
+        const int np_b = planes_for_class(half, nthr);
+        const bool fused_energy = LAYOUT == 0 && even && NW == 1 && np_b <= 8;
         while (remaining > 0) {
             int chunk = remaining;
             bool swap_now = false;
@@ -480,6 +550,9 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                     swap_now = true;
                 }
             }
+            uint32_t P[1][8];
+#pragma unroll
+            for (int p = 0; p < 8; ++p) P[0][p] = 0u;
             for (int g0 = 0; g0 < NW; g0 += WR) {
                 const int gw = min(WR, NW - g0);
                 if (n_groups > 1) {
@@ -489,12 +562,20 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                 for (int s = 0; s < chunk; ++s) {
                     const uint32_t ts = t + (uint32_t)s;
                     if (even) {
-                        for (int c = 0; c < 2; ++c) {
+                        for (int j = tid; j < half; j += nthr)
+                            update_site<LAYOUT>(sm, checker_site(j, 0, L, invH, invL), N, gw, g0, n_T, ts, r, c3flip,
+                                                k0, k1, segw);
+                        __syncthreads();
+                        if (fused_energy && swap_now && s == chunk - 1) {
                             for (int j = tid; j < half; j += nthr)
-                                update_site<LAYOUT>(sm, checker_site(j, c, L, invH, invL), N, gw, g0, n_T, ts, r,
+                                update_site<LAYOUT, true>(sm, checker_site(j, 1, L, invH, invL), N, gw, g0, n_T, ts, r,
+                                                          c3flip, k0, k1, segw, P, np_b);
+                        } else {
+                            for (int j = tid; j < half; j += nthr)
+                                update_site<LAYOUT>(sm, checker_site(j, 1, L, invH, invL), N, gw, g0, n_T, ts, r,
                                                     c3flip, k0, k1, segw);
-                            __syncthreads();
                         }
+                        __syncthreads();
                     } else {
                         for (int c = 0; c < jd.n_classes; ++c) {
                             const int end = jd.class_off[c + 1];
@@ -506,9 +587,13 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                     }
                 }
                 if (swap_now) {
-                    for (int w = 0; w < gw; ++w)
-                        count_unsat_word<LAYOUT>(sm.spin + (size_t)w * N, sm.j6, N, L, invL, (g0 + w) * SPW, n_T, np,
-                                                 sm.U);
+                    if (fused_energy) {
+                        reduce_planes8_add<1>(P[0], np_b, min(SPW, n_T), sm.U);
+                    } else {
+                        for (int w = 0; w < gw; ++w)
+                            count_unsat_word<LAYOUT>(sm.spin + (size_t)w * N, sm.j6, N, L, invL, (g0 + w) * SPW, n_T,
+                                                     np, sm.U);
+                    }
                 }
                 if (n_groups > 1) {
                     __syncthreads();
@@ -524,10 +609,11 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                 __syncthreads();   // slot energies U and swap draws are in
                 // Bit j of mask[k]: would pair k swap if the configuration that
                 // sat at position j before the pass had been carried up to k?
+                const int u_mine = lane < n_T ? sm.U[sm.sot[lane]] : 0;
                 for (int k = wave; k < pairs; k += nwaves) {
                     bool acc = false;
                     if (lane <= k) {
-                        const int d = sm.U[sm.sot[lane]] - sm.U[sm.sot[k + 1]];
+                        const int d = u_mine - sm.U[sm.sot[k + 1]];
                         const int sg = sm.ssgn[k];
                         acc = (sg == 0) || (d == 0) || ((sg > 0) == (d > 0));
                         if (!acc) {
@@ -541,22 +627,41 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                 }
                 __syncthreads();
                 if (wave == 0) {
-                    // walk the pairs in ascending order; lane k learns which old
-                    // position ends at temperature index k
+                    // Walk the pairs in ascending order on the scalar unit,
+                    // keeping only the set of rejected pairs; masks are read
+                    // eight at a time.  The configuration carried upwards
+                    // restarts at k + 1 after a rejection at k.
                     const uint64_t mine = lane < pairs ? sm.mask[lane] : 0ull;
                     const uint32_t mlo = (uint32_t)mine, mhi = (uint32_t)(mine >> 32);
                     int cj = 0;
-                    int src = 0;
-                    for (int k = 0; k < pairs; ++k) {
-                        // readlane returns int: zero-extend both halves
-                        const uint64_t mk = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mhi, k) << 32) |
-                                            (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mlo, k);
-                        if ((mk >> cj) & 1ull) {
-                            if (lane == k) src = k + 1;
-                        } else {
-                            if (lane == k) src = cj;
-                            cj = k + 1;
+                    uint64_t rej = 0;
+                    for (int k0b = 0; k0b < pairs; k0b += 8) {
+                        uint64_t mk[8];
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            const int kk = min(k0b + i, 63);
+                            // readlane returns int: zero-extend both halves
+                            mk[i] = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mhi, kk) << 32) |
+                                    (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mlo, kk);
                         }
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) {
+                            const int k = k0b + i;
+                            if (k < pairs && !((mk[i] >> cj) & 1ull)) {
+                                rej |= 1ull << k;
+                                cj = k + 1;
+                            }
+                        }
+                    }
+                    // lane k: pair k accepted -> the configuration from position k+1
+                    // comes down; rejected -> the carried one stays (it started at the
+                    // last restart point at or below k)
+                    int src;
+                    if (lane < pairs && !((rej >> lane) & 1ull)) {
+                        src = lane + 1;
+                    } else {
+                        const uint64_t starts = ((rej << 1) | 1ull) & (lane >= 63 ? ~0ull : ((2ull << lane) - 1ull));
+                        src = 63 - __clzll((long long)starts);
                     }
                     if (lane == pairs) src = cj;
                     const int newslot = lane < n_T ? sm.sot[src] : 0;
