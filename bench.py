@@ -152,6 +152,8 @@ def main():
     ap.add_argument("--workload", default="L16_R64")
     ap.add_argument("--layout", default="camsc", choices=["camsc", "amsc4"])
     ap.add_argument("--block-threads", type=int, default=0)
+    ap.add_argument("--no-split", action="store_true",
+                    help="one workgroup per ladder even when the job has fewer ladders than compute units")
     ap.add_argument("--swap-every", type=int, default=-1, help="override the workload's PT interval")
     ap.add_argument("--cpu-sweeps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -183,7 +185,9 @@ def main():
     stream = torch.cuda.Stream()
     J = inputs.couplings(L, R, cfg["seed"])
     betas = inputs.geometric_betas(n_T, cfg["t_min"], cfg["t_max"])
-    sim = B.Sim(L, J, betas, cfg["seed"], layout=args.layout, block_threads=args.block_threads, stream=stream)
+    sim = B.Sim(L, J, betas, cfg["seed"], layout=args.layout, block_threads=args.block_threads, stream=stream,
+                split=not args.no_split)
+    launch = sim.info()
     S, se = args.sweeps_per_step, (cfg["swap_every"] if args.swap_every < 0 else args.swap_every)
 
     def step(events=None):
@@ -236,6 +240,7 @@ def main():
         "config": {"workload": args.workload, "L": L, "spins": L ** 3, "realizations": R, "copies": 2,
                    "temperatures": n_T, "T_range": [cfg["t_min"], cfg["t_max"]], "sweeps_per_step": S,
                    "swap_every": se, "layout": args.layout, "measurement_per_step": True,
+                   "block_threads": launch["block_threads"], "workgroups_per_ladder": launch["split_parts"],
                    "kernel_ps_per_flip": round(avg_launch_s / flips_per_step * 1e12, 4),
                    "paper_ps_per_flip_gtx580": 33.5},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",

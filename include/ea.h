@@ -77,7 +77,10 @@ typedef struct ea_options {
                             of 64 in [64, 1024]                                        */
     int words_resident;  /* spin words per site held in LDS at once: 0 = as many as fit;
                             fewer makes the kernel stage word groups through HBM       */
-    int reserved_;
+    int split;           /* 0 = auto: a job with fewer ladders than CUs (CAMSC, <= 32
+                            temperatures, even L) spreads each ladder's slot groups over 2
+                            or 4 co-resident workgroups when each keeps >= 2048 site-groups
+                            of work per sweep; 1 = never; 2 = whenever possible           */
     void *stream;        /* hipStream_t to run on; NULL = the default stream            */
     /* optional device allocator (e.g. backed by a framework's caching allocator);
        both NULL = hipMalloc / hipFree.  dev_alloc returns NULL on failure.            */
@@ -220,6 +223,9 @@ int ea_swap_acceptance(ea_sim *sim, uint64_t *accepted);
 
 /* Shape queries. */
 int ea_get_dims(const ea_sim *sim, int *L, int *n_T, int *n_realizations, int *layout);
+/* Launch plan of a lone ea_sweep: workgroup size, spin words resident in LDS,
+ * workgroups per ladder (1, or 2/4 when split), dynamic LDS bytes. */
+int ea_sim_info(const ea_sim *sim, int *block_threads, int *words_resident, int *split_parts, size_t *lds_bytes);
 
 /* Release the handle and its device memory (NULL is a no-op). */
 void ea_destroy(ea_sim *sim);

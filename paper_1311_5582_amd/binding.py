@@ -29,7 +29,7 @@ _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 class Options(ctypes.Structure):
     _fields_ = [
         ("layout", ctypes.c_int), ("block_threads", ctypes.c_int),
-        ("words_resident", ctypes.c_int), ("reserved_", ctypes.c_int),
+        ("words_resident", ctypes.c_int), ("split", ctypes.c_int),
         ("stream", ctypes.c_void_p),
         ("dev_alloc", _ALLOC_FN), ("dev_free", _FREE_FN), ("alloc_ctx", ctypes.c_void_p),
     ]
@@ -106,6 +106,7 @@ def lib():
             "ea_job_footprint": (ctypes.c_int, [ctypes.c_int, f64p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                 ctypes.POINTER(ctypes.c_size_t)]),
             "ea_sim_footprint": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_size_t)]),
+            "ea_sim_info": (ctypes.c_int, [P, i32p, i32p, i32p, ctypes.POINTER(ctypes.c_size_t)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -180,7 +181,7 @@ class Sim:
     """One job: R realizations x 2 copies x n_T temperature slots on the GPU."""
 
     def __init__(self, L, couplings, betas, seed, layout="camsc", block_threads=0, words_resident=0,
-                 stream=None, torch_memory=True):
+                 stream=None, torch_memory=True, split=True):
         L = int(L)
         J = np.ascontiguousarray(couplings, dtype=np.int8)
         if J.ndim != 3 or J.shape[1:] != (L ** 3, 3):
@@ -191,6 +192,8 @@ class Sim:
         opt.layout = LAYOUTS[layout] if isinstance(layout, str) else int(layout)
         opt.block_threads = int(block_threads)
         opt.words_resident = int(words_resident)
+        # True/"auto": library choice; False: one workgroup per ladder; "always": split when possible
+        opt.split = {True: 0, "auto": 0, False: 1, "never": 1, "always": 2}[split]
         self._alloc = None
         torch = _torch_gpu() if (torch_memory or stream is not None) else None
         if stream is not None:
@@ -243,6 +246,12 @@ class Sim:
         s = np.ascontiguousarray(spins, dtype=np.int8)
         p = np.ascontiguousarray(temp_of_slot, dtype=np.int32)
         check(lib().ea_set_state(self._h, _p(s, ctypes.c_int8), _p(p, ctypes.c_int32), int(sweeps_done)))
+
+    def info(self):
+        bt, wr, parts = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        lds = ctypes.c_size_t()
+        check(lib().ea_sim_info(self._h, ctypes.byref(bt), ctypes.byref(wr), ctypes.byref(parts), ctypes.byref(lds)))
+        return dict(block_threads=bt.value, words_resident=wr.value, split_parts=parts.value, lds_bytes=int(lds.value))
 
     def footprint(self):
         b = ctypes.c_size_t()

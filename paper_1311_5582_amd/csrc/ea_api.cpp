@@ -156,6 +156,7 @@ int plan_launch(int N, int NW, const ea_options &opt, int *block_threads, int *w
     int wr_max = (int)((kLdsBudget - fixed) / ((size_t)N * 4));
     int wr = std::min(NW, wr_max);
     if (opt.words_resident < 0) return fail(EA_EINVAL, "words_resident=%d < 0", opt.words_resident);
+    if (opt.split < 0 || opt.split > 2) return fail(EA_EINVAL, "split=%d is not 0, 1 or 2", opt.split);
     if (opt.words_resident > 0) {
         if (opt.words_resident > wr_max)
             return fail(EA_EINVAL, "words_resident=%d exceeds the %d words that fit in LDS", opt.words_resident, wr_max);
@@ -230,7 +231,42 @@ size_t job_footprint_bytes(int L, int n_T, int R, int layout, int64_t swap_entri
     const size_t NW = (size_t)(n_T + slots_per_word(layout) - 1) / slots_per_word(layout);
     return a(ladders * NW * N * 4) + a((size_t)R * N) + a(ladders * kMaxTemps * 4) + a((size_t)n_T * kThrCols * 4) +
            a((size_t)swap_entries * 4) + 3 * a(kMaxTemps * 4) + a(N * 4) + a(2 * 4) + a(ladders * kMaxTemps * 4) +
-           a(ladders * 4) + a(sizeof(JobDesc));
+           a(ladders * 4) + a(sizeof(JobDesc)) + a(ladders * 2 * kMaxTemps * 8) + a(4);
+}
+
+// Workgroups per ladder for a lone launch: split a ladder's slot groups over
+// 2 or 4 co-resident workgroups when the job alone leaves CUs idle.
+static int choose_split(const ea_sim *s, int split_opt)
+{
+    if (split_opt == 1 || s->layout != EA_LAYOUT_CAMSC || s->NW != 1 || (s->L & 1)) return 1;
+    const int ladders = 2 * s->R;
+    const int ngr = (s->n_T + 3) >> 2;
+    const int per_lane = 6 * ((s->N / 2 + s->block_threads - 1) / s->block_threads);
+    if (per_lane > 255) return 1;   // class energy sums must fit 8 bit planes
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess) return 1;
+    int coop = 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, s->device) != hipSuccess || !coop) return 1;
+    for (int parts : {4, 2}) {
+        if (ngr % parts != 0 || ladders * parts > cus) continue;
+        // a small lattice is latency-bound: the exchange costs more than the split saves
+        if (split_opt == 0 && (int64_t)s->N * (ngr / parts) < 2048) continue;
+        const int blocks = (ladders + 7) / 8 * 8 * parts;
+        const int per_cu = sweep_split_max_blocks_per_cu(parts, s->block_threads, s->lds);
+        if (per_cu < 1 || (int64_t)per_cu * cus < blocks) continue;
+        return parts;
+    }
+    return 1;
+}
+
+int check_split_error(ea_sim *s)
+{
+    if (s->split_parts <= 1) return EA_OK;
+    uint32_t err = 0;
+    EA_HIP(hipMemcpyAsync(&err, s->h.error, sizeof err, hipMemcpyDeviceToHost, s->stream));
+    EA_HIP(hipStreamSynchronize(s->stream));
+    if (err) return fail(EA_EDEVICE, "a split-ladder exchange timed out; the job's state is not valid");
+    return EA_OK;
 }
 
 }  // namespace ea
@@ -361,6 +397,10 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
     h.sweep_ctr = s->d_counters;
     std::vector<uint32_t> acc((size_t)ladders * kMaxTemps, 0u);
     if ((rc = upload(s, acc, &h.swap_acc))) return bail(rc);
+    std::vector<uint64_t> xchg((size_t)ladders * 2 * kMaxTemps, 0);
+    std::vector<uint32_t> err(1, 0u);
+    if ((rc = upload(s, xchg, &h.xchg)) || (rc = upload(s, err, &h.error)))
+        return bail(rc);
     std::vector<uint32_t> units(ladders);
     for (int l = 0; l < ladders; ++l) units[l] = (uint32_t)l;   // job 0 of a lone launch
     if ((rc = upload(s, units, &s->d_units))) return bail(rc);
@@ -375,6 +415,7 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
     s->swap_total = (int64_t)sthr.size();
     plan_optional_lds(N, wr, bt, L % 2 != 0, s->swap_total, &h.swap_lds, &h.sites_lds);
     s->lds = lds_layout(N, wr, h.swap_lds, h.sites_lds).total;
+    s->split_parts = choose_split(s, opt.split);
     std::vector<JobDesc> hv(1, h);
     if ((rc = upload(s, hv, &s->d_job))) return bail(rc);
     he = launch_init_spins(s->d_job, h, s->layout, s->stream);
@@ -393,6 +434,16 @@ int ea_job_footprint(int L, const double *betas, int n_T, int n_realizations, in
     int64_t total = 0;
     if (int rc = build_swap_tables(betas, n_T, L * L * L, nullptr, nullptr, nullptr, nullptr, &total)) return rc;
     *bytes = job_footprint_bytes(L, n_T, n_realizations, layout, total);
+    return EA_OK;
+}
+
+int ea_sim_info(const ea_sim *s, int *block_threads, int *words_resident, int *split_parts, size_t *lds_bytes)
+{
+    if (!s) return fail(EA_EINVAL, "ea_sim_info: NULL handle");
+    if (block_threads) *block_threads = s->block_threads;
+    if (words_resident) *words_resident = s->words_resident;
+    if (split_parts) *split_parts = s->split_parts;
+    if (lds_bytes) *lds_bytes = s->lds;
     return EA_OK;
 }
 
@@ -440,7 +491,7 @@ int ea_observables(ea_sim *s, int32_t *energy, int32_t *overlap)
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     (void)hipFree(d);
     if (e != hipSuccess) return fail(EA_EDEVICE, "observables failed: %s", hipGetErrorString(e));
-    return EA_OK;
+    return check_split_error(s);
 }
 
 int ea_state(ea_sim *s, int8_t *spins, int32_t *temp_of_slot, int64_t *sweeps_done)
@@ -466,6 +517,7 @@ int ea_state(ea_sim *s, int8_t *spins, int32_t *temp_of_slot, int64_t *sweeps_do
         for (int l = 0; l < ladders; ++l)
             for (int k = 0; k < s->n_T; ++k) temp_of_slot[(size_t)l * s->n_T + k] = perm[(size_t)l * kMaxTemps + k];
     }
+    if (int rc = check_split_error(s)) return rc;
     if (sweeps_done) {
         uint32_t t = 0;
         EA_HIP(hipMemcpyAsync(&t, s->d_counters, sizeof t, hipMemcpyDeviceToHost, s->stream));
@@ -502,6 +554,10 @@ int ea_set_state(ea_sim *s, const int8_t *spins, const int32_t *temp_of_slot, in
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->h.temp_of_slot, perm.data(), perm.size() * 4, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s->d_counters, &t, sizeof t, hipMemcpyHostToDevice, s->stream);
+    // exchange words carry sweep tags: a rewound counter must not meet stale ones
+    if (e == hipSuccess) e = hipMemsetAsync(s->h.xchg, 0, (size_t)ladders * 2 * kMaxTemps * sizeof(uint64_t), s->stream);
+    // a valid state clears an earlier exchange timeout
+    if (e == hipSuccess) e = hipMemsetAsync(s->h.error, 0, sizeof(uint32_t), s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     (void)hipFree(d);
     if (e != hipSuccess) return fail(EA_EDEVICE, "state upload failed: %s", hipGetErrorString(e));

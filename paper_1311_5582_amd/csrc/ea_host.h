@@ -63,4 +63,9 @@ struct ea_sim {
     int64_t swap_total = 0;           // entries in the swap tables
     size_t lds = 0;                   // dynamic LDS bytes of this job's sweep workgroups
     size_t footprint = 0;             // device bytes owned by this job
+    int split_parts = 1;              // workgroups per ladder in a lone launch (1, 2 or 4)
 };
+
+namespace ea {
+int check_split_error(ea_sim *s);
+}

@@ -59,6 +59,8 @@ struct JobDesc {
     float invL, invH;         // 1/L and 1/(L/2), exact quotients for indices < 2^15
     uint32_t seg_bits;        // 4: width of a 2E+S segment (a runtime value on purpose: a
                               // constant width lets the compiler split v_bfe_u32 into shift+mask)
+    uint64_t *xchg;           // [ladders][2][kMaxTemps] (sweep index + 1) << 32 | slot energy, split workgroups
+    uint32_t *error;          // set to non-zero if a split exchange timed out
 };
 
 // Dynamic LDS carve-up of the sweep kernel, one definition for host and
@@ -110,6 +112,10 @@ hipError_t launch_init_spins(const JobDesc *d_job, const JobDesc &h_job, int lay
 hipError_t launch_sweep(const JobDesc *d_jobs, int n_jobs, const uint32_t *d_units, int n_units,
                         uint32_t *d_queue, int layout, int block_threads, size_t lds, int grid,
                         hipStream_t s);
+// Split launch: `parts` co-resident workgroups per ladder (cooperative launch).
+hipError_t launch_sweep_split(const JobDesc *d_job, int ladders, int parts, int block_threads, size_t lds,
+                              uint32_t *d_queue, hipStream_t s);
+int sweep_split_max_blocks_per_cu(int parts, int block_threads, size_t lds);
 hipError_t launch_observables(const JobDesc *d_job, const JobDesc &h_job, int layout, int32_t *d_energy,
                               int32_t *d_overlap, hipStream_t s);
 hipError_t launch_unpack(const JobDesc *d_job, const JobDesc &h_job, int layout, int8_t *d_spins, hipStream_t s);

@@ -181,7 +181,7 @@ __device__ __forceinline__ uint32_t camsc_decide(const uint32_t X[4], const uint
     uint32_t F = 0;
 #pragma unroll
     for (int g = NG - 1; g >= 0; --g) {
-        const U4 rr = philox10(site, c.t, c.r, c.c3 | (uint32_t)g, c.k0, c.k1);
+        const U4 rr = philox10(site, c.t, c.r, c.c3 + (uint32_t)g, c.k0, c.k1);
         const uint32_t *row = rows + 4 * g * kThrCols;
         F = (F << 1) | (rr.w < row[3 * kThrCols + field4(X[3], 4 * g, c.w)] ? 1u : 0u);
         F = (F << 1) | (rr.z < row[2 * kThrCols + field4(X[2], 4 * g, c.w)] ? 1u : 0u);
@@ -198,7 +198,7 @@ __device__ __forceinline__ uint32_t amsc4_decide(uint32_t X, const uint32_t *row
     uint32_t F = 0;
 #pragma unroll
     for (int g = NG - 1; g >= 0; --g) {
-        const U4 rr = philox10(site, c.t, c.r, c.c3 | (uint32_t)g, c.k0, c.k1);
+        const U4 rr = philox10(site, c.t, c.r, c.c3 + (uint32_t)g, c.k0, c.k1);
         const uint32_t *row = rows + 4 * g * kThrCols;
         F = (F << 4) | (rr.w < row[3 * kThrCols + field4(X, 16 * g + 12, c.w)] ? 1u : 0u);
         F = (F << 4) | (rr.z < row[2 * kThrCols + field4(X, 16 * g + 8, c.w)] ? 1u : 0u);
@@ -261,7 +261,7 @@ __device__ __forceinline__ void planes_add3(uint32_t (&P)[8], uint32_t s0, uint3
 // Wave-sum NP plane counters (DPP) and add slot b's total into U[slot0 + b]
 // for the slots of one word (bit position b * STR).
 template <int NP, int STR>
-__device__ __forceinline__ void reduce_planes_add(uint32_t (&P)[14], int nslots, int *U)
+__device__ __forceinline__ void reduce_planes_add(uint32_t (&P)[14], int nslots, int *U, int first = 0)
 {
     dpp_add_planes<NP + 0, 0x111, 0xF>(P);   // row_shr:1
     dpp_add_planes<NP + 1, 0x112, 0xF>(P);   // row_shr:2
@@ -270,30 +270,31 @@ __device__ __forceinline__ void reduce_planes_add(uint32_t (&P)[14], int nslots,
     dpp_add_planes<NP + 4, 0x142, 0xA>(P);   // row_bcast:15 into rows 1, 3
     dpp_add_planes<NP + 5, 0x143, 0xC>(P);   // row_bcast:31 into rows 2, 3
     const int lane = threadIdx.x & 63;
-    const int shift = (lane < nslots ? lane : 0) * STR;
+    const int shift = (lane < nslots ? first + lane : 0) * STR;
     int cnt = 0;
 #pragma unroll
     for (int p = 0; p < NP + 6; ++p) {
         const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)P[p], 63);
         cnt += (int)((w >> shift) & 1u) << p;
     }
-    if (lane < nslots && cnt) atomicAdd(&U[lane], cnt);
+    if (lane < nslots && cnt) atomicAdd(&U[first + lane], cnt);
 }
 
+// slots first .. first + nslots - 1 of the word (bit positions (first + b) * STR)
 template <int STR>
-__device__ __forceinline__ void reduce_planes8_add(const uint32_t (&P8)[8], int np, int nslots, int *U)
+__device__ __forceinline__ void reduce_planes8_add(const uint32_t (&P8)[8], int np, int nslots, int *U, int first = 0)
 {
     uint32_t P[14];
 #pragma unroll
     for (int p = 0; p < 14; ++p) P[p] = p < 8 ? P8[p] : 0u;
     switch (np) {
-        case 2: reduce_planes_add<2, STR>(P, nslots, U); break;
-        case 3: reduce_planes_add<3, STR>(P, nslots, U); break;
-        case 4: reduce_planes_add<4, STR>(P, nslots, U); break;
-        case 5: reduce_planes_add<5, STR>(P, nslots, U); break;
-        case 6: reduce_planes_add<6, STR>(P, nslots, U); break;
-        case 7: reduce_planes_add<7, STR>(P, nslots, U); break;
-        default: reduce_planes_add<8, STR>(P, nslots, U); break;
+        case 2: reduce_planes_add<2, STR>(P, nslots, U, first); break;
+        case 3: reduce_planes_add<3, STR>(P, nslots, U, first); break;
+        case 4: reduce_planes_add<4, STR>(P, nslots, U, first); break;
+        case 5: reduce_planes_add<5, STR>(P, nslots, U, first); break;
+        case 6: reduce_planes_add<6, STR>(P, nslots, U, first); break;
+        case 7: reduce_planes_add<7, STR>(P, nslots, U, first); break;
+        default: reduce_planes_add<8, STR>(P, nslots, U, first); break;
     }
 }
 
@@ -304,10 +305,15 @@ __device__ __forceinline__ void reduce_planes8_add(const uint32_t (&P8)[8], int 
 // bits of the site after the update are added into the per-lane plane counters
 // of its word: on a bipartite lattice every bond has exactly one endpoint in
 // that class, so these sums are the slots' unsatisfied-bond counts U.
-template <int LAYOUT, bool ACC = false>
+//
+// With SPLIT (CAMSC, one word per site) this workgroup owns only the slot
+// groups [gb, gb + ngr_own) of the word; the other groups' bits in its LDS
+// copy are never read for its own decisions (slots do not interact).
+template <int LAYOUT, bool ACC = false, bool SPLIT = false>
 __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int N, int gw, int g0, int n_T,
                                             uint32_t t, uint32_t r, uint32_t c3base, uint32_t k0, uint32_t k1,
-                                            uint32_t segw, uint32_t (*P)[8] = nullptr, int np = 0)
+                                            uint32_t segw, uint32_t (*P)[8] = nullptr, int np = 0, int gb = 0,
+                                            int ngr_own = 0)
 {
     constexpr uint32_t M = 0x11111111u;
     const uint32_t j6 = sm.j6[nb.i];
@@ -344,10 +350,19 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
             }
             const int slot0 = wg * 32;
             const int left = n_T - slot0;
-            const int ngr = left >= 32 ? 8 : (left + 3) >> 2;
-            const uint32_t valid = left >= 32 ? 0xFFFFFFFFu : ((1u << left) - 1u);
+            int ngr = left >= 32 ? 8 : (left + 3) >> 2;
+            uint32_t valid = left >= 32 ? 0xFFFFFFFFu : ((1u << left) - 1u);
             const uint32_t *rows = sm.thr + slot0 * kThrCols;
-            const Ctr c{t, r, c3base | (uint32_t)(wg * 8), k0, k1, segw};
+            Ctr c{t, r, c3base + (uint32_t)(wg * 8), k0, k1, segw};
+            if (SPLIT) {
+                // own groups only: shift them down to group 0, decide, shift the flips back
+#pragma unroll
+                for (int k = 0; k < 4; ++k) X[k] >>= 4 * gb;
+                rows += 4 * gb * kThrCols;
+                c.c3 += (uint32_t)gb;
+                ngr = ngr_own;
+                valid &= (ngr_own >= 8 ? 0xFFFFFFFFu : ((1u << (4 * ngr_own)) - 1u)) << (4 * gb);
+            }
             uint32_t F;
             switch (ngr) {
                 case 8: F = camsc_decide<8>(X, rows, nb.i, c); break;
@@ -359,6 +374,7 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
                 case 2: F = camsc_decide<2>(X, rows, nb.i, c); break;
                 default: F = camsc_decide<1>(X, rows, nb.i, c); break;
             }
+            if (SPLIT) F <<= 4 * gb;
             const uint32_t flip = (F | always) & valid;
             sw[nb.i] = S ^ flip;
             if (ACC) {
@@ -378,7 +394,7 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
             const int left = n_T - slot0;
             const uint32_t valid = left >= 8 ? M : (M & ((1u << (4 * left)) - 1u));
             const uint32_t *rows = sm.thr + slot0 * kThrCols;
-            const Ctr c{t, r, c3base | (uint32_t)(wg * 2), k0, k1, segw};
+            const Ctr c{t, r, c3base + (uint32_t)(wg * 2), k0, k1, segw};
             const uint32_t F = left > 4 ? amsc4_decide<2>(X, rows, nb.i, c) : amsc4_decide<1>(X, rows, nb.i, c);
             sw[nb.i] = S ^ ((F | always) & valid);
         }
@@ -465,14 +481,28 @@ __device__ __forceinline__ void count_unsat_word(const uint32_t *words, const ui
 }
 
 // ---------------------------------------------------------------------------
-// Sweep kernel: persistent workgroups pulling ladders from a queue.
+// Sweep kernel.
+//
+// PARTS = 1: persistent workgroups pulling ladders from a queue.
+// PARTS > 1 (one job, CAMSC, one word per site, even L; cooperative launch so
+// that all workgroups are resident): PARTS workgroups share a ladder, each
+// holding all of its words in LDS but deciding only its own slot groups.  At a
+// swap point they publish their slots' energies through a double-buffered
+// exchange in HBM (64-bit words tagged with the sweep index, so readers need
+// no fence; the wait is bounded and a timeout is reported through an error
+// flag, so a launch always ends), then all run the identical swap pass.  Partners are placed on one XCD
+// (equal blockIdx mod 8) so that the flags stay in one L2.
 // ---------------------------------------------------------------------------
-template <int LAYOUT>
+constexpr uint32_t kSpinLimit = 1u << 20;   // polls of a partner's flag before giving up
+
+template <int LAYOUT, int PARTS>
 __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restrict__ jobs,
                                                           const uint32_t *__restrict__ units, int n_units,
                                                           uint32_t *queue)
 {
     constexpr int SPW = Layout<LAYOUT>::kSlotsPerWord;
+    constexpr bool SPLIT = PARTS > 1;
+    static_assert(!SPLIT || LAYOUT == 0, "split ladders are CAMSC only");
     extern __shared__ __align__(16) uint8_t smem_raw[];
     __shared__ uint32_t s_next;
 
@@ -482,13 +512,24 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
     const int wave = tid >> 6;
     const int nwaves = nthr >> 6;
 
-    for (;;) {
-        if (tid == 0) s_next = atomicAdd(queue, 1u);
-        __syncthreads();
-        const uint32_t u = __builtin_amdgcn_readfirstlane(s_next);
-        __syncthreads();
-        if (u >= (uint32_t)n_units) break;
-        const uint32_t unit = units[u];
+    for (int iter = 0;; ++iter) {
+        uint32_t unit;
+        int part = 0;
+        if (SPLIT) {
+            if (iter > 0) break;
+            const int b = blockIdx.x;
+            part = (b >> 3) % PARTS;
+            const int ladder_b = (b / (8 * PARTS)) * 8 + (b & 7);
+            if (ladder_b >= n_units) break;   // padding block (its partners pad too)
+            unit = (uint32_t)ladder_b;
+        } else {
+            if (tid == 0) s_next = atomicAdd(queue, 1u);
+            __syncthreads();
+            const uint32_t u = __builtin_amdgcn_readfirstlane(s_next);
+            __syncthreads();
+            if (u >= (uint32_t)n_units) break;
+            unit = units[u];
+        }
         const JobDesc &jd = jobs[unit >> 20];
         const int ladder = unit & 0xFFFFF;
         const int N = jd.N, L = jd.L, NW = jd.NW, WR = jd.words_resident, n_T = jd.n_T;
@@ -540,6 +581,11 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
         // energies come out of the last colour class of the swap sweep
         const int np_b = planes_for_class(half, nthr);
         const bool fused_energy = LAYOUT == 0 && even && NW == 1 && np_b <= 8;
+        // slot groups this workgroup decides (all of them unless split)
+        const int ngr_own = SPLIT ? ((n_T + 3) >> 2) / PARTS : 0;
+        const int gb = SPLIT ? part * ngr_own : 0;
+        const int s_lo = SPLIT ? 4 * gb : 0;
+        const int s_hi = SPLIT ? min(n_T, 4 * (gb + ngr_own)) : n_T;
         while (remaining > 0) {
             int chunk = remaining;
             bool swap_now = false;
@@ -563,17 +609,19 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                     const uint32_t ts = t + (uint32_t)s;
                     if (even) {
                         for (int j = tid; j < half; j += nthr)
-                            update_site<LAYOUT>(sm, checker_site(j, 0, L, invH, invL), N, gw, g0, n_T, ts, r, c3flip,
-                                                k0, k1, segw);
+                            update_site<LAYOUT, false, SPLIT>(sm, checker_site(j, 0, L, invH, invL), N, gw, g0, n_T,
+                                                              ts, r, c3flip, k0, k1, segw, nullptr, 0, gb, ngr_own);
                         __syncthreads();
                         if (fused_energy && swap_now && s == chunk - 1) {
                             for (int j = tid; j < half; j += nthr)
-                                update_site<LAYOUT, true>(sm, checker_site(j, 1, L, invH, invL), N, gw, g0, n_T, ts, r,
-                                                          c3flip, k0, k1, segw, P, np_b);
+                                update_site<LAYOUT, true, SPLIT>(sm, checker_site(j, 1, L, invH, invL), N, gw, g0,
+                                                                 n_T, ts, r, c3flip, k0, k1, segw, P, np_b, gb,
+                                                                 ngr_own);
                         } else {
                             for (int j = tid; j < half; j += nthr)
-                                update_site<LAYOUT>(sm, checker_site(j, 1, L, invH, invL), N, gw, g0, n_T, ts, r,
-                                                    c3flip, k0, k1, segw);
+                                update_site<LAYOUT, false, SPLIT>(sm, checker_site(j, 1, L, invH, invL), N, gw, g0,
+                                                                  n_T, ts, r, c3flip, k0, k1, segw, nullptr, 0, gb,
+                                                                  ngr_own);
                         }
                         __syncthreads();
                     } else {
@@ -588,7 +636,7 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                 }
                 if (swap_now) {
                     if (fused_energy) {
-                        reduce_planes8_add<1>(P[0], np_b, min(SPW, n_T), sm.U);
+                        reduce_planes8_add<1>(P[0], np_b, s_hi - s_lo, sm.U, s_lo);
                     } else {
                         for (int w = 0; w < gw; ++w)
                             count_unsat_word<LAYOUT>(sm.spin + (size_t)w * N, sm.j6, N, L, invL, (g0 + w) * SPW, n_T,
@@ -604,6 +652,34 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                 // ---- replica-exchange pass after sweep t + chunk - 1 ----
                 const uint32_t tswap = t + (uint32_t)chunk - 1u;
                 const int pairs = n_T - 1;
+                if (SPLIT) {
+                    // Publish own slots' energies and collect the partners'.
+                    // Each word carries its sweep tag, so plain relaxed
+                    // atomics suffice: no fence, no cache write-back.
+                    __syncthreads();   // own energies are complete
+                    const uint32_t tag = tswap + 1u;
+                    uint64_t *xb = jd.xchg + ((size_t)ladder * 2 + ((tswap / (uint32_t)se) & 1u)) * kMaxTemps;
+                    if (tid >= s_lo && tid < s_hi)
+                        __hip_atomic_store(&xb[tid], ((uint64_t)tag << 32) | (uint32_t)sm.U[tid], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    if (tid < n_T && (tid < s_lo || tid >= s_hi)) {
+                        uint32_t spins = 0;
+                        uint64_t v;
+                        // bounded: after any timeout (error set) nobody waits long again
+                        while ((uint32_t)((v = __hip_atomic_load(&xb[tid], __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT)) >> 32) != tag) {
+                            if (++spins > kSpinLimit ||
+                                ((spins & 255u) == 0u &&
+                                 __hip_atomic_load(jd.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
+                                atomicOr(jd.error, 1u);
+                                v = 0;
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                        sm.U[tid] = (int32_t)(uint32_t)v;
+                    }
+                }
                 if (wave == 0 && lane < pairs)
                     sm.draw[lane] = philox10((uint32_t)lane, tswap, r, c3swap, k0, k1).x;
                 __syncthreads();   // slot energies U and swap draws are in
@@ -686,9 +762,17 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
             t += (uint32_t)chunk;
             remaining -= chunk;
         }
-        if (n_groups == 1)
+        if (SPLIT) {
+            // merge own slots' bits: the partners change disjoint bits, so the xors commute
+            const uint32_t own = (ngr_own >= 8 ? 0xFFFFFFFFu : ((1u << (4 * ngr_own)) - 1u)) << s_lo;
+            for (int idx = tid; idx < N; idx += nthr) {
+                const uint32_t delta = (sm.spin[idx] ^ g_spin[idx]) & own;
+                if (delta) atomicXor(&g_spin[idx], delta);
+            }
+        } else if (n_groups == 1) {
             for (int idx = tid; idx < NW * N; idx += nthr) g_spin[idx] = sm.spin[idx];
-        if (tid < n_T) {
+        }
+        if (tid < n_T && part == 0) {
             jd.temp_of_slot[ladder * kMaxTemps + tid] = sm.perm[tid];
             if (tid < n_T - 1) jd.swap_acc[ladder * kMaxTemps + tid] += sm.acc[tid];
         }
@@ -854,9 +938,9 @@ hipError_t sweep_set_lds(int layout, size_t lds)
     static std::atomic<size_t> set_max[2] = {{0}, {0}};
     std::atomic<size_t> &cur = set_max[layout ? 1 : 0];
     if (lds <= cur.load()) return hipSuccess;
-    hipError_t e = layout == 0 ? hipFuncSetAttribute((const void *)sweep_kernel<0>,
+    hipError_t e = layout == 0 ? hipFuncSetAttribute((const void *)sweep_kernel<0, 1>,
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
-                               : hipFuncSetAttribute((const void *)sweep_kernel<1>,
+                               : hipFuncSetAttribute((const void *)sweep_kernel<1, 1>,
                                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e == hipSuccess) {
         size_t prev = cur.load();
@@ -872,15 +956,41 @@ hipError_t launch_sweep(const JobDesc *d_jobs, int n_jobs, const uint32_t *d_uni
     hipError_t e = sweep_set_lds(layout, lds);
     if (e != hipSuccess) return e;
     if (layout == 0)
-        hipLaunchKernelGGL(sweep_kernel<0>, dim3(grid), dim3(block_threads), lds, s, d_jobs, d_units, n_units,
+        hipLaunchKernelGGL((sweep_kernel<0, 1>), dim3(grid), dim3(block_threads), lds, s, d_jobs, d_units, n_units,
                            d_queue);
     else
-        hipLaunchKernelGGL(sweep_kernel<1>, dim3(grid), dim3(block_threads), lds, s, d_jobs, d_units, n_units,
+        hipLaunchKernelGGL((sweep_kernel<1, 1>), dim3(grid), dim3(block_threads), lds, s, d_jobs, d_units, n_units,
                            d_queue);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(advance_kernel, dim3((n_jobs + 255) / 256), dim3(256), 0, s, d_jobs, n_jobs, d_queue);
     return hipGetLastError();
+}
+
+hipError_t launch_sweep_split(const JobDesc *d_job, int ladders, int parts, int block_threads, size_t lds,
+                              uint32_t *d_queue, hipStream_t s)
+{
+    const void *fn = parts == 4 ? (const void *)sweep_kernel<0, 4> : (const void *)sweep_kernel<0, 2>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    // partners share blockIdx mod 8: ladder l, part p -> block (l / 8) * 8 * parts + p * 8 + l % 8
+    const int grid = (ladders + 7) / 8 * 8 * parts;
+    const uint32_t *no_units = nullptr;
+    int n_units = ladders;
+    void *args[] = {(void *)&d_job, (void *)&no_units, (void *)&n_units, (void *)&d_queue};
+    e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block_threads), args, (unsigned)lds, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, d_job, 1, d_queue);
+    return hipGetLastError();
+}
+
+int sweep_split_max_blocks_per_cu(int parts, int block_threads, size_t lds)
+{
+    int n = 0;
+    hipError_t e = parts == 4
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_kernel<0, 4>, block_threads, lds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_kernel<0, 2>, block_threads, lds);
+    return e == hipSuccess ? n : 0;
 }
 
 hipError_t launch_observables(const JobDesc *d_job, const JobDesc &h, int layout, int32_t *d_energy,
@@ -919,9 +1029,9 @@ int sweep_max_blocks_per_cu(int layout, int block_threads, size_t lds)
     int n = 0;
     hipError_t e;
     if (layout == 0)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_kernel<0>, block_threads, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_kernel<0, 1>, block_threads, lds);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_kernel<1>, block_threads, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_kernel<1, 1>, block_threads, lds);
     return e == hipSuccess ? n : 0;
 }
 

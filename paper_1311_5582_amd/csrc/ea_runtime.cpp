@@ -292,12 +292,20 @@ int ea_sweep_batch(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps, con
         s->h.n_sweeps = (int32_t)n_sweeps[0];
         s->h.swap_every = swap_every[0];
         EA_HIP(hipMemcpyAsync(&s->d_job->n_sweeps, &s->h.n_sweeps, 2 * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        int grid = 0;
-        if (int rc = device_grid(s->layout, s->block_threads, s->lds, s->h.ladders, &grid)) return rc;
-        EA_HIP(launch_sweep(s->d_job, 1, s->d_units, s->h.ladders, s->d_counters + 1, s->layout, s->block_threads,
-                            s->lds, grid, st));
+        if (s->split_parts > 1) {
+            EA_HIP(launch_sweep_split(s->d_job, s->h.ladders, s->split_parts, s->block_threads, s->lds,
+                                      s->d_counters + 1, st));
+        } else {
+            int grid = 0;
+            if (int rc = device_grid(s->layout, s->block_threads, s->lds, s->h.ladders, &grid)) return rc;
+            EA_HIP(launch_sweep(s->d_job, 1, s->d_units, s->h.ladders, s->d_counters + 1, s->layout,
+                                s->block_threads, s->lds, grid, st));
+        }
         s->t += n_sweeps[0];
-        if (!s->user_stream) EA_HIP(hipStreamSynchronize(st));
+        if (!s->user_stream) {
+            EA_HIP(hipStreamSynchronize(st));
+            return check_split_error(s);
+        }
         return EA_OK;
     }
     std::vector<JobDesc> descs(n_sims);

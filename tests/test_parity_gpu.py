@@ -193,3 +193,28 @@ def test_set_state_rejects_bad_permutation():
     perm[0, 1, 2] = perm[0, 1, 3]
     with pytest.raises(B.EAError):
         sim.set_state(s, perm, t)
+
+
+@pytest.mark.parametrize("L,R,n_T,swap_every", [(8, 1, 16, 1), (16, 2, 32, 1), (6, 3, 24, 3), (4, 2, 8, 2),
+                                                (10, 1, 32, 0)])
+def test_split_ladders_equal_unsplit(oracle_lib, L, R, n_T, swap_every):
+    """A job with few ladders spreads each ladder's slot groups over 2 or 4
+    co-resident workgroups that exchange slot energies at swap points; the
+    chain is the same as one workgroup per ladder, and the oracle's."""
+    seed = 500 + L + n_T
+    J = inputs.couplings(L, R, seed)
+    betas = inputs.geometric_betas(n_T, 0.4, 2.0)
+    a = B.Sim(L, J, betas, seed, split="always")
+    b = B.Sim(L, J, betas, seed, split=False)
+    print(f"[parity] split info {a.info()} unsplit {b.info()}", flush=True)
+    assert a.info()["split_parts"] > 1 and b.info()["split_parts"] == 1
+    for n in (5, 1, 14):
+        a.sweep(n, swap_every)
+        b.sweep(n, swap_every)
+        sa, sb = a.state(), b.state()
+        assert np.array_equal(sa[0], sb[0]) and np.array_equal(sa[1], sb[1]) and sa[2] == sb[2]
+    assert np.array_equal(a.observables()[0], b.observables()[0])
+    orc = oracle_lib.OracleSim(L, J, betas, seed)
+    orc.sweep(20, swap_every)
+    assert np.array_equal(a.state()[0], orc.spins)
+    assert np.array_equal(a.swap_acceptance(), b.swap_acceptance())
