@@ -166,7 +166,7 @@ def main():
     ap.add_argument("--serving-scale", type=float, default=1.0,
                     help="multiply every job's sweep count (1.0 = the lognormal trace as drawn)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
-                    help="before timing, run one plain device-to-device copy of this many MiB "
+                    help="before timing, run one elementwise kernel that reads and writes this many MiB "
                          "(reference kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
 
@@ -203,7 +203,9 @@ def main():
         src = torch.ones(n, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        # an elementwise kernel (a same-dtype copy_ may go to a DMA engine):
+        # reads n bytes, writes n bytes
+        torch.bitwise_not(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
     for _ in range(args.warmup):
@@ -246,7 +248,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
                      "frac": round(achieved / peak, 4), "traffic": measured_traffic(args.workload, args.layout),
                      "ops_per_flip": ALG_OPS_PER_FLIP, "kernel_sha1": kernel_source_hash(),
-                     "kernel": "sweep_kernel<%s>" % ("CAMSC" if args.layout == "camsc" else "AMSC4")},
+                     "kernel": "sweep_kernel<%s, %d>" % ("CAMSC" if args.layout == "camsc" else "AMSC4",
+                                                        launch["split_parts"])},
     }
     sim.close()
     if not args.no_batched:

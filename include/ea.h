@@ -111,7 +111,12 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T,
  * order), with a parallel-tempering pass after every sweep t for which
  * swap_every > 0 and (t+1) % swap_every == 0 (Sec. 4.1); swap_every = 0 turns
  * PT off.  Asynchronous on the handle's stream when one was given, otherwise
- * synchronous.  EA_ESTATE if the total sweep count would reach 2^32. */
+ * synchronous.  EA_ESTATE if the total sweep count would reach 2^32.
+ * A split job (ea_sim_info: split_parts > 1) launches cooperatively and its
+ * workgroups wait for each other at swap points with a bounded wait; should a
+ * wait ever time out, this call (or the next ea_observables / ea_state on an
+ * asynchronous stream) returns EA_EDEVICE and the state is invalid until
+ * ea_set_state. */
 int ea_sweep(ea_sim *sim, int64_t n_sweeps, int swap_every);
 
 /* One launch over the ladders of several jobs of uneven size (north-star

@@ -89,10 +89,11 @@ def _trace(n, seed=9):
     return out
 
 
-def test_server_results_alone_equal_mix():
+def test_server_results_alone_equal_mix(oracle_lib):
     """Jobs admitted under a budget that holds only a few at a time, with a
     small quantum so they interleave: each final state equals the job run
-    alone, and the energies/overlaps equal ea_observables of that run."""
+    alone, and the energies/overlaps equal ea_observables of that run; one
+    realization of every job equals the oracle's."""
     trace = _trace(8)
     fps = [B.job_footprint(j["L"], inputs.geometric_betas(j["n_T"], 0.4, 2.0), j["R"]) for j in trace]
     budget = sum(sorted(fps)[-3:])
@@ -112,6 +113,14 @@ def test_server_results_alone_equal_mix():
         assert np.array_equal(spins, s2) and np.array_equal(perm, p2), f"job {jid} differs from alone"
         E2, q2 = alone.observables()
         assert np.array_equal(E, E2) and np.array_equal(q, q2)
+        r = j["seed"] % j["R"]
+        betas = inputs.geometric_betas(j["n_T"], 0.4, 2.0)
+        orc = oracle_lib.OracleSim(j["L"], inputs.couplings(j["L"], j["R"], j["seed"])[[r]], betas, j["seed"],
+                                   rid=np.array([r]))
+        orc.sweep(j["sweeps"], j["swap_every"])
+        assert np.array_equal(spins[r], orc.spins[0]) and np.array_equal(perm[r], orc.temp_of_slot[0])
+        Eo, qo = orc.observables()
+        assert np.array_equal(E[r], Eo[0]) and np.array_equal(q[r], qo[0])
     st = srv.stats()
     print(f"[runtime] server stats {st} wall {wall:.3f}s", flush=True)
     assert st["hbm_used"] == 0
