@@ -155,7 +155,7 @@ def main():
     ap.add_argument("--no-split", action="store_true",
                     help="one workgroup per ladder even when the job has fewer ladders than compute units")
     ap.add_argument("--swap-every", type=int, default=-1, help="override the workload's PT interval")
-    ap.add_argument("--cpu-sweeps", type=int, default=60)
+    ap.add_argument("--cpu-sweeps", type=int, default=900)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-sweeps", type=int, default=250)

@@ -556,6 +556,7 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
             sm.perm[tid] = tid < n_T ? jd.temp_of_slot[ladder * kMaxTemps + tid] : 0;
             sm.acc[tid] = 0;
             sm.U[tid] = 0;
+            sm.mask[tid] = 0ull;
             sm.soff[tid] = jd.swap_off[tid];
             sm.slen[tid] = jd.swap_len[tid];
             sm.ssgn[tid] = jd.swap_sgn[tid];
@@ -683,51 +684,42 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                 if (wave == 0 && lane < pairs)
                     sm.draw[lane] = philox10((uint32_t)lane, tswap, r, c3swap, k0, k1).x;
                 __syncthreads();   // slot energies U and swap draws are in
-                // Bit j of mask[k]: would pair k swap if the configuration that
-                // sat at position j before the pass had been carried up to k?
+                // Bit k of col[j]: would pair k swap if the configuration that
+                // sat at position j before the pass had been carried up to k
+                // (j <= k)?  Waves take pairs in turn and OR their bits in.
                 const int u_mine = lane < n_T ? sm.U[sm.sot[lane]] : 0;
+                uint64_t colbits = 0;
                 for (int k = wave; k < pairs; k += nwaves) {
-                    bool acc = false;
                     if (lane <= k) {
                         const int d = u_mine - sm.U[sm.sot[k + 1]];
                         const int sg = sm.ssgn[k];
-                        acc = (sg == 0) || (d == 0) || ((sg > 0) == (d > 0));
+                        bool acc = (sg == 0) || (d == 0) || ((sg > 0) == (d > 0));
                         if (!acc) {
                             const int n = d < 0 ? -d : d;
                             const uint32_t thr = n < sm.slen[k] ? stab[sm.soff[k] + n] : 0u;
                             acc = sm.draw[k] < thr;
                         }
+                        if (acc) colbits |= 1ull << k;
                     }
-                    const uint64_t m = __ballot(acc);
-                    if (lane == 0) sm.mask[k] = m;
                 }
+                if (colbits) atomicOr((unsigned long long *)&sm.mask[lane], (unsigned long long)colbits);
                 __syncthreads();
                 if (wave == 0) {
-                    // Walk the pairs in ascending order on the scalar unit,
-                    // keeping only the set of rejected pairs; masks are read
-                    // eight at a time.  The configuration carried upwards
-                    // restarts at k + 1 after a rejection at k.
-                    const uint64_t mine = lane < pairs ? sm.mask[lane] : 0ull;
-                    const uint32_t mlo = (uint32_t)mine, mhi = (uint32_t)(mine >> 32);
-                    int cj = 0;
+                    // The ascending pass, visiting only its rejections: from
+                    // restart point j the next rejected pair is the first k >= j
+                    // whose bit is clear in col[j], and after a rejection at k
+                    // the carried configuration restarts at k + 1.
+                    const uint64_t col = sm.mask[lane];
+                    sm.mask[lane] = 0ull;   // consumed; ready for the next swap point
+                    const uint64_t open = ~col & ((1ull << pairs) - 1ull) & (~0ull << lane);   // pairs <= 63
+                    const int nr = open ? (int)__builtin_ctzll(open) : 64;
                     uint64_t rej = 0;
-                    for (int k0b = 0; k0b < pairs; k0b += 8) {
-                        uint64_t mk[8];
-#pragma unroll
-                        for (int i = 0; i < 8; ++i) {
-                            const int kk = min(k0b + i, 63);
-                            // readlane returns int: zero-extend both halves
-                            mk[i] = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(mhi, kk) << 32) |
-                                    (uint64_t)(uint32_t)__builtin_amdgcn_readlane(mlo, kk);
-                        }
-#pragma unroll
-                        for (int i = 0; i < 8; ++i) {
-                            const int k = k0b + i;
-                            if (k < pairs && !((mk[i] >> cj) & 1ull)) {
-                                rej |= 1ull << k;
-                                cj = k + 1;
-                            }
-                        }
+                    int cj = 0;
+                    for (;;) {   // cj grows every turn: at most `pairs` turns
+                        const int r = __builtin_amdgcn_readlane(nr, cj);
+                        if (r >= pairs) break;
+                        rej |= 1ull << r;
+                        cj = r + 1;
                     }
                     // lane k: pair k accepted -> the configuration from position k+1
                     // comes down; rejected -> the carried one stays (it started at the
@@ -745,13 +737,13 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                     if (lane < n_T) {
                         sm.sot[lane] = newslot;
                         sm.perm[newslot] = lane;
+                        // the slot now at temperature `lane` takes that temperature's row
+                        const uint4 *from = (const uint4 *)(sm.fthr + lane * kThrCols);
+                        uint4 *to = (uint4 *)(sm.thr + newslot * kThrCols);
+#pragma unroll
+                        for (int c = 0; c < kThrCols / 4; ++c) to[c] = from[c];
                     }
-                    sm.U[lane] = 0;   // consumed; ready for the next swap point
-                }
-                __syncthreads();
-                for (int idx = tid; idx < kMaxTemps * kThrCols; idx += nthr) {
-                    const int slot = idx / kThrCols;
-                    sm.thr[idx] = slot < n_T ? sm.fthr[sm.perm[slot] * kThrCols + (idx % kThrCols)] : 0u;
+                    sm.U[lane] = 0;   // consumed
                 }
                 __syncthreads();
             } else if (swap_now) {
