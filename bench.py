@@ -152,6 +152,8 @@ def main():
     ap.add_argument("--workload", default="L16_R64")
     ap.add_argument("--layout", default="camsc", choices=["camsc", "amsc4"])
     ap.add_argument("--block-threads", type=int, default=0)
+    ap.add_argument("--rng", default="words", choices=["words", "planes"],
+                    help="flip-draw stream: one Philox word per flip, or bit planes compared MSB first")
     ap.add_argument("--no-split", action="store_true",
                     help="one workgroup per ladder even when the job has fewer ladders than compute units")
     ap.add_argument("--swap-every", type=int, default=-1, help="override the workload's PT interval")
@@ -186,7 +188,7 @@ def main():
     J = inputs.couplings(L, R, cfg["seed"])
     betas = inputs.geometric_betas(n_T, cfg["t_min"], cfg["t_max"])
     sim = B.Sim(L, J, betas, cfg["seed"], layout=args.layout, block_threads=args.block_threads, stream=stream,
-                split=not args.no_split)
+                split=not args.no_split, rng=args.rng)
     launch = sim.info()
     S, se = args.sweeps_per_step, (cfg["swap_every"] if args.swap_every < 0 else args.swap_every)
 
@@ -241,7 +243,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "L": L, "spins": L ** 3, "realizations": R, "copies": 2,
                    "temperatures": n_T, "T_range": [cfg["t_min"], cfg["t_max"]], "sweeps_per_step": S,
-                   "swap_every": se, "layout": args.layout, "measurement_per_step": True,
+                   "swap_every": se, "layout": args.layout, "rng": args.rng, "measurement_per_step": True,
                    "block_threads": launch["block_threads"], "workgroups_per_ladder": launch["split_parts"],
                    "kernel_ps_per_flip": round(avg_launch_s / flips_per_step * 1e12, 4),
                    "paper_ps_per_flip_gtx580": 33.5},

@@ -66,6 +66,17 @@ extern "C" {
                               bond energies are widened to 4-bit segments only to sum */
 #define EA_LAYOUT_AMSC4 1  /* 4-bit segment per slot (spin in bit 0), 8 slots per word */
 
+/* flip-draw streams (Sec. 4.3.2: raw 32-bit integers against 32-bit thresholds) */
+#define EA_RNG_WORDS  0    /* one Philox output word per (slot, site, sweep), as in the
+                              stream description above                                  */
+#define EA_RNG_PLANES 1    /* the same 32-bit uniform per (slot, site, sweep), stored
+                              bit-sliced: slots form halves of 16 (h = slot >> 4); bit
+                              31 - p of slot s's uniform is bit s & 15 of the 16-bit
+                              field p & 1 of word (p & 7) >> 1 of
+                              block(i, t, r, 4<<28 | c<<24 | h<<8 | p>>3).  The compare
+                              is decided at the first differing bit, so the kernel
+                              draws only the planes it needs                             */
+
 #define EA_MAX_TEMPS 64    /* temperatures (slots) per copy                           */
 #define EA_MAX_L     32    /* lattice side                                            */
 
@@ -81,6 +92,9 @@ typedef struct ea_options {
                             temperatures, even L) spreads each ladder's slot groups over 2
                             or 4 co-resident workgroups when each keeps >= 2048 site-groups
                             of work per sweep; 1 = never; 2 = whenever possible           */
+    int rng;             /* flip-draw stream: EA_RNG_WORDS (default) or EA_RNG_PLANES
+                            (CAMSC only); both give each flip the acceptance law
+                            P(draw < threshold) = threshold / 2^32                      */
     void *stream;        /* hipStream_t to run on; NULL = the default stream            */
     /* optional device allocator (e.g. backed by a framework's caching allocator);
        both NULL = hipMalloc / hipFree.  dev_alloc returns NULL on failure.            */
@@ -177,7 +191,7 @@ typedef struct ea_server_options {
     int max_active;           /* admitted jobs at once, <= 4095 (0 = 4095)                        */
     int autotune;             /* 1 = tune each job mix's workgroup size (cached by shape); default 0 */
     int keep_state;           /* keep each finished job's spins and permutation on the host       */
-    int reserved_;
+    int rng;                  /* EA_RNG_* flip-draw stream of every job (planes: CAMSC only)      */
     void *stream;             /* hipStream_t; NULL = a stream owned by the server                 */
 } ea_server_options;
 

@@ -24,7 +24,7 @@ _f64p = ctypes.POINTER(ctypes.c_double)
 
 class _OrcSim(ctypes.Structure):
     _fields_ = [
-        ("L", ctypes.c_int), ("n_T", ctypes.c_int), ("R", ctypes.c_int), ("pad_", ctypes.c_int),
+        ("L", ctypes.c_int), ("n_T", ctypes.c_int), ("R", ctypes.c_int), ("rng", ctypes.c_int),
         ("seed", ctypes.c_uint64), ("t", ctypes.c_int64),
         ("rid", _i32p), ("J", _i8p), ("betas", _f64p),
         ("spins", _i8p), ("temp_of_slot", _i32p), ("Urun", _i64p),
@@ -47,6 +47,9 @@ def lib():
         L.orc_philox4x32_10.restype = None
         L.orc_flip_threshold.argtypes = [ctypes.c_double, ctypes.c_int]
         L.orc_flip_threshold.restype = ctypes.c_uint32
+        L.orc_flip_draw.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                    ctypes.c_int, ctypes.c_int]
+        L.orc_flip_draw.restype = ctypes.c_uint32
         L.orc_swap_threshold.argtypes = [ctypes.c_double, ctypes.c_int64]
         L.orc_swap_threshold.restype = ctypes.c_uint32
         L.orc_n_phases.argtypes = [ctypes.c_int]
@@ -79,6 +82,16 @@ def philox4x32_10(ctr, key):
     out = np.zeros(4, dtype=np.uint32)
     lib().orc_philox4x32_10(_ptr(c, ctypes.c_uint32), _ptr(k, ctypes.c_uint32), _ptr(out, ctypes.c_uint32))
     return out
+
+
+RNG_WORDS, RNG_PLANES = 0, 1
+RNGS = {"words": RNG_WORDS, "planes": RNG_PLANES}
+
+
+def flip_draw(seed, rng, i, t, r, c, slot):
+    """The flip draw of (realization id r, copy c, slot, sweep t, site i)."""
+    return int(lib().orc_flip_draw(int(seed) & (2 ** 64 - 1), RNGS.get(rng, rng), int(i), int(t), int(r), int(c),
+                                   int(slot)))
 
 
 def flip_threshold(beta, u):
@@ -116,7 +129,7 @@ class OracleSim:
     rid: realization ids (Philox counter word 2), default 0..R-1.
     """
 
-    def __init__(self, L, couplings, betas, seed, rid=None, track_energy=False, stats=False):
+    def __init__(self, L, couplings, betas, seed, rid=None, track_energy=False, stats=False, rng="words"):
         self.L = int(L)
         self.N = self.L ** 3
         self.J = np.ascontiguousarray(couplings, dtype=np.int8)
@@ -140,7 +153,9 @@ class OracleSim:
             self.flip_tries = self.flip_acc = self.swap_tries = self.swap_acc = None
         self._s = _OrcSim()
         s = self._s
-        s.L, s.n_T, s.R, s.seed, s.t = self.L, self.n_T, self.R, self.seed, 0
+        self.rng = RNGS.get(rng, rng)
+        assert self.rng in (RNG_WORDS, RNG_PLANES)
+        s.L, s.n_T, s.R, s.seed, s.t, s.rng = self.L, self.n_T, self.R, self.seed, 0, self.rng
         s.rid = _ptr(self.rid, ctypes.c_int32)
         s.J = _ptr(self.J, ctypes.c_int8)
         s.betas = _ptr(self.betas, ctypes.c_double)

@@ -52,6 +52,15 @@
  *   swap  draw (r, c, pair k, t)      : ctr (k, t, r, 1<<28 | c<<24), word 0
  *   init  spin (r, c, slot, site i)   : ctr (i, 0, r, 2<<28 | c<<24 | slot>>2), word slot&3, bit 0
  *
+ * Second flip-draw stream (ORC_RNG_PLANES), same acceptance law: the slot's
+ * 32-bit uniform is spread over 32 bit planes.  Slots form halves of 16
+ * (h = slot >> 4); plane p of half h (p = 0 holds the most significant bit)
+ * is the 16-bit field p & 1 (low field first) of word (p & 7) >> 1 of
+ *   ctr (i, t, r, 4<<28 | c<<24 | h<<8 | p>>3),
+ * and bit slot & 15 of plane p is bit 31 - p of the slot's uniform.  The
+ * comparison draw < threshold is then decided at the first plane where the
+ * two differ, which lets a bit-parallel implementation stop early.
+ *
  * Build: gcc -O2 -fPIC -shared (see oracle/build.py).  No threads, no SIMD
  * intrinsics, no blocking or fusion.
  */
@@ -105,10 +114,25 @@ static uint32_t orc_draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, u
 #define ORC_DOMAIN_FLIP 0u
 #define ORC_DOMAIN_SWAP 1u
 #define ORC_DOMAIN_INIT 2u
+#define ORC_DOMAIN_PLANE 4u
 
 static uint32_t orc_c3(uint32_t domain, int copy, int slot_group)
 {
     return (domain << 28) | ((uint32_t)copy << 24) | (uint32_t)slot_group;
+}
+
+/* The flip draw of one (realization, copy, slot, sweep, site). */
+uint32_t orc_flip_draw(uint64_t seed, int rng, uint32_t i, uint32_t t, uint32_t r, int c, int slot)
+{
+    if (rng != ORC_RNG_PLANES) return orc_draw(seed, i, t, r, orc_c3(ORC_DOMAIN_FLIP, c, slot >> 2), slot & 3);
+    uint32_t uniform = 0u;
+    for (int p = 0; p < 32; ++p) {
+        uint32_t w = orc_draw(seed, i, t, r, orc_c3(ORC_DOMAIN_PLANE, c, ((slot >> 4) << 8) | (p >> 3)),
+                              (p & 7) >> 1);
+        uint32_t plane = (w >> (16 * (p & 1))) & 0xFFFFu;
+        uniform |= ((plane >> (slot & 15)) & 1u) << (31 - p);
+    }
+    return uniform;
 }
 
 /* ---------------------------------------------------------------------- */
@@ -280,8 +304,8 @@ static void orc_stage(orc_sim *sim, int colour, uint32_t t)
                             if (u >= 3) {
                                 flip = 1;
                             } else {
-                                uint32_t draw = orc_draw(sim->seed, (uint32_t)i, t, (uint32_t)sim->rid[r],
-                                                         orc_c3(ORC_DOMAIN_FLIP, c, slot >> 2), slot & 3);
+                                uint32_t draw = orc_flip_draw(sim->seed, sim->rng, (uint32_t)i, t,
+                                                              (uint32_t)sim->rid[r], c, slot);
                                 flip = draw < orc_flip_threshold(beta, u);
                             }
                             if (sim->flip_tries) {

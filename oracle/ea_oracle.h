@@ -11,13 +11,17 @@
 
 #define ORC_MAX_TEMPS 64
 
+/* flip-draw streams */
+#define ORC_RNG_WORDS  0  /* one 32-bit word per (slot, site, sweep)                    */
+#define ORC_RNG_PLANES 1  /* the slot's 32-bit uniform read from bit planes of 16 slots */
+
 /* All arrays are owned by the caller.  Spins are stored one per byte (+1/-1),
  * indexed by slot; temp_of_slot maps each slot to its temperature index. */
 typedef struct {
     int L;                   /* lattice side, >= 2                              */
     int n_T;                 /* temperatures (= slots) per copy, 1..64          */
     int R;                   /* realizations held in this state                 */
-    int pad_;
+    int rng;                 /* ORC_RNG_WORDS (0) or ORC_RNG_PLANES (1)          */
     uint64_t seed;           /* Philox key                                      */
     int64_t t;               /* sweeps done (global sweep index of the next)    */
     const int32_t *rid;      /* [R] realization id used as Philox counter word 2 */
@@ -34,6 +38,8 @@ typedef struct {
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 uint32_t orc_flip_threshold(double beta, int u);
+/* the flip draw of (realization id r, copy c, slot, sweep t, site i) under stream `rng` */
+uint32_t orc_flip_draw(uint64_t seed, int rng, uint32_t i, uint32_t t, uint32_t r, int c, int slot);
 uint32_t orc_swap_threshold(double dbeta_abs, int64_t n);
 int orc_n_phases(int L);
 int orc_colour(int L, int x, int y, int z);

@@ -20,6 +20,8 @@ HEADER = os.path.join(ROOT, "include", "ea.h")
 EA_OK, EA_EINVAL, EA_ENOMEM, EA_EDEVICE, EA_ESTATE = 0, -1, -2, -3, -4
 LAYOUT_CAMSC, LAYOUT_AMSC4 = 0, 1
 LAYOUTS = {"camsc": LAYOUT_CAMSC, "amsc4": LAYOUT_AMSC4}
+RNG_WORDS, RNG_PLANES = 0, 1
+RNGS = {"words": RNG_WORDS, "planes": RNG_PLANES}
 MAX_TEMPS = 64
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -29,7 +31,7 @@ _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 class Options(ctypes.Structure):
     _fields_ = [
         ("layout", ctypes.c_int), ("block_threads", ctypes.c_int),
-        ("words_resident", ctypes.c_int), ("split", ctypes.c_int),
+        ("words_resident", ctypes.c_int), ("split", ctypes.c_int), ("rng", ctypes.c_int),
         ("stream", ctypes.c_void_p),
         ("dev_alloc", _ALLOC_FN), ("dev_free", _FREE_FN), ("alloc_ctx", ctypes.c_void_p),
     ]
@@ -43,7 +45,7 @@ class PlanOptions(ctypes.Structure):
 class ServerOptions(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("quantum_sweeps", ctypes.c_int), ("layout", ctypes.c_int),
                 ("max_active", ctypes.c_int), ("autotune", ctypes.c_int), ("keep_state", ctypes.c_int),
-                ("reserved_", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("rng", ctypes.c_int), ("stream", ctypes.c_void_p)]
 
 
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_CANCELLED, JOB_FAILED = 0, 1, 2, 3, 4
@@ -181,7 +183,7 @@ class Sim:
     """One job: R realizations x 2 copies x n_T temperature slots on the GPU."""
 
     def __init__(self, L, couplings, betas, seed, layout="camsc", block_threads=0, words_resident=0,
-                 stream=None, torch_memory=True, split=True):
+                 stream=None, torch_memory=True, split=True, rng="words"):
         L = int(L)
         J = np.ascontiguousarray(couplings, dtype=np.int8)
         if J.ndim != 3 or J.shape[1:] != (L ** 3, 3):
@@ -194,6 +196,7 @@ class Sim:
         opt.words_resident = int(words_resident)
         # True/"auto": library choice; False: one workgroup per ladder; "always": split when possible
         opt.split = {True: 0, "auto": 0, False: 1, "never": 1, "always": 2}[split]
+        opt.rng = RNGS[rng] if isinstance(rng, str) else int(rng)
         self._alloc = None
         torch = _torch_gpu() if (torch_memory or stream is not None) else None
         if stream is not None:
@@ -323,7 +326,7 @@ class Server:
     """Continuous-batching job server (see ea_server_* in include/ea.h)."""
 
     def __init__(self, hbm_budget_bytes=0, quantum_sweeps=200, layout="camsc", max_active=0, autotune=False,
-                 keep_state=False):
+                 keep_state=False, rng="words"):
         opt = ServerOptions()
         lib().ea_default_server_options(ctypes.byref(opt))
         opt.hbm_budget_bytes = int(hbm_budget_bytes)
@@ -332,6 +335,7 @@ class Server:
         opt.max_active = int(max_active)
         opt.autotune = int(bool(autotune))
         opt.keep_state = int(bool(keep_state))
+        opt.rng = RNGS[rng] if isinstance(rng, str) else int(rng)
         self._h = ctypes.c_void_p()
         self.shapes = {}
         check(lib().ea_server_create(ctypes.byref(opt), ctypes.byref(self._h)))

@@ -148,7 +148,7 @@ int plan_launch(int N, int NW, const ea_options &opt, int *block_threads, int *w
 {
     // words resident in LDS
     const LdsLayout lay = lds_layout(N, 1, 1, 1);
-    if (lay.mask % 8 != 0 || lay.spin % 16 != 0 || lay.thr % 16 != 0 || lay.stab % 4 != 0 || lay.sites % 4 != 0)
+    if (lay.mask % 8 != 0 || lay.ptab % 16 != 0 || lay.spin % 16 != 0 || lay.thr % 16 != 0 || lay.stab % 4 != 0 || lay.sites % 4 != 0)
         return fail(EA_EINVAL, "internal LDS layout misaligned for %d sites", N);
     const size_t fixed = lds_layout(N, 0, 0, 0).total;
     if (fixed + (size_t)N * 4 > kLdsBudget)
@@ -177,13 +177,13 @@ int plan_launch(int N, int NW, const ea_options &opt, int *block_threads, int *w
     return EA_OK;
 }
 
-int device_grid(int layout, int bt, size_t lds, int n_units, int *grid)
+int device_grid(int kv, int bt, size_t lds, int n_units, int *grid)
 {
     int dev = 0;
     EA_HIP(hipGetDevice(&dev));
     int cus = 0;
     EA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    int per_cu = sweep_max_blocks_per_cu(layout, bt, lds);
+    int per_cu = sweep_max_blocks_per_cu(kv, bt, lds);
     if (per_cu < 1) return fail(EA_EDEVICE, "sweep kernel cannot be resident with %d threads and %zu B LDS", bt, lds);
     *grid = std::max(1, std::min(n_units, cus * per_cu));
     return EA_OK;
@@ -252,7 +252,8 @@ static int choose_split(const ea_sim *s, int split_opt)
         // a small lattice is latency-bound: the exchange costs more than the split saves
         if (split_opt == 0 && (int64_t)s->N * (ngr / parts) < 2048) continue;
         const int blocks = (ladders + 7) / 8 * 8 * parts;
-        const int per_cu = sweep_split_max_blocks_per_cu(parts, s->block_threads, s->lds);
+        const int per_cu = sweep_split_max_blocks_per_cu(parts, kernel_variant(s->layout, s->h.rng),
+                                                         s->block_threads, s->lds);
         if (per_cu < 1 || (int64_t)per_cu * cus < blocks) continue;
         return parts;
     }
@@ -312,6 +313,9 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
     if (!couplings || !betas) return fail(EA_EINVAL, "couplings and betas must not be NULL");
     if (opt.layout != EA_LAYOUT_CAMSC && opt.layout != EA_LAYOUT_AMSC4)
         return fail(EA_EINVAL, "unknown layout %d", opt.layout);
+    if (opt.rng != EA_RNG_WORDS && opt.rng != EA_RNG_PLANES) return fail(EA_EINVAL, "unknown rng %d", opt.rng);
+    if (opt.rng == EA_RNG_PLANES && opt.layout != EA_LAYOUT_CAMSC)
+        return fail(EA_EINVAL, "plane draws need the CAMSC layout");
     if ((opt.dev_alloc == nullptr) != (opt.dev_free == nullptr))
         return fail(EA_EINVAL, "dev_alloc and dev_free must be given together");
     for (int k = 0; k < n_T; ++k)
@@ -410,6 +414,7 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
     h.L = L; h.N = N; h.n_T = n_T; h.NW = NW; h.n_classes = n_classes; h.words_resident = wr;
     h.n_sweeps = 0; h.swap_every = 0; h.ladders = ladders; h.block_threads = bt;
     h.seg_bits = 4;
+    h.rng = opt.rng;
     h.invL = 1.0f / (float)L;
     h.invH = 1.0f / (float)(L / 2 > 0 ? L / 2 : 1);
     s->swap_total = (int64_t)sthr.size();

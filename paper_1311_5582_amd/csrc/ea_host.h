@@ -41,7 +41,7 @@ int wgs_per_cu(size_t lds, int bt);
 int build_swap_tables(const double *betas, int n_T, int N, std::vector<uint32_t> *sthr, std::vector<int32_t> *soff,
                       std::vector<int32_t> *slen, std::vector<int32_t> *ssgn, int64_t *total);
 size_t job_footprint_bytes(int L, int n_T, int R, int layout, int64_t swap_entries);
-int device_grid(int layout, int bt, size_t lds, int n_units, int *grid);
+int device_grid(int kv, int bt, size_t lds, int n_units, int *grid);   // kv: kernel_variant()
 
 }  // namespace ea
 

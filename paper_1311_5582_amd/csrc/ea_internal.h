@@ -18,6 +18,7 @@ constexpr int kPhiloxRounds = 10;
 constexpr uint32_t kDomainFlip = 0u;
 constexpr uint32_t kDomainSwap = 1u;
 constexpr uint32_t kDomainInit = 2u;
+constexpr uint32_t kDomainPlane = 4u;   // bit-plane flip draws (EA_RNG_PLANES)
 
 constexpr int kMaxTemps = 64;
 constexpr int kThrCols = 16;          // threshold row: column 2E+S, E in 0..6, S in 0..1
@@ -61,6 +62,8 @@ struct JobDesc {
                               // constant width lets the compiler split v_bfe_u32 into shift+mask)
     uint64_t *xchg;           // [ladders][2][kMaxTemps] (sweep index + 1) << 32 | slot energy, split workgroups
     uint32_t *error;          // set to non-zero if a split exchange timed out
+    int32_t rng;              // EA_RNG_WORDS or EA_RNG_PLANES (CAMSC only)
+    int32_t pad_;
 };
 
 // Dynamic LDS carve-up of the sweep kernel, one definition for host and
@@ -78,6 +81,7 @@ struct LdsLayout {
     uint32_t ssgn;    // [kMaxTemps] i32 sign of beta_k - beta_{k+1}
     uint32_t acc;     // [kMaxTemps] u32 accepted swaps of this unit
     uint32_t mask;    // [kMaxTemps] u64 speculative accept bits
+    uint32_t ptab;    // [2 words][3 E][32 planes] u32 bit-sliced thresholds by slot (EA_RNG_PLANES)
     uint32_t spin;    // [words][N] u32 spin words
     uint32_t stab;    // [swap_entries] u32 swap tables (optional)
     uint32_t sites;   // [site_entries] u32 packed coordinates (optional)
@@ -99,7 +103,8 @@ __host__ __device__ inline LdsLayout lds_layout(int N, int words, int swap_entri
     l.ssgn = l.slen + kMaxTemps * 4;
     l.acc = l.ssgn + kMaxTemps * 4;
     l.mask = l.acc + kMaxTemps * 4;
-    l.spin = l.mask + kMaxTemps * 8;
+    l.ptab = l.mask + kMaxTemps * 8;
+    l.spin = l.ptab + 2 * 3 * 32 * 4;
     l.stab = l.spin + (uint32_t)words * (uint32_t)N * 4u;
     l.sites = l.stab + (uint32_t)swap_entries * 4u;
     l.j6 = l.sites + (uint32_t)site_entries * 4u;
@@ -109,18 +114,20 @@ __host__ __device__ inline LdsLayout lds_layout(int N, int words, int swap_entri
 
 // Host-side launchers (ea_kernels.hip).  Each returns the first HIP error.
 hipError_t launch_init_spins(const JobDesc *d_job, const JobDesc &h_job, int layout, hipStream_t s);
+// Sweep kernel variant: 0 CAMSC, 1 AMSC4, 2 CAMSC with plane draws.
+inline int kernel_variant(int layout, int rng) { return layout == 1 ? 1 : (rng ? 2 : 0); }
 hipError_t launch_sweep(const JobDesc *d_jobs, int n_jobs, const uint32_t *d_units, int n_units,
-                        uint32_t *d_queue, int layout, int block_threads, size_t lds, int grid,
+                        uint32_t *d_queue, int kv, int block_threads, size_t lds, int grid,
                         hipStream_t s);
 // Split launch: `parts` co-resident workgroups per ladder (cooperative launch).
-hipError_t launch_sweep_split(const JobDesc *d_job, int ladders, int parts, int block_threads, size_t lds,
+hipError_t launch_sweep_split(const JobDesc *d_job, int ladders, int parts, int kv, int block_threads, size_t lds,
                               uint32_t *d_queue, hipStream_t s);
-int sweep_split_max_blocks_per_cu(int parts, int block_threads, size_t lds);
+int sweep_split_max_blocks_per_cu(int parts, int kv, int block_threads, size_t lds);
 hipError_t launch_observables(const JobDesc *d_job, const JobDesc &h_job, int layout, int32_t *d_energy,
                               int32_t *d_overlap, hipStream_t s);
 hipError_t launch_unpack(const JobDesc *d_job, const JobDesc &h_job, int layout, int8_t *d_spins, hipStream_t s);
 hipError_t launch_pack(const JobDesc *d_job, const JobDesc &h_job, int layout, const int8_t *d_spins, hipStream_t s);
-hipError_t sweep_set_lds(int layout, size_t lds);
-int sweep_max_blocks_per_cu(int layout, int block_threads, size_t lds);
+hipError_t sweep_set_lds(int kv, size_t lds);
+int sweep_max_blocks_per_cu(int kv, int block_threads, size_t lds);
 
 }  // namespace ea

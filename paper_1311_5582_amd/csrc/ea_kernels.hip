@@ -134,6 +134,7 @@ struct Smem {
     int32_t *soff, *slen, *ssgn;   // swap tables: offset, length, sign of dbeta
     uint32_t *acc;    // accepted swaps per pair in this unit
     uint64_t *mask;   // speculative accept bits per pair
+    uint32_t *ptab;   // [2][3][32] bit-sliced thresholds by slot (plane draws)
     uint32_t *spin;   // [words_resident][N]
     uint32_t *stab;   // swap tables (when cached)
     uint32_t *sites;  // odd-L site list (when cached)
@@ -150,6 +151,7 @@ __device__ __forceinline__ Smem carve(uint8_t *base, int N, int words, int swap_
     s.perm = (int32_t *)(base + l.perm);
     s.sot = (int32_t *)(base + l.sot);
     s.draw = (uint32_t *)(base + l.draw);
+    s.ptab = (uint32_t *)(base + l.ptab);
     s.soff = (int32_t *)(base + l.soff);
     s.slen = (int32_t *)(base + l.slen);
     s.ssgn = (int32_t *)(base + l.ssgn);
@@ -211,6 +213,72 @@ __device__ __forceinline__ uint32_t amsc4_decide(uint32_t X, const uint32_t *row
 __device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c)
 {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);   // truth table of majority(a, b, c)
+}
+
+// CAMSC with bit-plane draws.  The uniform of slot s is bit-sliced over 32
+// planes (plane p holds bit 31 - p); plane p of the 16-slot half h is the
+// 16-bit field p & 1 of word (p & 7) >> 1 of block (site, t, r,
+// domain | copy | h << 8 | p >> 3).  `draw < threshold` is decided at the
+// first plane where the two differ, so the slots still undecided (`und`) are
+// compared plane by plane against their thresholds, which pt holds bit-sliced
+// by slot (pt[e * 32 + p] = bit 31 - p of the threshold at E = e, e = 0..2;
+// m1 / m2 select the slots with E = 1 / 2), and the wave stops drawing once
+// every lane is decided.  NH halves starting at global half index h0 (c3
+// already holds it); with NH == 1 the half sits at bit `lo` (0 or 16) of the
+// word.  Returns the slots whose draw is below their threshold.
+template <int NH>
+__device__ __forceinline__ uint32_t camsc_decide_planes(uint32_t und, uint32_t m1, uint32_t m2, const uint32_t *pt,
+                                                        uint32_t site, uint32_t t, uint32_t r, uint32_t c3,
+                                                        uint32_t k0, uint32_t k1, int lo)
+{
+    uint32_t lt = 0;
+    // byte selectors of v_perm_b32: one 16-bit field moved to bit `lo`, other bits 0
+    const uint32_t sel_even = lo ? 0x01000C0Cu : 0x0C0C0100u;
+    const uint32_t sel_odd = lo ? 0x03020C0Cu : 0x0C0C0302u;
+#pragma unroll 1
+    for (int g = 0; g < 4; ++g) {
+        if (__builtin_amdgcn_ballot_w64(und != 0u) == 0ull) break;   // every lane decided
+        const U4 a = philox10(site, t, r, c3 + (uint32_t)g, k0, k1);
+        U4 b = a;
+        if (NH == 2) b = philox10(site, t, r, c3 + (1u << 8) + (uint32_t)g, k0, k1);
+        const uint32_t wa[4] = {a.x, a.y, a.z, a.w};
+        const uint32_t wb[4] = {b.x, b.y, b.z, b.w};
+        const uint32_t *p0 = pt + 8 * g;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            uint32_t R;
+            if (NH == 2)   // low halves of both blocks' word, or high halves: slots 0..15 | 16..31
+                R = __builtin_amdgcn_perm(wb[q >> 1], wa[q >> 1], (q & 1) ? 0x07060302u : 0x05040100u);
+            else
+                R = __builtin_amdgcn_perm(wa[q >> 1], wa[q >> 1], (q & 1) ? sel_odd : sel_even);
+            const uint32_t t01 = (m1 & p0[32 + q]) | (~m1 & p0[q]);
+            const uint32_t T = (m2 & p0[64 + q]) | (~m2 & t01);
+            const uint32_t x = und & (R ^ T);   // decided at this plane
+            lt |= x & T;                        // draw bit 0, threshold bit 1: below
+            und ^= x;
+        }
+    }
+    return lt;
+}
+
+// Bit-sliced thresholds by slot for the plane draws, from the rows by slot:
+// ptab[w][e][p] bit b = bit 31 - p of the threshold of slot 32 w + b at E = e
+// (column 2e; with h = 0 both columns of an E are equal).  Rows of slots past
+// the ladder are zero.  One ballot per (e, p), shared out over the waves.
+__device__ __forceinline__ void build_ptab(const Smem &sm, int NW, int wave, int nwaves, int lane)
+{
+    const uint32_t v0 = sm.thr[lane * kThrCols + 0];
+    const uint32_t v1 = sm.thr[lane * kThrCols + 2];
+    const uint32_t v2 = sm.thr[lane * kThrCols + 4];
+    for (int item = wave; item < 96; item += nwaves) {
+        const int e = item >> 5, p = item & 31;
+        const uint32_t v = e == 0 ? v0 : (e == 1 ? v1 : v2);
+        const uint64_t b = __ballot((v >> (31 - p)) & 1u);
+        if (lane == 0) {
+            sm.ptab[item] = (uint32_t)b;
+            if (NW > 1) sm.ptab[96 + item] = (uint32_t)(b >> 32);
+        }
+    }
 }
 
 template <int CTRL, int ROW_MASK>
@@ -309,7 +377,7 @@ __device__ __forceinline__ void reduce_planes8_add(const uint32_t (&P8)[8], int 
 // With SPLIT (CAMSC, one word per site) this workgroup owns only the slot
 // groups [gb, gb + ngr_own) of the word; the other groups' bits in its LDS
 // copy are never read for its own decisions (slots do not interact).
-template <int LAYOUT, bool ACC = false, bool SPLIT = false>
+template <int LAYOUT, bool ACC = false, bool SPLIT = false, int RNG = 0>
 __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int N, int gw, int g0, int n_T,
                                             uint32_t t, uint32_t r, uint32_t c3base, uint32_t k0, uint32_t k1,
                                             uint32_t segw, uint32_t (*P)[8] = nullptr, int np = 0, int gb = 0,
@@ -336,7 +404,40 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
         const uint32_t e4 = S ^ sw[nb.zp] ^ m[4];
         const uint32_t e5 = S ^ sw[nb.zm] ^ m[5];
         const int wg = __builtin_amdgcn_readfirstlane(g0 + w);
-        if (LAYOUT == 0) {
+        if (LAYOUT == 0 && RNG == 1) {
+            // CAMSC with bit-plane draws: E as three bit planes (full adders)
+            const uint32_t s1 = xor3(e0, e1, e2), c1 = maj3(e0, e1, e2);
+            const uint32_t s2 = xor3(e3, e4, e5), c2 = maj3(e3, e4, e5);
+            const uint32_t E0 = s1 ^ s2, kk = s1 & s2;
+            const uint32_t E1 = xor3(c1, c2, kk), E2 = maj3(c1, c2, kk);
+            const uint32_t always = E2 | (E1 & E0);   // E >= 3
+            const int slot0 = wg * 32;
+            const int left = n_T - slot0;
+            uint32_t valid = left >= 32 ? 0xFFFFFFFFu : ((1u << left) - 1u);
+            int h0 = 2 * wg, nh = left > 16 ? 2 : 1, lo = 0;
+            if (SPLIT) {
+                const int a = 4 * gb, b = 4 * (gb + ngr_own) - 1;
+                valid &= (ngr_own >= 8 ? 0xFFFFFFFFu : ((1u << (4 * ngr_own)) - 1u)) << (4 * gb);
+                h0 = 2 * wg + (a >> 4);
+                nh = (b >> 4) - (a >> 4) + 1;
+                lo = nh == 1 ? (a & 16) : 0;
+            }
+            const uint32_t und = valid & ~always;
+            const uint32_t *pt = sm.ptab + wg * 96;
+            const uint32_t c3 = c3base | ((uint32_t)h0 << 8);
+            const uint32_t F = nh == 2 ? camsc_decide_planes<2>(und, E0 & ~E1, E1 & ~E0, pt, nb.i, t, r, c3, k0, k1, 0)
+                                       : camsc_decide_planes<1>(und, E0 & ~E1, E1 & ~E0, pt, nb.i, t, r, c3, k0, k1,
+                                                                lo);
+            const uint32_t flip = (F | always) & valid;
+            sw[nb.i] = S ^ flip;
+            if (ACC) {
+                // unsatisfied bonds after the update: E if kept, 6 - E if flipped;
+                // bit planes of 6 - E: (E0, ~(E1 ^ E0), ~(E2 ^ (E1 & E0)))
+                const uint32_t C1 = (flip & ~(E1 ^ E0)) | (~flip & E1);
+                const uint32_t C2 = (flip & ~(E2 ^ (E1 & E0))) | (~flip & E2);
+                planes_add3(*P, E0, C1, C2, np);
+            }
+        } else if (LAYOUT == 0) {
             // CAMSC: widen each 1-bit bond word into four 4-bit-segment words
             // (segment j of word k holds slot 4j + k), sum, append S.
             uint32_t X[4];
@@ -495,7 +596,7 @@ __device__ __forceinline__ void count_unsat_word(const uint32_t *words, const ui
 // ---------------------------------------------------------------------------
 constexpr uint32_t kSpinLimit = 1u << 20;   // polls of a partner's flag before giving up
 
-template <int LAYOUT, int PARTS>
+template <int LAYOUT, int PARTS, int RNG>
 __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restrict__ jobs,
                                                           const uint32_t *__restrict__ units, int n_units,
                                                           uint32_t *queue)
@@ -503,6 +604,7 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
     constexpr int SPW = Layout<LAYOUT>::kSlotsPerWord;
     constexpr bool SPLIT = PARTS > 1;
     static_assert(!SPLIT || LAYOUT == 0, "split ladders are CAMSC only");
+    static_assert(RNG == 0 || LAYOUT == 0, "plane draws are CAMSC only");
     extern __shared__ __align__(16) uint8_t smem_raw[];
     __shared__ uint32_t s_next;
 
@@ -537,7 +639,7 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
         const float invL = jd.invL, invH = jd.invH;
         const uint32_t r = (uint32_t)(ladder >> 1);
         const uint32_t copy = (uint32_t)(ladder & 1);
-        const uint32_t c3flip = (kDomainFlip << 28) | (copy << 24);
+        const uint32_t c3flip = ((RNG == 1 ? kDomainPlane : kDomainFlip) << 28) | (copy << 24);
         const uint32_t c3swap = (kDomainSwap << 28) | (copy << 24);
         const uint32_t k0 = jd.key0, k1 = jd.key1;
         const uint32_t segw = jd.seg_bits;
@@ -570,6 +672,10 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
             sm.thr[idx] = slot < n_T ? sm.fthr[sm.perm[slot] * kThrCols + (idx % kThrCols)] : 0u;
         }
         __syncthreads();
+        if (RNG == 1) {
+            build_ptab(sm, NW, wave, nwaves, lane);
+            __syncthreads();
+        }
         const uint32_t *stab = n_swap_lds ? sm.stab : jd.swap_thr;
         const uint32_t *slist = n_sites_lds ? sm.sites : jd.sites;
 
@@ -610,17 +716,17 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                     const uint32_t ts = t + (uint32_t)s;
                     if (even) {
                         for (int j = tid; j < half; j += nthr)
-                            update_site<LAYOUT, false, SPLIT>(sm, checker_site(j, 0, L, invH, invL), N, gw, g0, n_T,
+                            update_site<LAYOUT, false, SPLIT, RNG>(sm, checker_site(j, 0, L, invH, invL), N, gw, g0, n_T,
                                                               ts, r, c3flip, k0, k1, segw, nullptr, 0, gb, ngr_own);
                         __syncthreads();
                         if (fused_energy && swap_now && s == chunk - 1) {
                             for (int j = tid; j < half; j += nthr)
-                                update_site<LAYOUT, true, SPLIT>(sm, checker_site(j, 1, L, invH, invL), N, gw, g0,
+                                update_site<LAYOUT, true, SPLIT, RNG>(sm, checker_site(j, 1, L, invH, invL), N, gw, g0,
                                                                  n_T, ts, r, c3flip, k0, k1, segw, P, np_b, gb,
                                                                  ngr_own);
                         } else {
                             for (int j = tid; j < half; j += nthr)
-                                update_site<LAYOUT, false, SPLIT>(sm, checker_site(j, 1, L, invH, invL), N, gw, g0,
+                                update_site<LAYOUT, false, SPLIT, RNG>(sm, checker_site(j, 1, L, invH, invL), N, gw, g0,
                                                                   n_T, ts, r, c3flip, k0, k1, segw, nullptr, 0, gb,
                                                                   ngr_own);
                         }
@@ -629,7 +735,7 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                         for (int c = 0; c < jd.n_classes; ++c) {
                             const int end = jd.class_off[c + 1];
                             for (int it = jd.class_off[c] + tid; it < end; it += nthr)
-                                update_site<LAYOUT>(sm, neighbours_packed(slist[it], L), N, gw, g0, n_T, ts, r,
+                                update_site<LAYOUT, false, false, RNG>(sm, neighbours_packed(slist[it], L), N, gw, g0, n_T, ts, r,
                                                     c3flip, k0, k1, segw);
                             __syncthreads();
                         }
@@ -746,6 +852,10 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                     sm.U[lane] = 0;   // consumed
                 }
                 __syncthreads();
+                if (RNG == 1) {
+                    build_ptab(sm, NW, wave, nwaves, lane);
+                    __syncthreads();
+                }
             } else if (swap_now) {
                 __syncthreads();
                 if (tid < kMaxTemps) sm.U[tid] = 0;
@@ -924,16 +1034,24 @@ hipError_t launch_init_spins(const JobDesc *d_job, const JobDesc &h, int layout,
     return hipGetLastError();
 }
 
-hipError_t sweep_set_lds(int layout, size_t lds)
+// Sweep kernel variants: kv = 0 CAMSC, 1 AMSC4, 2 CAMSC with plane draws.
+static const void *sweep_fn(int kv, int parts)
+{
+    if (kv == 1) return (const void *)sweep_kernel<1, 1, 0>;
+    if (kv == 2)
+        return parts == 4 ? (const void *)sweep_kernel<0, 4, 1>
+                          : (parts == 2 ? (const void *)sweep_kernel<0, 2, 1> : (const void *)sweep_kernel<0, 1, 1>);
+    return parts == 4 ? (const void *)sweep_kernel<0, 4, 0>
+                      : (parts == 2 ? (const void *)sweep_kernel<0, 2, 0> : (const void *)sweep_kernel<0, 1, 0>);
+}
+
+hipError_t sweep_set_lds(int kv, size_t lds)
 {
     // the attribute is process-wide per kernel; raise it only when a launch needs more
-    static std::atomic<size_t> set_max[2] = {{0}, {0}};
-    std::atomic<size_t> &cur = set_max[layout ? 1 : 0];
+    static std::atomic<size_t> set_max[3] = {{0}, {0}, {0}};
+    std::atomic<size_t> &cur = set_max[kv];
     if (lds <= cur.load()) return hipSuccess;
-    hipError_t e = layout == 0 ? hipFuncSetAttribute((const void *)sweep_kernel<0, 1>,
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
-                               : hipFuncSetAttribute((const void *)sweep_kernel<1, 1>,
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute(sweep_fn(kv, 1), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e == hipSuccess) {
         size_t prev = cur.load();
         while (prev < lds && !cur.compare_exchange_weak(prev, lds)) {
@@ -943,26 +1061,21 @@ hipError_t sweep_set_lds(int layout, size_t lds)
 }
 
 hipError_t launch_sweep(const JobDesc *d_jobs, int n_jobs, const uint32_t *d_units, int n_units, uint32_t *d_queue,
-                        int layout, int block_threads, size_t lds, int grid, hipStream_t s)
+                        int kv, int block_threads, size_t lds, int grid, hipStream_t s)
 {
-    hipError_t e = sweep_set_lds(layout, lds);
+    hipError_t e = sweep_set_lds(kv, lds);
     if (e != hipSuccess) return e;
-    if (layout == 0)
-        hipLaunchKernelGGL((sweep_kernel<0, 1>), dim3(grid), dim3(block_threads), lds, s, d_jobs, d_units, n_units,
-                           d_queue);
-    else
-        hipLaunchKernelGGL((sweep_kernel<1, 1>), dim3(grid), dim3(block_threads), lds, s, d_jobs, d_units, n_units,
-                           d_queue);
-    e = hipGetLastError();
+    void *args[] = {(void *)&d_jobs, (void *)&d_units, (void *)&n_units, (void *)&d_queue};
+    e = hipLaunchKernel(sweep_fn(kv, 1), dim3(grid), dim3(block_threads), args, lds, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(advance_kernel, dim3((n_jobs + 255) / 256), dim3(256), 0, s, d_jobs, n_jobs, d_queue);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_split(const JobDesc *d_job, int ladders, int parts, int block_threads, size_t lds,
+hipError_t launch_sweep_split(const JobDesc *d_job, int ladders, int parts, int kv, int block_threads, size_t lds,
                               uint32_t *d_queue, hipStream_t s)
 {
-    const void *fn = parts == 4 ? (const void *)sweep_kernel<0, 4> : (const void *)sweep_kernel<0, 2>;
+    const void *fn = sweep_fn(kv, parts);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     // partners share blockIdx mod 8: ladder l, part p -> block (l / 8) * 8 * parts + p * 8 + l % 8
@@ -976,12 +1089,10 @@ hipError_t launch_sweep_split(const JobDesc *d_job, int ladders, int parts, int 
     return hipGetLastError();
 }
 
-int sweep_split_max_blocks_per_cu(int parts, int block_threads, size_t lds)
+int sweep_split_max_blocks_per_cu(int parts, int kv, int block_threads, size_t lds)
 {
     int n = 0;
-    hipError_t e = parts == 4
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_kernel<0, 4>, block_threads, lds)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_kernel<0, 2>, block_threads, lds);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_fn(kv, parts), block_threads, lds);
     return e == hipSuccess ? n : 0;
 }
 
@@ -1016,14 +1127,10 @@ hipError_t launch_pack(const JobDesc *d_job, const JobDesc &h, int layout, const
     return hipGetLastError();
 }
 
-int sweep_max_blocks_per_cu(int layout, int block_threads, size_t lds)
+int sweep_max_blocks_per_cu(int kv, int block_threads, size_t lds)
 {
     int n = 0;
-    hipError_t e;
-    if (layout == 0)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_kernel<0, 1>, block_threads, lds);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_kernel<1, 1>, block_threads, lds);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_fn(kv, 1), block_threads, lds);
     return e == hipSuccess ? n : 0;
 }
 

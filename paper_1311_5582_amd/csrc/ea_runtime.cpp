@@ -19,7 +19,7 @@ namespace ea {
 
 // Device arrays of one launch: descriptors, unit list, work-queue counter.
 struct LaunchSet {
-    int layout = 0;
+    int layout = 0;   // kernel variant (kernel_variant of the jobs' layout and draw stream)
     int n_jobs = 0;
     int n_units = 0;
     int bt = 0;
@@ -105,6 +105,7 @@ static int validate_jobs(ea_sim *const *sims, int n_sims, const int64_t *n_sweep
         const ea_sim *s = sims[j];
         if (!s) return fail(EA_EINVAL, "sims[%d] is NULL", j);
         if (s->layout != sims[0]->layout) return fail(EA_EINVAL, "sims[%d] has a different layout", j);
+        if (s->h.rng != sims[0]->h.rng) return fail(EA_EINVAL, "sims[%d] has a different flip-draw stream", j);
         if (s->device != sims[0]->device) return fail(EA_EINVAL, "sims[%d] lives on another device", j);
         if (n_sweeps[j] < 0 || n_sweeps[j] > 0x7FFFFFFF) return fail(EA_EINVAL, "n_sweeps[%d] out of range", j);
         if (swap_every[j] < 0) return fail(EA_EINVAL, "swap_every[%d] < 0", j);
@@ -293,12 +294,14 @@ int ea_sweep_batch(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps, con
         s->h.swap_every = swap_every[0];
         EA_HIP(hipMemcpyAsync(&s->d_job->n_sweeps, &s->h.n_sweeps, 2 * sizeof(int32_t), hipMemcpyHostToDevice, st));
         if (s->split_parts > 1) {
-            EA_HIP(launch_sweep_split(s->d_job, s->h.ladders, s->split_parts, s->block_threads, s->lds,
+            EA_HIP(launch_sweep_split(s->d_job, s->h.ladders, s->split_parts, kernel_variant(s->layout, s->h.rng),
+                                      s->block_threads, s->lds,
                                       s->d_counters + 1, st));
         } else {
             int grid = 0;
-            if (int rc = device_grid(s->layout, s->block_threads, s->lds, s->h.ladders, &grid)) return rc;
-            EA_HIP(launch_sweep(s->d_job, 1, s->d_units, s->h.ladders, s->d_counters + 1, s->layout,
+            const int kv = kernel_variant(s->layout, s->h.rng);
+            if (int rc = device_grid(kv, s->block_threads, s->lds, s->h.ladders, &grid)) return rc;
+            EA_HIP(launch_sweep(s->d_job, 1, s->d_units, s->h.ladders, s->d_counters + 1, kv,
                                 s->block_threads, s->lds, grid, st));
         }
         s->t += n_sweeps[0];
@@ -317,7 +320,7 @@ int ea_sweep_batch(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps, con
         lds[j] = sims[j]->lds;
     }
     LaunchSet ls;
-    int rc = launchset_build(ls, descs, lds, s0->layout, 0, st);
+    int rc = launchset_build(ls, descs, lds, kernel_variant(s0->layout, s0->h.rng), 0, st);
     if (rc == EA_OK) rc = launchset_launch(ls, st);
     if (rc == EA_OK) {
         hipError_t e = hipStreamSynchronize(st);
@@ -388,9 +391,11 @@ int ea_plan_create(ea_sim *const *sims, int n_sims, int sweeps_per_step, const i
     }
     int bt = opt.block_threads;
     if (bt == 0 && opt.autotune) {
-        if (int rc = autotune_bt(descs, lds, sims[0]->layout, p->stream, &bt)) return bail(rc);
+        if (int rc = autotune_bt(descs, lds, kernel_variant(sims[0]->layout, sims[0]->h.rng), p->stream, &bt))
+            return bail(rc);
     }
-    if (int rc = launchset_build(p->ls, descs, lds, sims[0]->layout, bt, p->stream)) return bail(rc);
+    if (int rc = launchset_build(p->ls, descs, lds, kernel_variant(sims[0]->layout, sims[0]->h.rng), bt, p->stream))
+        return bail(rc);
     if (p->use_graph && p->ls.n_units > 0) {
         hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {

@@ -94,6 +94,9 @@ int ea_server_create(const ea_server_options *opt_in, ea_server **out)
     if (opt_in) opt = *opt_in;
     if (opt.quantum_sweeps < 1) return fail(EA_EINVAL, "quantum_sweeps < 1");
     if (opt.layout != EA_LAYOUT_CAMSC && opt.layout != EA_LAYOUT_AMSC4) return fail(EA_EINVAL, "unknown layout");
+    if (opt.rng != EA_RNG_WORDS && opt.rng != EA_RNG_PLANES) return fail(EA_EINVAL, "unknown rng");
+    if (opt.rng == EA_RNG_PLANES && opt.layout != EA_LAYOUT_CAMSC)
+        return fail(EA_EINVAL, "plane draws need the CAMSC layout");
     if (opt.max_active < 0 || opt.max_active > 4095) return fail(EA_EINVAL, "max_active outside [0, 4095]");
     ea_server *sv = new (std::nothrow) ea_server;
     if (!sv) return fail(EA_ENOMEM, "host allocation failed");
@@ -159,6 +162,7 @@ int ea_server_step(ea_server *sv, int *n_running, int *n_queued, int *n_finished
         ea_options o;
         ea_default_options(&o);
         o.layout = sv->opt.layout;
+        o.rng = sv->opt.rng;
         o.stream = sv->stream;
         const int rc = ea_create(j->L, j->J.data(), j->betas.data(), j->n_T, j->R, j->seed, &o, &j->sim);
         if (rc != EA_OK) {

@@ -44,7 +44,7 @@ def test_swap_thresholds_match_oracle(lib, oracle_lib):
             assert B.swap_threshold(db, n) == oracle_lib.swap_threshold(db, n), (db, n)
 
 
-def _create(lib, L=4, n_T=4, R=1, J=None, betas=None, layout=0, block_threads=0, words_resident=0, split=0):
+def _create(lib, L=4, n_T=4, R=1, J=None, betas=None, layout=0, block_threads=0, words_resident=0, split=0, rng=0):
     if J is None:
         J = inputs.couplings(L, R, seed=1) if L >= 2 else np.ones((R, max(L, 1) ** 3, 3), np.int8)
     if betas is None:
@@ -54,6 +54,7 @@ def _create(lib, L=4, n_T=4, R=1, J=None, betas=None, layout=0, block_threads=0,
     opt = B.Options()
     lib.ea_default_options(ctypes.byref(opt))
     opt.layout, opt.block_threads, opt.words_resident, opt.split = layout, block_threads, words_resident, split
+    opt.rng = rng
     h = ctypes.c_void_p()
     rc = lib.ea_create(L, J.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
                        b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n_T, R, 7, ctypes.byref(opt),
@@ -66,6 +67,7 @@ def _create(lib, L=4, n_T=4, R=1, J=None, betas=None, layout=0, block_threads=0,
     dict(layout=2), dict(block_threads=100), dict(block_threads=2048), dict(block_threads=64, L=24),
     dict(betas=[1.0, 0.0, 0.5, 0.2]), dict(betas=[1.0, -1.0, 0.5, 0.2]), dict(betas=[1.0, float("nan"), 0.5, 0.2]),
     dict(betas=[1.0, float("inf"), 0.5, 0.2]), dict(words_resident=-1), dict(split=3), dict(split=-1),
+    dict(rng=2), dict(rng=-1), dict(rng=1, layout=1),
     dict(L=32, n_T=64, words_resident=2, J=np.ones((1, 32 ** 3, 3), np.int8)),
 ])
 def test_create_rejects_invalid_arguments(lib, case):

@@ -55,6 +55,57 @@ def test_philox_matches_rocrand(oracle_lib, rocrand_probe):
         assert list(oracle_lib.philox4x32_10(c, k)) == ref
 
 
+def test_plane_draws_are_rocrand_blocks_transposed(oracle_lib, rocrand_probe):
+    """The bit-plane stream: plane p of half h is a 16-bit field of a Philox
+    block; transposing rocRAND's blocks with numpy must give each slot's
+    uniform (bit 31 - p of the uniform = bit slot & 15 of plane p)."""
+    rng = np.random.default_rng(7)
+    cases = []
+    for n in range(12):
+        seed = int(rng.integers(0, 2 ** 63)) if n else 0
+        i, t, r, c = (int(rng.integers(0, 2 ** 32)), int(rng.integers(0, 2 ** 30)), int(rng.integers(0, 2 ** 20)),
+                      n & 1)
+        cases.append((seed, i, t, r, c))
+    rows = []
+    for seed, i, t, r, c in cases:
+        for h in range(4):
+            for g in range(4):
+                rows.append((i, t, r, (4 << 28) | (c << 24) | (h << 8) | g, seed & 0xFFFFFFFF, seed >> 32))
+    text = "\n".join(" ".join(str(v) for v in row) for row in rows) + "\n"
+    res = subprocess.run([rocrand_probe], input=text, capture_output=True, text=True, check=True)
+    blocks = np.array([list(map(int, line.split())) for line in res.stdout.strip().splitlines()], dtype=np.uint64)
+    blocks = blocks.reshape(len(cases), 4, 4, 4)          # case, half, group, word
+    for n, (seed, i, t, r, c) in enumerate(cases):
+        for h in range(4):
+            words = blocks[n, h].reshape(16)              # plane pair p>>1 = 4 g + word
+            planes = np.empty(32, dtype=np.uint64)
+            planes[0::2] = words & 0xFFFF
+            planes[1::2] = words >> 16
+            bits = (planes[:, None] >> np.arange(16, dtype=np.uint64)[None, :]) & 1   # [plane][slot in half]
+            uniform = (bits << (31 - np.arange(32, dtype=np.uint64))[:, None]).sum(axis=0)
+            for q in range(16):
+                assert oracle_lib.flip_draw(seed, "planes", i, t, r, c, 16 * h + q) == int(uniform[q])
+
+
+def test_plane_draws_uniform_and_independent(oracle_lib):
+    """Uniforms of the bit-plane stream: top bits equidistributed, slots of one
+    site (inside a half and across halves) uncorrelated and distinct."""
+    U = np.array([[oracle_lib.flip_draw(99, "planes", i, 3, 1, 0, s) for s in range(64)] for i in range(400)],
+                 dtype=np.float64)
+    top = (U // 2 ** 28).astype(int).ravel()
+    counts = np.bincount(top, minlength=16)
+    chi2 = float(((counts - top.size / 16) ** 2 / (top.size / 16)).sum())
+    assert chi2 < 45.0                                   # 15 d.o.f., p ~ 1e-4
+    x = U / 2 ** 32 - 0.5
+    for a, b in ((0, 1), (14, 15), (15, 16), (0, 16), (31, 32), (5, 63)):
+        corr = float(np.mean(x[:, a] * x[:, b]) / np.sqrt(np.mean(x[:, a] ** 2) * np.mean(x[:, b] ** 2)))
+        assert abs(corr) < 0.2, (a, b, corr)
+    assert all(len(set(row)) == 64 for row in U.astype(np.int64).tolist())
+    # the other stream is untouched by the option
+    assert oracle_lib.flip_draw(99, "words", 5, 3, 1, 0, 6) == int(
+        oracle_lib.philox4x32_10([5, 3, 1, (0 << 28) | (0 << 24) | 1], [99, 0])[2])
+
+
 # --------------------------------------------------------------------------
 # Integer probability tables (Sec. 4.3.1, 4.3.2)
 # --------------------------------------------------------------------------
@@ -216,17 +267,18 @@ def test_gauge_invariance(oracle_lib):
         assert np.array_equal(d.spins, -c.spins)
 
 
-def test_exact_boltzmann_distribution_L2(oracle_lib):
+@pytest.mark.parametrize("stream", ["words", "planes"])
+def test_exact_boltzmann_distribution_L2(oracle_lib, stream):
     """Time averages at every temperature index against exact enumeration of
     the 2^8 states of the L = 2 lattice (24 bonds), including the expected
     swap acceptance of every pair; the bound is 5 standard errors estimated
-    from batch means."""
+    from batch means.  Both flip-draw streams obey the same law."""
     L, R = 2, 24
     J1 = inputs.couplings(L, 1, seed=2024)[0]
     J = np.repeat(J1[None], R, axis=0)
     betas = np.array([1.1, 0.75, 0.5, 0.3])
     n_T = len(betas)
-    sim = _sim(oracle_lib, L, J, betas, seed=7, stats=True)
+    sim = _sim(oracle_lib, L, J, betas, seed=7, stats=True, rng=stream)
     spectrum = bf.enumerate_energies(L, J1)
     sim.sweep(200, 1)                                       # burn-in
     sim.flip_tries[...] = 0

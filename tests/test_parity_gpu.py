@@ -29,15 +29,16 @@ def _report(tag, **kw):
 
 
 def run_pair(oracle_lib, L, R, n_T, seed, sweeps, swap_every, layout="camsc", t_min=0.4, t_max=2.0,
-             rids=None, block_threads=0, words_resident=0, couplings=None, splits=None):
+             rids=None, block_threads=0, words_resident=0, couplings=None, splits=None, rng="words", split=True):
     """Run the GPU on all R realizations and the oracle on `rids`; compare."""
     _report("run", L=L, R=R, n_T=n_T, seed=seed, sweeps=sweeps, swap_every=swap_every, layout=layout,
-            bt=block_threads, wr=words_resident)
+            bt=block_threads, wr=words_resident, rng=rng, split=split)
     J = inputs.couplings(L, R, seed) if couplings is None else couplings
     betas = inputs.geometric_betas(n_T, t_min, t_max)
     rids = list(range(R)) if rids is None else list(rids)
-    sim = B.Sim(L, J, betas, seed, layout=layout, block_threads=block_threads, words_resident=words_resident)
-    orc = oracle_lib.OracleSim(L, J[rids], betas, seed, rid=np.array(rids))
+    sim = B.Sim(L, J, betas, seed, layout=layout, block_threads=block_threads, words_resident=words_resident,
+                rng=rng, split=split)
+    orc = oracle_lib.OracleSim(L, J[rids], betas, seed, rid=np.array(rids), rng=rng)
     s0, p0, t0 = sim.state()
     assert t0 == 0
     assert np.array_equal(s0[rids], orc.spins), "initial spins differ"
@@ -218,3 +219,24 @@ def test_split_ladders_equal_unsplit(oracle_lib, L, R, n_T, swap_every):
     orc.sweep(20, swap_every)
     assert np.array_equal(a.state()[0], orc.spins)
     assert np.array_equal(a.swap_acceptance(), b.swap_acceptance())
+
+
+@pytest.mark.parametrize("L,R,n_T,swap_every,split,bt,wr", [
+    (8, 1, 16, 1, True, 0, 0),        # the single small job
+    (6, 3, 13, 1, False, 0, 0),       # ragged: one partial half
+    (5, 2, 22, 1, True, 0, 0),        # odd L (three colour classes), two halves, ragged
+    (4, 2, 40, 2, True, 0, 0),        # two words per site
+    (8, 1, 64, 3, False, 64, 1),      # four halves, second word staged through HBM, 64 threads
+    (16, 2, 32, 1, "always", 0, 0),   # split ladders, one half per part
+    (10, 1, 32, 0, "always", 0, 0),   # split in 4 parts: quarter halves
+    (6, 3, 24, 3, "always", 0, 0),    # split in 2: the second part spans both halves
+    (2, 2, 4, 1, False, 0, 0),        # smallest lattice
+])
+def test_plane_draws_equal_oracle(oracle_lib, L, R, n_T, swap_every, split, bt, wr):
+    """The bit-plane flip-draw stream: bit for bit the oracle's chain."""
+    sim, *_ = run_pair(oracle_lib, L, R, n_T, 4000 + 13 * L + n_T, 21, swap_every, rng="planes", split=split,
+                       block_threads=bt, words_resident=wr, splits=[1, 9, 11])
+    info = sim.info()
+    print(f"[parity] planes launch {info}", flush=True)
+    if split == "always":
+        assert info["split_parts"] > 1
