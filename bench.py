@@ -77,6 +77,30 @@ def cpu_baseline(L, n_T, t_min, t_max, seed, sweeps, threads):
                       f"PT every sweep ({flips:.3g} flip attempts, {dt:.1f} s wall)"}
 
 
+def bench_other_stream(B, torch, L, J, betas, seed, layout, block_threads, split, rng, sweeps, swap_every, steps):
+    """The same workload and launch with the other flip-draw stream (kernel time
+    from HIP events on the launch stream, wall time around the steps)."""
+    stream = torch.cuda.Stream()
+    sim = B.Sim(L, J, betas, seed, layout=layout, block_threads=block_threads, stream=stream, split=split, rng=rng)
+    sim.sweep(sweeps, swap_every)
+    sim.observables()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        sim.sweep(sweeps, swap_every)
+        b.record(stream)
+        sim.observables()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    flips = sweeps * L ** 3 * len(betas) * J.shape[0] * 2
+    kern = float(np.mean([a.elapsed_time(b) for a, b in evs])) / 1e3
+    sim.close()
+    return {"rng": rng, "steps": steps, "ps_per_flip": round(wall / (flips * steps) * 1e12, 4),
+            "kernel_ps_per_flip": round(kern / flips * 1e12, 4)}
+
+
 def flips_of(job, sweeps):
     return sweeps * job["L"] ** 3 * job["n_T"] * job["R"] * 2
 
@@ -154,6 +178,8 @@ def main():
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--rng", default="words", choices=["words", "planes"],
                     help="flip-draw stream: one Philox word per flip, or bit planes compared MSB first")
+    ap.add_argument("--no-other-stream", action="store_true",
+                    help="skip timing the same workload with the other flip-draw stream")
     ap.add_argument("--no-split", action="store_true",
                     help="one workgroup per ladder even when the job has fewer ladders than compute units")
     ap.add_argument("--swap-every", type=int, default=-1, help="override the workload's PT interval")
@@ -254,6 +280,10 @@ def main():
                                                         launch["split_parts"])},
     }
     sim.close()
+    if not args.no_other_stream and args.layout == "camsc":
+        other = "planes" if args.rng == "words" else "words"
+        out["other_stream"] = bench_other_stream(B, torch, L, J, betas, cfg["seed"], args.layout, args.block_threads,
+                                                 not args.no_split, other, S, se, 3)
     if not args.no_batched:
         out["batched"] = bench_batched(B, inputs, torch, args.batched_sweeps, args.batched_steps)
     if not args.no_serving:

@@ -6,6 +6,7 @@ one spin per byte and shares no code with the HIP path; see ea_oracle.c for
 the definition it implements and the paper sections each step follows.
 """
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -67,6 +68,8 @@ def lib():
         L.orc_sweep.restype = ctypes.c_int
         L.orc_observables.argtypes = [ctypes.POINTER(_OrcSim), _i32p, _i32p]
         L.orc_observables.restype = None
+        L.orc_measure.argtypes = [ctypes.POINTER(_OrcSim), _i64p, _i64p, ctypes.POINTER(ctypes.c_uint64), _i64p]
+        L.orc_measure.restype = None
         _lib = L
     return _lib
 
@@ -187,3 +190,38 @@ class OracleSim:
         overlap = np.zeros((self.R, self.n_T), dtype=np.int32)
         lib().orc_observables(ctypes.byref(self._s), _ptr(energy, ctypes.c_int32), _ptr(overlap, ctypes.c_int32))
         return energy, overlap
+
+    def new_measurements(self):
+        """Zeroed accumulators: count, sum_q2 [R][n_T], sum_q4 [R][n_T][2] (lo, hi), sum_c [R][n_T][L]."""
+        return (np.zeros((self.R, self.n_T), np.int64), np.zeros((self.R, self.n_T), np.int64),
+                np.zeros((self.R, self.n_T, 2), np.uint64), np.zeros((self.R, self.n_T, self.L), np.int64))
+
+    def measure(self, acc):
+        """Add one measurement of the current state into `acc` (from new_measurements)."""
+        count, q2, q4, c = acc
+        lib().orc_measure(ctypes.byref(self._s), _ptr(count, ctypes.c_int64), _ptr(q2, ctypes.c_int64),
+                          _ptr(q4, ctypes.c_uint64), _ptr(c, ctypes.c_int64))
+        return acc
+
+
+def binder_and_xi(acc, L):
+    """Spin-glass Binder ratio g = (3 - [<q^4>] / [<q^2>]^2) / 2 and correlation
+    length over L per temperature index from measurement accumulators; [.] is
+    the average over realizations.  xi = sqrt(chi(0) / chi(k) - 1) / (2 sin(k / 2))
+    with k = 2 pi / L along each axis, chi(0) = [<q^2>] / N and chi(k) the
+    axis-averaged [<|sum_i q_i e^{i k x}|^2>] / N = [<sum_d C[d] cos(k d)>] / (3 N);
+    nan where chi(0) / chi(k) < 1."""
+    count, q2, q4, c = acc
+    N = L ** 3
+    n = count.astype(np.float64)
+    m2 = (q2 / n).mean(axis=0)
+    q4v = q4[..., 0].astype(np.float64) + q4[..., 1].astype(np.float64) * 2.0 ** 64
+    m4 = (q4v / n).mean(axis=0)
+    g = 0.5 * (3.0 - m4 / (m2 * m2))
+    k = 2.0 * math.pi / L
+    w = np.cos(k * np.arange(L))
+    chik = ((c @ w) / n / (3.0 * N)).mean(axis=0)
+    chi0 = m2 / N
+    ratio = chi0 / chik
+    xi = np.where(ratio >= 1.0, np.sqrt(np.maximum(ratio - 1.0, 0.0)) / (2.0 * math.sin(k / 2.0)), np.nan)
+    return g, xi / L

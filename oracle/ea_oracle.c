@@ -418,3 +418,59 @@ void orc_observables(const orc_sim *sim, int32_t *energy, int32_t *overlap)
             }
     }
 }
+
+/* ---------------------------------------------------------------------- */
+/* Measurements of the spin-glass order [Sec. 5: Binder ratio of the      */
+/* overlap, correlation length].  For realization r and temperature index */
+/* k, with q_i = s_i(copy 0 at T_k) s_i(copy 1 at T_k):                   */
+/*   q        = sum_i q_i                                                  */
+/*   Q_a[p]   = sum of q_i over the sites whose coordinate a (x, y, z) is p */
+/*   C[d]     = sum_a sum_p Q_a[p] Q_a[(p + d) mod L],  d = 0 .. L-1        */
+/* so that |sum_i q_i e^{i k x_a}|^2 summed over the three axes equals     */
+/* sum_d C[d] cos(k d) for k = 2 pi m / L.  One call adds one measurement: */
+/* count += 1, sum_q2 += q^2, sum_q4 += q^4 (exact, 128 bits as lo, hi),   */
+/* sum_c[d] += C[d].                                                        */
+/* ---------------------------------------------------------------------- */
+void orc_measure(const orc_sim *sim, int64_t *count, int64_t *sum_q2, uint64_t *sum_q4, int64_t *sum_c)
+{
+    int L = sim->L, n_T = sim->n_T;
+    int64_t Q[3][32];
+    for (int r = 0; r < sim->R; ++r) {
+        int32_t slot_of_temp[2][ORC_MAX_TEMPS];
+        for (int c = 0; c < 2; ++c) {
+            const int32_t *temp_of_slot = orc_perm(sim, r, c);
+            for (int slot = 0; slot < n_T; ++slot) slot_of_temp[c][temp_of_slot[slot]] = slot;
+        }
+        for (int k = 0; k < n_T; ++k) {
+            const int8_t *s0 = orc_spins(sim, r, 0, slot_of_temp[0][k]);
+            const int8_t *s1 = orc_spins(sim, r, 1, slot_of_temp[1][k]);
+            int64_t q = 0;
+            for (int a = 0; a < 3; ++a)
+                for (int p = 0; p < L; ++p) Q[a][p] = 0;
+            for (int z = 0; z < L; ++z)
+                for (int y = 0; y < L; ++y)
+                    for (int x = 0; x < L; ++x) {
+                        int i = orc_site(L, x, y, z);
+                        int qi = s0[i] * s1[i];
+                        q += qi;
+                        Q[0][x] += qi;
+                        Q[1][y] += qi;
+                        Q[2][z] += qi;
+                    }
+            size_t rk = (size_t)r * n_T + k;
+            count[rk] += 1;
+            sum_q2[rk] += q * q;
+            /* q^4 < 2^61 for N <= 32^3; 128-bit sum as two words */
+            uint64_t q4 = (uint64_t)(q * q) * (uint64_t)(q * q);
+            uint64_t lo = sum_q4[2 * rk] + q4;
+            sum_q4[2 * rk + 1] += (lo < q4) ? 1u : 0u;
+            sum_q4[2 * rk] = lo;
+            for (int d = 0; d < L; ++d) {
+                int64_t cd = 0;
+                for (int a = 0; a < 3; ++a)
+                    for (int p = 0; p < L; ++p) cd += Q[a][p] * Q[a][(p + d) % L];
+                sum_c[rk * (size_t)L + d] += cd;
+            }
+        }
+    }
+}

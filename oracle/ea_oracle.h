@@ -53,4 +53,8 @@ int orc_sweep(orc_sim *sim, int64_t n_sweeps, int swap_every);
 /* energy [R][2][n_T] by temperature index; overlap [R][n_T] (either may be NULL) */
 void orc_observables(const orc_sim *sim, int32_t *energy, int32_t *overlap);
 
+/* one measurement of the overlap moments and plane-sum autocorrelations,
+ * added to count/sum_q2 [R][n_T], sum_q4 [R][n_T][2] (lo, hi), sum_c [R][n_T][L] */
+void orc_measure(const orc_sim *sim, int64_t *count, int64_t *sum_q2, uint64_t *sum_q4, int64_t *sum_c);
+
 #endif

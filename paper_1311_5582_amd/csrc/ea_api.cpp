@@ -249,7 +249,9 @@ static int choose_split(const ea_sim *s, int split_opt)
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, s->device) != hipSuccess || !coop) return 1;
     for (int parts : {4, 2}) {
         if (ngr % parts != 0 || ladders * parts > cus) continue;
-        // a small lattice is latency-bound: the exchange costs more than the split saves
+        // never more workgroups than CUs (measured: 4 parts x 512 threads, two per CU, is
+        // slower than 2 parts x 1024); a small lattice is latency-bound: the exchange
+        // costs more than the split saves
         if (split_opt == 0 && (int64_t)s->N * (ngr / parts) < 2048) continue;
         const int blocks = (ladders + 7) / 8 * 8 * parts;
         const int per_cu = sweep_split_max_blocks_per_cu(parts, kernel_variant(s->layout, s->h.rng),

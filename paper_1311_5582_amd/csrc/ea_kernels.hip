@@ -787,28 +787,35 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                         sm.U[tid] = (int32_t)(uint32_t)v;
                     }
                 }
-                if (wave == 0 && lane < pairs)
+                // the last wave draws (wave 0 may still be waiting for partners)
+                if (wave == nwaves - 1 && lane < pairs)
                     sm.draw[lane] = philox10((uint32_t)lane, tswap, r, c3swap, k0, k1).x;
                 __syncthreads();   // slot energies U and swap draws are in
                 // Bit k of col[j]: would pair k swap if the configuration that
                 // sat at position j before the pass had been carried up to k
-                // (j <= k)?  Waves take pairs in turn and OR their bits in.
-                const int u_mine = lane < n_T ? sm.U[sm.sot[lane]] : 0;
-                uint64_t colbits = 0;
-                for (int k = wave; k < pairs; k += nwaves) {
-                    if (lane <= k) {
-                        const int d = u_mine - sm.U[sm.sot[k + 1]];
-                        const int sg = sm.ssgn[k];
-                        bool acc = (sg == 0) || (d == 0) || ((sg > 0) == (d > 0));
-                        if (!acc) {
-                            const int n = d < 0 ? -d : d;
-                            const uint32_t thr = n < sm.slen[k] ? stab[sm.soff[k] + n] : 0u;
-                            acc = sm.draw[k] < thr;
-                        }
-                        if (acc) colbits |= 1ull << k;
+                // (j <= k)?  Waves take start positions j in turn, lanes the
+                // pairs k, so one ballot is col[j].  No data-dependent branch:
+                // a pair's table length is uniform and a non-empty table has
+                // entry 0.
+                {
+                    const int k = lane;
+                    const bool live = k < pairs;
+                    const int kk = live ? k : 0;
+                    const int u_next = sm.U[sm.sot[kk + 1]];
+                    const int sg = sm.ssgn[kk];
+                    const int len = sm.slen[kk];
+                    const int off = sm.soff[kk];
+                    const uint32_t dr = sm.draw[kk];
+                    for (int j = wave; j < pairs; j += nwaves) {
+                        const int d = sm.U[sm.sot[j]] - u_next;
+                        const int n = d < 0 ? -d : d;
+                        const uint32_t thr = len > 0 ? stab[off + min(n, len - 1)] : 0u;
+                        const bool favourable = (sg == 0) || (d == 0) || ((sg > 0) == (d > 0));
+                        const bool acc = live && k >= j && (favourable || (n < len && dr < thr));
+                        const uint64_t col = __ballot(acc);
+                        if (lane == 0) sm.mask[j] = col;
                     }
                 }
-                if (colbits) atomicOr((unsigned long long *)&sm.mask[lane], (unsigned long long)colbits);
                 __syncthreads();
                 if (wave == 0) {
                     // The ascending pass, visiting only its rejections: from

@@ -321,3 +321,79 @@ def test_exact_boltzmann_distribution_L2(oracle_lib, stream):
             p = 1.0 if u >= 3 else oracle_lib.flip_threshold(betas[k], u) / 2 ** 32
             got = sim.flip_acc[k, u] / n
             assert abs(got - p) <= 5 * math.sqrt(max(p * (1 - p), 1e-12) / n) + 1e-9, (k, u, got, p)
+
+
+# --------------------------------------------------------------------------
+# Measurements: overlap moments and plane-sum autocorrelations (Sec. 5)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("L", [2, 3, 4, 5])
+def test_measure_against_numpy_fft(oracle_lib, L):
+    """Plane sums, their autocorrelation and the overlap moments against a
+    numpy evaluation: |FFT of the plane sums|^2 summed over the axes equals
+    sum_d C[d] cos(2 pi m d / L) for every m; q^4 exactly in 128 bits."""
+    rng = np.random.default_rng(40 + L)
+    R, n_T = 2, 5
+    J = inputs.couplings(L, R, seed=L)
+    sim = _sim(oracle_lib, L, J, inputs.geometric_betas(n_T, 0.5, 2.0))
+    acc = sim.new_measurements()
+    expect_q2 = np.zeros((R, n_T), dtype=object)
+    expect_q4 = np.zeros((R, n_T), dtype=object)
+    expect_c = np.zeros((R, n_T, L), dtype=np.int64)
+    for rep in range(4):
+        spins = rng.choice(np.array([-1, 1], dtype=np.int8), size=sim.spins.shape)
+        perm = np.stack([np.stack([rng.permutation(n_T) for _ in range(2)]) for _ in range(R)]).astype(np.int32)
+        sim.set_state(spins, perm, 0)
+        sim.measure(acc)
+        for r in range(R):
+            sot = [np.argsort(perm[r, c]) for c in range(2)]
+            for k in range(n_T):
+                qf = (spins[r, 0, sot[0][k]].astype(np.int64) * spins[r, 1, sot[1][k]]).reshape(L, L, L)  # z, y, x
+                planes = [qf.sum(axis=(0, 1)), qf.sum(axis=(0, 2)), qf.sum(axis=(1, 2))]          # x, y, z
+                q = int(qf.sum())
+                expect_q2[r, k] += q * q
+                expect_q4[r, k] += q ** 4
+                for Q in planes:
+                    expect_c[r, k] += np.array([int(np.dot(Q, np.roll(Q, -d))) for d in range(L)])
+                # the FFT identity on this single measurement
+                c1 = sum(np.array([int(np.dot(Q, np.roll(Q, -d))) for d in range(L)]) for Q in planes)
+                power = sum(np.abs(np.fft.fft(Q)) ** 2 for Q in planes)
+                for m in range(L):
+                    assert abs(float(np.dot(c1, np.cos(2 * math.pi * m * np.arange(L) / L))) - power[m]) < 1e-6
+    count, q2, q4, c = acc
+    assert np.all(count == 4)
+    for r in range(R):
+        for k in range(n_T):
+            assert int(q2[r, k]) == expect_q2[r, k]
+            assert int(q4[r, k, 0]) + (int(q4[r, k, 1]) << 64) == expect_q4[r, k]
+    assert np.array_equal(c, expect_c)
+
+
+def test_binder_and_xi_closed_forms(oracle_lib):
+    """g = 1 when every measurement has |q| = N (identical copies); xi from an
+    Ornstein-Zernike form chi(k) = chi(0) / (1 + (2 sin(k/2))^2 xi^2) is
+    recovered exactly; a field uncorrelated between sites has xi = 0."""
+    L, R, n_T = 4, 3, 2
+    N = L ** 3
+    J = inputs.couplings(L, R, seed=1)
+    sim = _sim(oracle_lib, L, J, inputs.geometric_betas(n_T, 0.5, 2.0))
+    s = sim.spins.copy()
+    s[:, 1] = s[:, 0]
+    sim.set_state(s, np.tile(np.arange(n_T, dtype=np.int32), (R, 2, 1)), 0)
+    acc = sim.new_measurements()
+    for _ in range(3):
+        sim.measure(acc)
+    g, _ = oracle_lib.binder_and_xi(acc, L)
+    assert np.allclose(g, 1.0, rtol=0, atol=1e-12)
+    # synthetic accumulators with a prescribed chi(0) / chi(k)
+    k = 2 * math.pi / L
+    for xi in (0.0, 0.7, 2.5):
+        chi0 = 40.0
+        chik = chi0 / (1 + (2 * math.sin(k / 2)) ** 2 * xi ** 2)
+        # one realization, one temperature: C[d] = A + B cos(k d) gives sum_d C cos(k d) = B L / 2
+        q2 = chi0 * N
+        B = chik * 3 * N * 2 / L
+        A = (q2 * 3 - B * sum(math.cos(k * d) for d in range(L))) / L   # sum_d C[d] = 3 q^2
+        Cd = np.array([A + B * math.cos(k * d) for d in range(L)])
+        acc2 = (np.ones((1, 1), np.int64), np.array([[q2]]), np.zeros((1, 1, 2), np.uint64), Cd[None, None, :])
+        _, xl = oracle_lib.binder_and_xi(acc2, L)
+        assert abs(xl[0] * L - xi) < 1e-9

@@ -240,3 +240,20 @@ def test_plane_draws_equal_oracle(oracle_lib, L, R, n_T, swap_every, split, bt, 
     print(f"[parity] planes launch {info}", flush=True)
     if split == "always":
         assert info["split_parts"] > 1
+
+
+@pytest.mark.parametrize("rng", ["words", "planes"])
+def test_repeated_temperatures(oracle_lib, rng):
+    """Equal neighbouring inverse temperatures: that pair's swap table is empty
+    and every swap between them is accepted."""
+    L, R, seed = 6, 2, 321
+    J = inputs.couplings(L, R, seed)
+    betas = np.array([0.5, 0.5, 0.7, 0.7, 0.7, 1.0, 1.4])
+    sim = B.Sim(L, J, betas, seed, rng=rng)
+    orc = oracle_lib.OracleSim(L, J, betas, seed, rng=rng)
+    for n, se in ((7, 1), (5, 2)):
+        sim.sweep(n, se)
+        orc.sweep(n, se)
+    s, perm, t = sim.state()
+    assert np.array_equal(perm, orc.temp_of_slot) and np.array_equal(s, orc.spins)
+    assert np.array_equal(sim.observables()[0], orc.observables()[0])
