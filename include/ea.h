@@ -240,6 +240,32 @@ int ea_set_state(ea_sim *sim, const int8_t *spins, const int32_t *temp_of_slot,
  * [R][2][n_T-1] (n_T = 1: nothing written).  Synchronous. */
 int ea_swap_acceptance(ea_sim *sim, uint64_t *accepted);
 
+/* ---- Measurements of the spin-glass order (Sec. 5: Binder ratio of the overlap,
+ * correlation length) ----
+ * For realization r and temperature index k, with q_i = s_i(copy 0 at T_k) *
+ * s_i(copy 1 at T_k), q = sum_i q_i, and Q_a[p] the sum of q_i over the sites
+ * whose coordinate a (x, y, z) equals p:
+ *   C[d] = sum_a sum_p Q_a[p] Q_a[(p + d) mod L],   d = 0 .. L-1,
+ * so that the axis-summed |sum_i q_i exp(i k x_a)|^2 equals sum_d C[d] cos(k d).
+ * ea_measure adds one measurement of the current state to device-resident
+ * accumulators: count += 1, sum_q2 += q^2, sum_q4 += q^4 (exact, a 128-bit sum
+ * kept as two 64-bit words, low word first), sum_c[d] += C[d].  Asynchronous
+ * on the handle's stream when one was given, otherwise synchronous. */
+int ea_measure(ea_sim *sim);
+/* Copy the accumulators: count and sum_q2 int64 [R][n_T], sum_q4 uint64 [R][n_T][2],
+ * sum_c int64 [R][n_T][L]; any pointer may be NULL.  Synchronous. */
+int ea_measure_read(ea_sim *sim, int64_t *count, int64_t *sum_q2, uint64_t *sum_q4, int64_t *sum_c);
+/* Zero the accumulators (ea_create starts them at zero; ea_set_state keeps them). */
+int ea_measure_reset(ea_sim *sim);
+/* Per temperature index, from the accumulators with [.] the average over
+ * realizations of each realization's time average <.>:
+ *   binder[k]    = (3 - [<q^4>] / [<q^2>]^2) / 2,
+ *   xi_over_L[k] = sqrt(chi(0) / chi(k_min) - 1) / (2 sin(k_min / 2)) / L,
+ * chi(0) = [<q^2>] / N, chi(k_min) = [<sum_d C[d] cos(k_min d)>] / (3 N),
+ * k_min = 2 pi / L (NaN where chi(0) < chi(k_min)).  Host arithmetic in double
+ * on the exact sums.  EA_ESTATE if a realization has no measurement. */
+int ea_binder_xi(ea_sim *sim, double *binder, double *xi_over_L);
+
 /* Shape queries. */
 int ea_get_dims(const ea_sim *sim, int *L, int *n_T, int *n_realizations, int *layout);
 /* Launch plan of a lone ea_sweep: workgroup size, spin words resident in LDS,

@@ -109,6 +109,11 @@ def lib():
                                                 ctypes.POINTER(ctypes.c_size_t)]),
             "ea_sim_footprint": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_size_t)]),
             "ea_sim_info": (ctypes.c_int, [P, i32p, i32p, i32p, ctypes.POINTER(ctypes.c_size_t)]),
+            "ea_measure": (ctypes.c_int, [P]),
+            "ea_measure_read": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                               ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64)]),
+            "ea_measure_reset": (ctypes.c_int, [P]),
+            "ea_binder_xi": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -250,6 +255,34 @@ class Sim:
         p = np.ascontiguousarray(temp_of_slot, dtype=np.int32)
         check(lib().ea_set_state(self._h, _p(s, ctypes.c_int8), _p(p, ctypes.c_int32), int(sweeps_done)))
 
+    def measure(self):
+        """Add one measurement of the current state to the device accumulators."""
+        check(lib().ea_measure(self._h))
+
+    def measurements(self):
+        """(count, sum_q2 [R][n_T], sum_q4 [R][n_T][2] uint64 lo/hi, sum_c [R][n_T][L])."""
+        R, n_T, L = self.R, self.n_T, self.L
+        count = np.zeros((R, n_T), np.int64)
+        q2 = np.zeros((R, n_T), np.int64)
+        q4 = np.zeros((R, n_T, 2), np.uint64)
+        c = np.zeros((R, n_T, L), np.int64)
+        check(lib().ea_measure_read(self._h, count.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    q2.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    q4.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                    c.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return count, q2, q4, c
+
+    def reset_measurements(self):
+        check(lib().ea_measure_reset(self._h))
+
+    def binder_xi(self):
+        """Binder ratio and xi / L per temperature index."""
+        g = np.zeros(self.n_T, np.float64)
+        x = np.zeros(self.n_T, np.float64)
+        check(lib().ea_binder_xi(self._h, g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return g, x
+
     def info(self):
         bt, wr, parts = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         lds = ctypes.c_size_t()
@@ -305,6 +338,34 @@ class Plan:
 
     def run(self, n_steps=1):
         check(lib().ea_plan_run(self._h, int(n_steps)))
+
+    def measure(self):
+        """Add one measurement of the current state to the device accumulators."""
+        check(lib().ea_measure(self._h))
+
+    def measurements(self):
+        """(count, sum_q2 [R][n_T], sum_q4 [R][n_T][2] uint64 lo/hi, sum_c [R][n_T][L])."""
+        R, n_T, L = self.R, self.n_T, self.L
+        count = np.zeros((R, n_T), np.int64)
+        q2 = np.zeros((R, n_T), np.int64)
+        q4 = np.zeros((R, n_T, 2), np.uint64)
+        c = np.zeros((R, n_T, L), np.int64)
+        check(lib().ea_measure_read(self._h, count.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    q2.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    q4.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                    c.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return count, q2, q4, c
+
+    def reset_measurements(self):
+        check(lib().ea_measure_reset(self._h))
+
+    def binder_xi(self):
+        """Binder ratio and xi / L per temperature index."""
+        g = np.zeros(self.n_T, np.float64)
+        x = np.zeros(self.n_T, np.float64)
+        check(lib().ea_binder_xi(self._h, g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return g, x
 
     def info(self):
         bt, grid, units, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

@@ -4,6 +4,7 @@
 // kernels of ea_kernels.hip.
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -231,7 +232,8 @@ size_t job_footprint_bytes(int L, int n_T, int R, int layout, int64_t swap_entri
     const size_t NW = (size_t)(n_T + slots_per_word(layout) - 1) / slots_per_word(layout);
     return a(ladders * NW * N * 4) + a((size_t)R * N) + a(ladders * kMaxTemps * 4) + a((size_t)n_T * kThrCols * 4) +
            a((size_t)swap_entries * 4) + 3 * a(kMaxTemps * 4) + a(N * 4) + a(2 * 4) + a(ladders * kMaxTemps * 4) +
-           a(ladders * 4) + a(sizeof(JobDesc)) + a(ladders * 2 * kMaxTemps * 8) + a(4);
+           a(ladders * 4) + a(sizeof(JobDesc)) + a(ladders * 2 * kMaxTemps * 8) + a(4) +
+           a((size_t)R * n_T * (4 + L) * 8);
 }
 
 // Workgroups per ladder for a lone launch: split a ladder's slot groups over
@@ -407,6 +409,8 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
     std::vector<uint32_t> err(1, 0u);
     if ((rc = upload(s, xchg, &h.xchg)) || (rc = upload(s, err, &h.error)))
         return bail(rc);
+    std::vector<int64_t> meas((size_t)n_realizations * n_T * (4 + L), 0);
+    if ((rc = upload(s, meas, &s->d_meas))) return bail(rc);
     std::vector<uint32_t> units(ladders);
     for (int l = 0; l < ladders; ++l) units[l] = (uint32_t)l;   // job 0 of a lone launch
     if ((rc = upload(s, units, &s->d_units))) return bail(rc);
@@ -451,6 +455,90 @@ int ea_sim_info(const ea_sim *s, int *block_threads, int *words_resident, int *s
     if (words_resident) *words_resident = s->words_resident;
     if (split_parts) *split_parts = s->split_parts;
     if (lds_bytes) *lds_bytes = s->lds;
+    return EA_OK;
+}
+
+// ---- measurements (Sec. 5) ----
+static void meas_parts(ea_sim *s, int64_t **count, int64_t **q2, uint64_t **q4, int64_t **c)
+{
+    const size_t rt = (size_t)s->R * s->n_T;
+    *count = s->d_meas;
+    *q2 = s->d_meas + rt;
+    *q4 = (uint64_t *)(s->d_meas + 2 * rt);
+    *c = s->d_meas + 4 * rt;
+}
+
+int ea_measure(ea_sim *s)
+{
+    if (!s) return fail(EA_EINVAL, "ea_measure: NULL handle");
+    EA_HIP(hipSetDevice(s->device));
+    int64_t *count, *q2, *c;
+    uint64_t *q4;
+    meas_parts(s, &count, &q2, &q4, &c);
+    EA_HIP(launch_measure(s->d_job, s->h, s->layout, count, q2, q4, c, s->stream));
+    if (!s->user_stream) {
+        EA_HIP(hipStreamSynchronize(s->stream));
+        return check_split_error(s);
+    }
+    return EA_OK;
+}
+
+int ea_measure_read(ea_sim *s, int64_t *count, int64_t *sum_q2, uint64_t *sum_q4, int64_t *sum_c)
+{
+    if (!s) return fail(EA_EINVAL, "ea_measure_read: NULL handle");
+    EA_HIP(hipSetDevice(s->device));
+    const size_t rt = (size_t)s->R * s->n_T;
+    std::vector<int64_t> h(rt * (4 + s->L));
+    EA_HIP(hipMemcpyAsync(h.data(), s->d_meas, h.size() * 8, hipMemcpyDeviceToHost, s->stream));
+    EA_HIP(hipStreamSynchronize(s->stream));
+    if (int rc = check_split_error(s)) return rc;
+    if (count) std::memcpy(count, h.data(), rt * 8);
+    if (sum_q2) std::memcpy(sum_q2, h.data() + rt, rt * 8);
+    if (sum_q4) std::memcpy(sum_q4, h.data() + 2 * rt, 2 * rt * 8);
+    if (sum_c) std::memcpy(sum_c, h.data() + 4 * rt, rt * s->L * 8);
+    return EA_OK;
+}
+
+int ea_measure_reset(ea_sim *s)
+{
+    if (!s) return fail(EA_EINVAL, "ea_measure_reset: NULL handle");
+    EA_HIP(hipSetDevice(s->device));
+    EA_HIP(hipMemsetAsync(s->d_meas, 0, (size_t)s->R * s->n_T * (4 + s->L) * 8, s->stream));
+    if (!s->user_stream) EA_HIP(hipStreamSynchronize(s->stream));
+    return EA_OK;
+}
+
+int ea_binder_xi(ea_sim *s, double *binder, double *xi_over_L)
+{
+    if (!s) return fail(EA_EINVAL, "ea_binder_xi: NULL handle");
+    const int R = s->R, n_T = s->n_T, L = s->L;
+    const size_t rt = (size_t)R * n_T;
+    std::vector<int64_t> count(rt), q2(rt), c(rt * L);
+    std::vector<uint64_t> q4(2 * rt);
+    if (int rc = ea_measure_read(s, count.data(), q2.data(), q4.data(), c.data())) return rc;
+    const double N = (double)s->N, kmin = 2.0 * M_PI / L;
+    for (int k = 0; k < n_T; ++k) {
+        double m2 = 0, m4 = 0, ck = 0;
+        for (int r = 0; r < R; ++r) {
+            const size_t rk = (size_t)r * n_T + k;
+            if (count[rk] <= 0) return fail(EA_ESTATE, "no measurement taken for realization %d", r);
+            const double n = (double)count[rk];
+            m2 += (double)q2[rk] / n;
+            m4 += ((double)q4[2 * rk] + std::ldexp((double)q4[2 * rk + 1], 64)) / n;
+            double sk = 0;
+            for (int d = 0; d < L; ++d) sk += (double)c[rk * L + d] * std::cos(kmin * d);
+            ck += sk / n;
+        }
+        m2 /= R;
+        m4 /= R;
+        ck /= R;
+        if (binder) binder[k] = 0.5 * (3.0 - m4 / (m2 * m2));
+        if (xi_over_L) {
+            const double ratio = (m2 / N) / (ck / (3.0 * N));
+            xi_over_L[k] = ratio >= 1.0 ? std::sqrt(ratio - 1.0) / (2.0 * std::sin(kmin / 2.0)) / L
+                                        : std::numeric_limits<double>::quiet_NaN();
+        }
+    }
     return EA_OK;
 }
 

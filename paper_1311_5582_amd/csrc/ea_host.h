@@ -64,6 +64,7 @@ struct ea_sim {
     size_t lds = 0;                   // dynamic LDS bytes of this job's sweep workgroups
     size_t footprint = 0;             // device bytes owned by this job
     int split_parts = 1;              // workgroups per ladder in a lone launch (1, 2 or 4)
+    int64_t *d_meas = nullptr;        // measurement sums: count, q^2 [R][n_T], q^4 [R][n_T][2], C [R][n_T][L]
 };
 
 namespace ea {

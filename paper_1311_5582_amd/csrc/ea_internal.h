@@ -126,6 +126,8 @@ int sweep_split_max_blocks_per_cu(int parts, int kv, int block_threads, size_t l
 hipError_t launch_observables(const JobDesc *d_job, const JobDesc &h_job, int layout, int32_t *d_energy,
                               int32_t *d_overlap, hipStream_t s);
 hipError_t launch_unpack(const JobDesc *d_job, const JobDesc &h_job, int layout, int8_t *d_spins, hipStream_t s);
+hipError_t launch_measure(const JobDesc *d_job, const JobDesc &h_job, int layout, int64_t *count, int64_t *sum_q2,
+                          uint64_t *sum_q4, int64_t *sum_c, hipStream_t s);
 hipError_t launch_pack(const JobDesc *d_job, const JobDesc &h_job, int layout, const int8_t *d_spins, hipStream_t s);
 hipError_t sweep_set_lds(int kv, size_t lds);
 int sweep_max_blocks_per_cu(int kv, int block_threads, size_t lds);

@@ -926,6 +926,69 @@ __global__ void init_spins_kernel(const JobDesc *__restrict__ jd_ptr)
 }
 
 // ---------------------------------------------------------------------------
+// Overlap measurement (Sec. 5: Binder ratio and correlation length of the
+// spin-glass order): one workgroup per (realization, temperature index).
+// q_i = +1 where the two copies at that temperature agree, -1 elsewhere; its
+// plane sums along x, y and z are formed in LDS (a thread per x-line), and the
+// measurement adds q^2, q^4 (as a 128-bit sum) and the plane-sum
+// autocorrelation C[d] = sum_a sum_p Q_a[p] Q_a[(p + d) mod L] into
+// accumulators that only this workgroup touches, so every sum is exact.
+// ---------------------------------------------------------------------------
+template <int LAYOUT>
+__global__ void __launch_bounds__(256) measure_kernel(const JobDesc *__restrict__ jd_ptr, int64_t *count,
+                                                      int64_t *sum_q2, uint64_t *sum_q4, int64_t *sum_c)
+{
+    constexpr int SPW = Layout<LAYOUT>::kSlotsPerWord;
+    constexpr int STR = Layout<LAYOUT>::kStride;
+    __shared__ int s_Q[3][32];
+    __shared__ int s_slot[2];
+    const JobDesc &jd = *jd_ptr;
+    const int n_T = jd.n_T, N = jd.N, L = jd.L, NW = jd.NW;
+    const int r = blockIdx.x / n_T, k = blockIdx.x % n_T;
+    const int tid = threadIdx.x;
+    if (tid < 96) s_Q[tid / 32][tid % 32] = 0;
+    if (tid < 2 * n_T) {
+        const int c = tid / n_T, s = tid % n_T;
+        if (jd.temp_of_slot[(2 * r + c) * kMaxTemps + s] == k) s_slot[c] = s;
+    }
+    __syncthreads();
+    const int a = s_slot[0], b = s_slot[1];
+    const uint32_t *wa = jd.spins + ((size_t)(2 * r) * NW + a / SPW) * N;
+    const uint32_t *wb = jd.spins + ((size_t)(2 * r + 1) * NW + b / SPW) * N;
+    const int sa = (a % SPW) * STR, sb = (b % SPW) * STR;
+    for (int line = tid; line < L * L; line += blockDim.x) {
+        const int y = line % L, z = line / L;
+        int sum = 0;
+        for (int x = 0; x < L; ++x) {
+            const int i = x + L * line;
+            const int qi = 1 - 2 * (int)(((wa[i] >> sa) ^ (wb[i] >> sb)) & 1u);
+            sum += qi;
+            atomicAdd(&s_Q[0][x], qi);
+        }
+        atomicAdd(&s_Q[1][y], sum);
+        atomicAdd(&s_Q[2][z], sum);
+    }
+    __syncthreads();
+    const size_t rk = (size_t)r * n_T + k;
+    if (tid < L) {
+        int64_t cd = 0;
+        for (int ax = 0; ax < 3; ++ax)
+            for (int p = 0; p < L; ++p) cd += (int64_t)s_Q[ax][p] * s_Q[ax][(p + tid) % L];
+        sum_c[rk * L + tid] += cd;
+    }
+    if (tid == 0) {
+        int64_t q = 0;
+        for (int p = 0; p < L; ++p) q += s_Q[0][p];
+        count[rk] += 1;
+        sum_q2[rk] += q * q;
+        const uint64_t q4 = (uint64_t)(q * q) * (uint64_t)(q * q);   // < 2^61 for N <= 2^15
+        const uint64_t lo = sum_q4[2 * rk] + q4;
+        sum_q4[2 * rk + 1] += lo < q4 ? 1u : 0u;
+        sum_q4[2 * rk] = lo;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Measurement kernel (Sec. 4.1): one workgroup per realization.
 // ---------------------------------------------------------------------------
 template <int LAYOUT>
@@ -1111,6 +1174,17 @@ hipError_t launch_observables(const JobDesc *d_job, const JobDesc &h, int layout
         hipLaunchKernelGGL(observables_kernel<0>, dim3(R), dim3(512), 0, s, d_job, d_energy, d_overlap);
     else
         hipLaunchKernelGGL(observables_kernel<1>, dim3(R), dim3(512), 0, s, d_job, d_energy, d_overlap);
+    return hipGetLastError();
+}
+
+hipError_t launch_measure(const JobDesc *d_job, const JobDesc &h, int layout, int64_t *count, int64_t *sum_q2,
+                          uint64_t *sum_q4, int64_t *sum_c, hipStream_t s)
+{
+    const int blocks = h.ladders / 2 * h.n_T;
+    if (layout == 0)
+        hipLaunchKernelGGL(measure_kernel<0>, dim3(blocks), dim3(256), 0, s, d_job, count, sum_q2, sum_q4, sum_c);
+    else
+        hipLaunchKernelGGL(measure_kernel<1>, dim3(blocks), dim3(256), 0, s, d_job, count, sum_q2, sum_q4, sum_c);
     return hipGetLastError();
 }
 

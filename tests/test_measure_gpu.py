@@ -1,0 +1,77 @@
+"""Measurements of the spin-glass order on the GPU (Sec. 5): the overlap
+moments and plane-sum autocorrelations against the oracle bit for bit, the
+Binder ratio and correlation length derived from them, and the paper's
+ferromagnetic check that xi / L of different sizes cross at 1/T = 0.2217."""
+import numpy as np
+import pytest
+
+from paper_1311_5582_amd import binding as B
+from paper_1311_5582_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.lib()
+
+
+@pytest.mark.parametrize("L,R,n_T,layout,rng,split", [
+    (6, 3, 12, "camsc", "words", True),
+    (5, 2, 22, "camsc", "words", True),     # odd L
+    (4, 2, 40, "camsc", "planes", True),    # two words per site
+    (7, 2, 13, "amsc4", "words", True),
+    (16, 2, 32, "camsc", "words", "always"),
+    (2, 3, 4, "camsc", "words", False),
+])
+def test_measurements_equal_oracle(oracle_lib, L, R, n_T, layout, rng, split):
+    seed = 900 + L + n_T
+    J = inputs.couplings(L, R, seed)
+    betas = inputs.geometric_betas(n_T, 0.4, 2.0)
+    sim = B.Sim(L, J, betas, seed, layout=layout, rng=rng, split=split)
+    orc = oracle_lib.OracleSim(L, J, betas, seed, rng=rng)
+    acc = orc.new_measurements()
+    print(f"[measure] L={L} R={R} n_T={n_T} {layout} {rng} launch {sim.info()}", flush=True)
+    for n in (3, 1, 5, 2):
+        sim.sweep(n, 1)
+        orc.sweep(n, 1)
+        sim.measure()
+        orc.measure(acc)
+    got = sim.measurements()
+    for a, b in zip(got, acc):
+        assert np.array_equal(a, b)
+    g, xl = sim.binder_xi()
+    go, xo = oracle_lib.binder_and_xi(acc, L)
+    assert np.allclose(g, go, rtol=1e-12, atol=1e-12)
+    assert np.allclose(xl, xo, rtol=1e-9, atol=1e-12, equal_nan=True)
+    sim.reset_measurements()
+    assert not any(np.any(a) for a in sim.measurements())
+
+
+def _ferro_xi(L, betas, R, seed, warm, sweeps, every):
+    sim = B.Sim(L, inputs.ferro_couplings(L, R), betas, seed)
+    sim.sweep(warm, 1)
+    for _ in range(sweeps // every):
+        sim.sweep(every, 1)
+        sim.measure()
+    return sim.binder_xi()[1]
+
+
+def test_ferromagnet_xi_crossing():
+    """3D Ising ferromagnet (all J = +1): xi / L of L = 8 and L = 12 cross
+    close to the critical 1/T = 0.2217 the paper quotes; well below it the
+    larger lattice has the smaller xi / L, well above it the larger."""
+    betas = np.linspace(0.19, 0.25, 13)
+    x8 = _ferro_xi(8, betas, 32, 11, 2000, 40000, 20)
+    x12 = _ferro_xi(12, betas, 32, 12, 2000, 40000, 20)
+    d = x12 - x8
+    print(f"[measure] beta {np.round(betas, 4).tolist()}\n  xi/L L=8 {np.round(x8, 4).tolist()}\n"
+          f"  xi/L L=12 {np.round(x12, 4).tolist()}", flush=True)
+    assert d[0] < 0 and d[-1] > 0
+    j = int(np.argmax(d > 0))
+    cross = betas[j - 1] + (betas[j] - betas[j - 1]) * (-d[j - 1]) / (d[j] - d[j - 1])
+    print(f"[measure] crossing at 1/T = {cross:.4f}", flush=True)
+    assert abs(cross - 0.2217) < 0.01
