@@ -33,6 +33,15 @@ METRIC = "ps per spin-flip attempt (1 GPU, batched vs plain) + p50/p99 job laten
 # bond energies (2).  On gfx950 every one of these issues at full rate
 # (measured: v_mad_u64_u32 33.4 T/s, v_bitop3 36.1 T/s on 256 CUs).
 ALG_OPS_PER_FLIP = 16
+# The same for the bit-plane stream: a flip attempt needs the planes up to the
+# first one where its draw and threshold differ.  Per 16-slot half a Philox
+# block (40 ops) gives 8 planes and is needed 1.06 times on average (all 16
+# slots decided within 8 planes with probability (1 - 2^-8)^16): 2.65 ops per
+# flip; each plane costs 6 ops per 32 slots (select the threshold bit, compare,
+# record, retire, place the plane) over about 8.5 planes: 1.6; bond words and
+# their bit-sliced sum (6 xor3, a full-adder tree of 8, masks and the update,
+# about 20 ops per 32 slots): 0.63.  About 5 in all.
+ALG_OPS_PER_FLIP_PLANES = 5
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz int32 lane-operations per second
 PEAK_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 KERNEL_SRC = os.path.join(ROOT, "paper_1311_5582_amd", "csrc", "ea_kernels.hip")
@@ -44,11 +53,12 @@ def kernel_source_hash():
     return hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()[:12]
 
 
-def measured_traffic(workload, layout):
+def measured_traffic(workload, layout, rng="words"):
     """HBM bytes per sweep launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, only if it was taken on the current kernel source."""
     import re
-    path = os.path.join(PROFILES, f"sweep_kernel_{workload}_{layout}.md")
+    suffix = "" if rng == "words" else "_" + rng
+    path = os.path.join(PROFILES, f"sweep_kernel_{workload}_{layout}{suffix}.md")
     if not os.path.exists(path):
         return None
     m = re.search(r"traffic_bytes_per_launch:\s*(\d+)\s+kernel_sha1:\s*([0-9a-f]+)", open(path).read())
@@ -252,7 +262,8 @@ def main():
     total_flips = flips_per_step * args.steps
     ps_per_flip = wall / total_flips * 1e12
     avg_launch_s = float(np.mean(kernel_ms)) / 1e3
-    achieved = ALG_OPS_PER_FLIP * flips_per_step / avg_launch_s / 1e12
+    ops_per_flip = ALG_OPS_PER_FLIP if args.rng == "words" else ALG_OPS_PER_FLIP_PLANES
+    achieved = ops_per_flip * flips_per_step / avg_launch_s / 1e12
     peak = PEAK_OPS_PER_S / 1e12
     out = {
         "metric": METRIC,
@@ -274,8 +285,8 @@ def main():
                    "kernel_ps_per_flip": round(avg_launch_s / flips_per_step * 1e12, 4),
                    "paper_ps_per_flip_gtx580": 33.5},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": measured_traffic(args.workload, args.layout),
-                     "ops_per_flip": ALG_OPS_PER_FLIP, "kernel_sha1": kernel_source_hash(),
+                     "frac": round(achieved / peak, 4), "traffic": measured_traffic(args.workload, args.layout, args.rng),
+                     "ops_per_flip": ops_per_flip, "kernel_sha1": kernel_source_hash(),
                      "kernel": "sweep_kernel<%s, %d>" % ("CAMSC" if args.layout == "camsc" else "AMSC4",
                                                         launch["split_parts"])},
     }
