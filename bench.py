@@ -111,6 +111,37 @@ def bench_other_stream(B, torch, L, J, betas, seed, layout, block_threads, split
             "kernel_ps_per_flip": round(kern / flips * 1e12, 4)}
 
 
+def bench_layout_study(B, torch, inputs, sweeps, steps):
+    """The paper's layout comparison (16^3 lattice, PT every 10 sweeps) on the
+    benchmark's L=16 job: every layout, one workgroup per ladder, plus CAMSC
+    with split ladders and with bit-plane draws."""
+    cfg = inputs.CONFIGS["L16_R64"]
+    L, R, n_T = cfg["L"], cfg["R"], cfg["n_T"]
+    J = inputs.couplings(L, R, cfg["seed"])
+    betas = inputs.geometric_betas(n_T, cfg["t_min"], cfg["t_max"])
+    flips = sweeps * L ** 3 * n_T * R * 2
+    out = {"workload": "L=16, 64 realizations x 2 copies, 32 temperatures, PT every 10 sweeps",
+           "sweeps_per_step": sweeps, "steps": steps}
+    for name, layout, split, rng in (("amsc1", "amsc1", False, "words"), ("amsc3", "amsc3", False, "words"),
+                                     ("amsc4", "amsc4", False, "words"), ("camsc", "camsc", False, "words"),
+                                     ("camsc_split", "camsc", True, "words"),
+                                     ("camsc_split_planes", "camsc", True, "planes")):
+        stream = torch.cuda.Stream()
+        sim = B.Sim(L, J, betas, cfg["seed"], layout=layout, stream=stream, split=split, rng=rng)
+        sim.sweep(sweeps, 10)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for a, b in evs:
+            a.record(stream)
+            sim.sweep(sweeps, 10)
+            b.record(stream)
+        torch.cuda.synchronize()
+        kern = float(np.mean([a.elapsed_time(b) for a, b in evs])) / 1e3
+        out[name] = round(kern / flips * 1e12, 4)
+        sim.close()
+    return out
+
+
 def flips_of(job, sweeps):
     return sweeps * job["L"] ** 3 * job["n_T"] * job["R"] * 2
 
@@ -184,10 +215,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sweeps-per-step", type=int, default=1000)
     ap.add_argument("--workload", default="L16_R64")
-    ap.add_argument("--layout", default="camsc", choices=["camsc", "amsc4"])
+    ap.add_argument("--layout", default="camsc", choices=["camsc", "amsc4", "amsc3", "amsc1"])
     ap.add_argument("--block-threads", type=int, default=0)
     ap.add_argument("--rng", default="words", choices=["words", "planes"],
                     help="flip-draw stream: one Philox word per flip, or bit planes compared MSB first")
+    ap.add_argument("--layout-study", action="store_true",
+                    help="also time every spin layout on the L=16 job with PT every 10 sweeps")
     ap.add_argument("--no-other-stream", action="store_true",
                     help="skip timing the same workload with the other flip-draw stream")
     ap.add_argument("--no-split", action="store_true",
@@ -287,14 +320,15 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
                      "frac": round(achieved / peak, 4), "traffic": measured_traffic(args.workload, args.layout, args.rng),
                      "ops_per_flip": ops_per_flip, "kernel_sha1": kernel_source_hash(),
-                     "kernel": "sweep_kernel<%s, %d>" % ("CAMSC" if args.layout == "camsc" else "AMSC4",
-                                                        launch["split_parts"])},
+                     "kernel": "sweep_kernel<%s, %d>" % (args.layout.upper(), launch["split_parts"])},
     }
     sim.close()
     if not args.no_other_stream and args.layout == "camsc":
         other = "planes" if args.rng == "words" else "words"
         out["other_stream"] = bench_other_stream(B, torch, L, J, betas, cfg["seed"], args.layout, args.block_threads,
                                                  not args.no_split, other, S, se, 3)
+    if args.layout_study:
+        out["layout_study_kernel_ps_per_flip"] = bench_layout_study(B, torch, inputs, 200, 3)
     if not args.no_batched:
         out["batched"] = bench_batched(B, inputs, torch, args.batched_sweeps, args.batched_steps)
     if not args.no_serving:

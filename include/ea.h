@@ -65,6 +65,11 @@ extern "C" {
 #define EA_LAYOUT_CAMSC 0  /* 1 bit per temperature slot, 32 slots per 32-bit word; the
                               bond energies are widened to 4-bit segments only to sum */
 #define EA_LAYOUT_AMSC4 1  /* 4-bit segment per slot (spin in bit 0), 8 slots per word */
+#define EA_LAYOUT_AMSC3 2  /* 3-bit segment per slot (spin in bit 0), 10 slots per word; the
+                              local energy is summed in the segments and joined with S slot by
+                              slot                                                            */
+#define EA_LAYOUT_AMSC1 3  /* 1 bit per slot, 32 slots per word (stored like CAMSC); the local
+                              energy of each slot is summed on its own                        */
 
 /* flip-draw streams (Sec. 4.3.2: raw 32-bit integers against 32-bit thresholds) */
 #define EA_RNG_WORDS  0    /* one Philox output word per (slot, site, sweep), as in the
@@ -83,7 +88,7 @@ extern "C" {
 typedef struct ea_sim ea_sim;   /* opaque handle: one job of R realizations x 2 copies */
 
 typedef struct ea_options {
-    int layout;          /* EA_LAYOUT_CAMSC (default) or EA_LAYOUT_AMSC4               */
+    int layout;          /* EA_LAYOUT_CAMSC (default), _AMSC4, _AMSC3 or _AMSC1         */
     int block_threads;   /* threads per workgroup: 0 = library choice, else a multiple
                             of 64 in [64, 1024]                                        */
     int words_resident;  /* spin words per site held in LDS at once: 0 = as many as fit;

@@ -19,7 +19,8 @@ HEADER = os.path.join(ROOT, "include", "ea.h")
 
 EA_OK, EA_EINVAL, EA_ENOMEM, EA_EDEVICE, EA_ESTATE = 0, -1, -2, -3, -4
 LAYOUT_CAMSC, LAYOUT_AMSC4 = 0, 1
-LAYOUTS = {"camsc": LAYOUT_CAMSC, "amsc4": LAYOUT_AMSC4}
+LAYOUT_AMSC3, LAYOUT_AMSC1 = 2, 3
+LAYOUTS = {"camsc": LAYOUT_CAMSC, "amsc4": LAYOUT_AMSC4, "amsc3": LAYOUT_AMSC3, "amsc1": LAYOUT_AMSC1}
 RNG_WORDS, RNG_PLANES = 0, 1
 RNGS = {"words": RNG_WORDS, "planes": RNG_PLANES}
 MAX_TEMPS = 64

@@ -315,7 +315,7 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
     if (n_realizations < 1 || n_realizations > (1 << 19))
         return fail(EA_EINVAL, "n_realizations=%d outside [1, 2^19]", n_realizations);
     if (!couplings || !betas) return fail(EA_EINVAL, "couplings and betas must not be NULL");
-    if (opt.layout != EA_LAYOUT_CAMSC && opt.layout != EA_LAYOUT_AMSC4)
+    if (opt.layout < EA_LAYOUT_CAMSC || opt.layout > EA_LAYOUT_AMSC1)
         return fail(EA_EINVAL, "unknown layout %d", opt.layout);
     if (opt.rng != EA_RNG_WORDS && opt.rng != EA_RNG_PLANES) return fail(EA_EINVAL, "unknown rng %d", opt.rng);
     if (opt.rng == EA_RNG_PLANES && opt.layout != EA_LAYOUT_CAMSC)
@@ -440,7 +440,7 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
 int ea_job_footprint(int L, const double *betas, int n_T, int n_realizations, int layout, size_t *bytes)
 {
     if (!betas || !bytes || L < 2 || L > EA_MAX_L || n_T < 1 || n_T > EA_MAX_TEMPS || n_realizations < 1 ||
-        (layout != EA_LAYOUT_CAMSC && layout != EA_LAYOUT_AMSC4))
+        (layout < EA_LAYOUT_CAMSC || layout > EA_LAYOUT_AMSC1))
         return fail(EA_EINVAL, "ea_job_footprint: bad arguments");
     int64_t total = 0;
     if (int rc = build_swap_tables(betas, n_T, L * L * L, nullptr, nullptr, nullptr, nullptr, &total)) return rc;

@@ -27,10 +27,21 @@ constexpr int kMaxWaves = kMaxBlock / 64;
 
 // Layout parameters: slots per 32-bit word and the bit stride between slots.
 template <int LAYOUT> struct Layout;
-template <> struct Layout<0> { static constexpr int kSlotsPerWord = 32; static constexpr int kStride = 1; };
-template <> struct Layout<1> { static constexpr int kSlotsPerWord = 8;  static constexpr int kStride = 4; };
+// kKeep marks the spin bit of every slot.
+template <> struct Layout<0> {   // CAMSC
+    static constexpr int kSlotsPerWord = 32; static constexpr int kStride = 1; static constexpr uint32_t kKeep = 0xFFFFFFFFu;
+};
+template <> struct Layout<1> {   // AMSC4
+    static constexpr int kSlotsPerWord = 8;  static constexpr int kStride = 4; static constexpr uint32_t kKeep = 0x11111111u;
+};
+template <> struct Layout<2> {   // AMSC3
+    static constexpr int kSlotsPerWord = 10; static constexpr int kStride = 3; static constexpr uint32_t kKeep = 0x09249249u;
+};
+template <> struct Layout<3> {   // AMSC1 (stored like CAMSC)
+    static constexpr int kSlotsPerWord = 32; static constexpr int kStride = 1; static constexpr uint32_t kKeep = 0xFFFFFFFFu;
+};
 
-inline int slots_per_word(int layout) { return layout == 0 ? 32 : 8; }
+inline int slots_per_word(int layout) { return layout == 1 ? 8 : (layout == 2 ? 10 : 32); }
 
 // One job (an ea_sim) as the kernels see it.  Lives in device memory.
 struct JobDesc {
@@ -114,8 +125,11 @@ __host__ __device__ inline LdsLayout lds_layout(int N, int words, int swap_entri
 
 // Host-side launchers (ea_kernels.hip).  Each returns the first HIP error.
 hipError_t launch_init_spins(const JobDesc *d_job, const JobDesc &h_job, int layout, hipStream_t s);
-// Sweep kernel variant: 0 CAMSC, 1 AMSC4, 2 CAMSC with plane draws.
-inline int kernel_variant(int layout, int rng) { return layout == 1 ? 1 : (rng ? 2 : 0); }
+// Sweep kernel variant: 0 CAMSC, 1 AMSC4, 2 CAMSC with plane draws, 3 AMSC3, 4 AMSC1.
+inline int kernel_variant(int layout, int rng)
+{
+    return layout == 0 ? (rng ? 2 : 0) : (layout == 1 ? 1 : (layout == 2 ? 3 : 4));
+}
 hipError_t launch_sweep(const JobDesc *d_jobs, int n_jobs, const uint32_t *d_units, int n_units,
                         uint32_t *d_queue, int kv, int block_threads, size_t lds, int grid,
                         hipStream_t s);

@@ -390,9 +390,9 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
     uint32_t m[6];
 #pragma unroll
     for (int d = 0; d < 6; ++d) m[d] = 0u - ((j6 >> d) & 1u);
-    if (LAYOUT == 1) {
+    if (LAYOUT == 1 || LAYOUT == 2) {
 #pragma unroll
-        for (int d = 0; d < 6; ++d) m[d] &= M;
+        for (int d = 0; d < 6; ++d) m[d] &= Layout<LAYOUT>::kKeep;
     }
     for (int w = 0; w < gw; ++w) {
         uint32_t *sw = sm.spin + (size_t)w * N;
@@ -486,7 +486,7 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
                 const uint32_t b0 = s1 ^ s2, k = s1 & s2;
                 planes_add3(*P, b0, xor3(c1, c2, k), maj3(c1, c2, k), np);
             }
-        } else {
+        } else if (LAYOUT == 1) {
             // AMSC4: 4-bit segments throughout; 2E+S is formed for all slots at once.
             const uint32_t E = e0 + e1 + e2 + e3 + e4 + e5;
             const uint32_t X = (E << 1) | S;
@@ -498,6 +498,41 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
             const Ctr c{t, r, c3base + (uint32_t)(wg * 2), k0, k1, segw};
             const uint32_t F = left > 4 ? amsc4_decide<2>(X, rows, nb.i, c) : amsc4_decide<1>(X, rows, nb.i, c);
             sw[nb.i] = S ^ ((F | always) & valid);
+        } else {
+            // AMSC3 / AMSC1 (Sec. 4.3.3): 2E+S is joined slot by slot.  AMSC3
+            // sums the six bond words in its 3-bit segments first (E <= 6 never
+            // carries out of a segment); AMSC1 sums each slot's six bond bits
+            // on their own.  One Philox block serves four consecutive slots.
+            constexpr int SPW = Layout<LAYOUT>::kSlotsPerWord;
+            constexpr int STR = Layout<LAYOUT>::kStride;
+            const uint32_t E3 = LAYOUT == 2 ? e0 + e1 + e2 + e3 + e4 + e5 : 0u;
+            const int slot0 = wg * SPW;
+            const int n = min(SPW, n_T - slot0);
+            const uint32_t *rows = sm.thr + slot0 * kThrCols;
+            uint32_t flip = 0;
+            U4 blk{0u, 0u, 0u, 0u};
+            int cur = -1;
+#pragma unroll
+            for (int j = 0; j < SPW; ++j) {
+                if (j >= n) break;
+                const int slot = slot0 + j;
+                if ((slot >> 2) != cur) {   // uniform across the wave
+                    cur = slot >> 2;
+                    blk = philox10(nb.i, t, r, c3base + (uint32_t)cur, k0, k1);
+                }
+                uint32_t E;
+                if (LAYOUT == 2)
+                    E = (E3 >> (3 * j)) & 7u;
+                else
+                    E = ((e0 >> j) & 1u) + ((e1 >> j) & 1u) + ((e2 >> j) & 1u) + ((e3 >> j) & 1u) +
+                        ((e4 >> j) & 1u) + ((e5 >> j) & 1u);
+                const uint32_t col = (E << 1) | ((S >> (j * STR)) & 1u);
+                const int q = slot & 3;
+                const uint32_t dr = q == 0 ? blk.x : (q == 1 ? blk.y : (q == 2 ? blk.z : blk.w));
+                const bool f = col >= 6u || dr < rows[j * kThrCols + col];
+                flip |= (f ? 1u : 0u) << (j * STR);
+            }
+            sw[nb.i] = S ^ flip;
         }
     }
 }
@@ -520,7 +555,7 @@ __device__ void count_unsat_word_np(const uint32_t *words, const uint8_t *j6, in
 {
     constexpr int SPW = Layout<LAYOUT>::kSlotsPerWord;
     constexpr int STR = Layout<LAYOUT>::kStride;
-    const uint32_t keep = LAYOUT == 0 ? 0xFFFFFFFFu : 0x11111111u;
+    const uint32_t keep = Layout<LAYOUT>::kKeep;
     uint32_t P[14];
 #pragma unroll
     for (int p = 0; p < 14; ++p) P[p] = 0;
@@ -914,12 +949,18 @@ __global__ void init_spins_kernel(const JobDesc *__restrict__ jd_ptr)
         const int ladder = (int)(idx / ((size_t)jd.N * jd.NW));
         const uint32_t c3 = (kDomainInit << 28) | ((uint32_t)(ladder & 1) << 24);
         uint32_t word = 0;
-        for (int g = 0; g < SPW / 4; ++g) {
-            const int slot = w * SPW + 4 * g;
+        U4 rr{0u, 0u, 0u, 0u};
+        int cur = -1;
+        for (int j = 0; j < SPW; ++j) {   // slot groups of 4 need not align with words (AMSC3)
+            const int slot = w * SPW + j;
             if (slot >= jd.n_T) break;
-            const U4 rr = philox10((uint32_t)i, 0u, (uint32_t)(ladder >> 1), c3 | (uint32_t)(slot >> 2), jd.key0, jd.key1);
-            const uint32_t v[4] = {rr.x, rr.y, rr.z, rr.w};
-            for (int k = 0; k < 4 && slot + k < jd.n_T; ++k) word |= (v[k] & 1u) << ((4 * g + k) * STR);
+            if ((slot >> 2) != cur) {
+                cur = slot >> 2;
+                rr = philox10((uint32_t)i, 0u, (uint32_t)(ladder >> 1), c3 | (uint32_t)cur, jd.key0, jd.key1);
+            }
+            const int q = slot & 3;
+            const uint32_t v = q == 0 ? rr.x : (q == 1 ? rr.y : (q == 2 ? rr.z : rr.w));
+            word |= (v & 1u) << (j * STR);
         }
         jd.spins[idx] = word;
     }
@@ -1094,20 +1135,27 @@ int grid_for(size_t total, int block)
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+// Storage of a layout's words (AMSC1 words are CAMSC words).
+static int storage_layout(int layout) { return layout == 3 ? 0 : layout; }
+
 hipError_t launch_init_spins(const JobDesc *d_job, const JobDesc &h, int layout, hipStream_t s)
 {
     const size_t total = (size_t)h.ladders * h.NW * h.N;
-    if (layout == 0)
-        hipLaunchKernelGGL(init_spins_kernel<0>, dim3(grid_for(total, 256)), dim3(256), 0, s, d_job);
-    else
-        hipLaunchKernelGGL(init_spins_kernel<1>, dim3(grid_for(total, 256)), dim3(256), 0, s, d_job);
+    // AMSC1 words are stored like CAMSC words
+    switch (storage_layout(layout)) {
+        case 0: hipLaunchKernelGGL(init_spins_kernel<0>, dim3(grid_for(total, 256)), dim3(256), 0, s, d_job); break;
+        case 1: hipLaunchKernelGGL(init_spins_kernel<1>, dim3(grid_for(total, 256)), dim3(256), 0, s, d_job); break;
+        default: hipLaunchKernelGGL(init_spins_kernel<2>, dim3(grid_for(total, 256)), dim3(256), 0, s, d_job); break;
+    }
     return hipGetLastError();
 }
 
-// Sweep kernel variants: kv = 0 CAMSC, 1 AMSC4, 2 CAMSC with plane draws.
+// Sweep kernel variants: kv = 0 CAMSC, 1 AMSC4, 2 CAMSC with plane draws, 3 AMSC3, 4 AMSC1.
 static const void *sweep_fn(int kv, int parts)
 {
     if (kv == 1) return (const void *)sweep_kernel<1, 1, 0>;
+    if (kv == 3) return (const void *)sweep_kernel<2, 1, 0>;
+    if (kv == 4) return (const void *)sweep_kernel<3, 1, 0>;
     if (kv == 2)
         return parts == 4 ? (const void *)sweep_kernel<0, 4, 1>
                           : (parts == 2 ? (const void *)sweep_kernel<0, 2, 1> : (const void *)sweep_kernel<0, 1, 1>);
@@ -1118,7 +1166,7 @@ static const void *sweep_fn(int kv, int parts)
 hipError_t sweep_set_lds(int kv, size_t lds)
 {
     // the attribute is process-wide per kernel; raise it only when a launch needs more
-    static std::atomic<size_t> set_max[3] = {{0}, {0}, {0}};
+    static std::atomic<size_t> set_max[5] = {{0}, {0}, {0}, {0}, {0}};
     std::atomic<size_t> &cur = set_max[kv];
     if (lds <= cur.load()) return hipSuccess;
     hipError_t e = hipFuncSetAttribute(sweep_fn(kv, 1), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1170,10 +1218,12 @@ hipError_t launch_observables(const JobDesc *d_job, const JobDesc &h, int layout
                               int32_t *d_overlap, hipStream_t s)
 {
     const int R = h.ladders / 2;
-    if (layout == 0)
-        hipLaunchKernelGGL(observables_kernel<0>, dim3(R), dim3(512), 0, s, d_job, d_energy, d_overlap);
-    else
-        hipLaunchKernelGGL(observables_kernel<1>, dim3(R), dim3(512), 0, s, d_job, d_energy, d_overlap);
+    // AMSC1 words are stored like CAMSC words
+    switch (storage_layout(layout)) {
+        case 0: hipLaunchKernelGGL(observables_kernel<0>, dim3(R), dim3(512), 0, s, d_job, d_energy, d_overlap); break;
+        case 1: hipLaunchKernelGGL(observables_kernel<1>, dim3(R), dim3(512), 0, s, d_job, d_energy, d_overlap); break;
+        default: hipLaunchKernelGGL(observables_kernel<2>, dim3(R), dim3(512), 0, s, d_job, d_energy, d_overlap); break;
+    }
     return hipGetLastError();
 }
 
@@ -1181,30 +1231,36 @@ hipError_t launch_measure(const JobDesc *d_job, const JobDesc &h, int layout, in
                           uint64_t *sum_q4, int64_t *sum_c, hipStream_t s)
 {
     const int blocks = h.ladders / 2 * h.n_T;
-    if (layout == 0)
-        hipLaunchKernelGGL(measure_kernel<0>, dim3(blocks), dim3(256), 0, s, d_job, count, sum_q2, sum_q4, sum_c);
-    else
-        hipLaunchKernelGGL(measure_kernel<1>, dim3(blocks), dim3(256), 0, s, d_job, count, sum_q2, sum_q4, sum_c);
+    // AMSC1 words are stored like CAMSC words
+    switch (storage_layout(layout)) {
+        case 0: hipLaunchKernelGGL(measure_kernel<0>, dim3(blocks), dim3(256), 0, s, d_job, count, sum_q2, sum_q4, sum_c); break;
+        case 1: hipLaunchKernelGGL(measure_kernel<1>, dim3(blocks), dim3(256), 0, s, d_job, count, sum_q2, sum_q4, sum_c); break;
+        default: hipLaunchKernelGGL(measure_kernel<2>, dim3(blocks), dim3(256), 0, s, d_job, count, sum_q2, sum_q4, sum_c); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_unpack(const JobDesc *d_job, const JobDesc &h, int layout, int8_t *d_spins, hipStream_t s)
 {
     const size_t total = (size_t)h.ladders * h.n_T * h.N;
-    if (layout == 0)
-        hipLaunchKernelGGL(unpack_kernel<0>, dim3(grid_for(total, 256)), dim3(256), 0, s, d_job, d_spins);
-    else
-        hipLaunchKernelGGL(unpack_kernel<1>, dim3(grid_for(total, 256)), dim3(256), 0, s, d_job, d_spins);
+    // AMSC1 words are stored like CAMSC words
+    switch (storage_layout(layout)) {
+        case 0: hipLaunchKernelGGL(unpack_kernel<0>, dim3(grid_for(total, 256)), dim3(256), 0, s, d_job, d_spins); break;
+        case 1: hipLaunchKernelGGL(unpack_kernel<1>, dim3(grid_for(total, 256)), dim3(256), 0, s, d_job, d_spins); break;
+        default: hipLaunchKernelGGL(unpack_kernel<2>, dim3(grid_for(total, 256)), dim3(256), 0, s, d_job, d_spins); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_pack(const JobDesc *d_job, const JobDesc &h, int layout, const int8_t *d_spins, hipStream_t s)
 {
     const size_t total = (size_t)h.ladders * h.NW * h.N;
-    if (layout == 0)
-        hipLaunchKernelGGL(pack_kernel<0>, dim3(grid_for(total, 256)), dim3(256), 0, s, d_job, d_spins);
-    else
-        hipLaunchKernelGGL(pack_kernel<1>, dim3(grid_for(total, 256)), dim3(256), 0, s, d_job, d_spins);
+    // AMSC1 words are stored like CAMSC words
+    switch (storage_layout(layout)) {
+        case 0: hipLaunchKernelGGL(pack_kernel<0>, dim3(grid_for(total, 256)), dim3(256), 0, s, d_job, d_spins); break;
+        case 1: hipLaunchKernelGGL(pack_kernel<1>, dim3(grid_for(total, 256)), dim3(256), 0, s, d_job, d_spins); break;
+        default: hipLaunchKernelGGL(pack_kernel<2>, dim3(grid_for(total, 256)), dim3(256), 0, s, d_job, d_spins); break;
+    }
     return hipGetLastError();
 }
 

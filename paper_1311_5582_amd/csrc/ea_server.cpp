@@ -93,7 +93,7 @@ int ea_server_create(const ea_server_options *opt_in, ea_server **out)
     ea_default_server_options(&opt);
     if (opt_in) opt = *opt_in;
     if (opt.quantum_sweeps < 1) return fail(EA_EINVAL, "quantum_sweeps < 1");
-    if (opt.layout != EA_LAYOUT_CAMSC && opt.layout != EA_LAYOUT_AMSC4) return fail(EA_EINVAL, "unknown layout");
+    if (opt.layout < EA_LAYOUT_CAMSC || opt.layout > EA_LAYOUT_AMSC1) return fail(EA_EINVAL, "unknown layout");
     if (opt.rng != EA_RNG_WORDS && opt.rng != EA_RNG_PLANES) return fail(EA_EINVAL, "unknown rng");
     if (opt.rng == EA_RNG_PLANES && opt.layout != EA_LAYOUT_CAMSC)
         return fail(EA_EINVAL, "plane draws need the CAMSC layout");

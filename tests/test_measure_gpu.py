@@ -24,6 +24,8 @@ def _gpu():
     (5, 2, 22, "camsc", "words", True),     # odd L
     (4, 2, 40, "camsc", "planes", True),    # two words per site
     (7, 2, 13, "amsc4", "words", True),
+    (6, 2, 23, "amsc3", "words", True),
+    (5, 2, 33, "amsc1", "words", True),
     (16, 2, 32, "camsc", "words", "always"),
     (2, 3, 4, "camsc", "words", False),
 ])

@@ -69,7 +69,7 @@ def check_observables_properties(L, J, betas, s, perm, E, q):
         assert np.array_equal(q[r], qq)
 
 
-@pytest.mark.parametrize("layout", ["camsc", "amsc4"])
+@pytest.mark.parametrize("layout", ["camsc", "amsc4", "amsc3", "amsc1"])
 def test_plain_L8_full_run(oracle_lib, layout):
     """The single-job workload in full: L=8, 1 realization, 16 temperatures in
     [0.5, 2.0], 1000 sweeps, PT after every sweep."""
@@ -84,7 +84,8 @@ def test_plain_L8_full_run(oracle_lib, layout):
 
 @pytest.mark.parametrize("L,n_T,layout", [(2, 4, "camsc"), (3, 5, "camsc"), (5, 22, "camsc"), (6, 34, "camsc"),
                                           (7, 40, "amsc4"), (4, 64, "camsc"), (4, 1, "camsc"), (5, 2, "amsc4"),
-                                          (6, 13, "amsc4"), (9, 33, "camsc")])
+                                          (6, 13, "amsc4"), (9, 33, "camsc"), (3, 7, "amsc3"), (6, 10, "amsc3"),
+                                          (5, 23, "amsc3"), (4, 64, "amsc3"), (7, 33, "amsc1"), (4, 5, "amsc1")])
 def test_shapes_and_ragged_slots(oracle_lib, L, n_T, layout):
     """Even and odd L (two and three colour classes), ladders that fill a
     word exactly or leave a ragged tail, the smallest lattice and ladder."""
@@ -101,7 +102,7 @@ def test_split_calls_equal_one_call(oracle_lib):
     run_pair(oracle_lib, 6, 2, 20, 5, 37, 4, splits=[1, 9, 0, 13, 14])
 
 
-@pytest.mark.parametrize("layout", ["camsc", "amsc4"])
+@pytest.mark.parametrize("layout", ["camsc", "amsc4", "amsc3", "amsc1"])
 @pytest.mark.parametrize("block_threads,words_resident", [(64, 0), (256, 0), (1024, 0), (128, 1), (64, 2)])
 def test_launch_shape_invariance(oracle_lib, layout, block_threads, words_resident):
     """Any workgroup size and any number of LDS-resident words (staging the
@@ -121,12 +122,12 @@ def test_L16_R64_sampled(oracle_lib):
 
 
 def test_L24_sampled_staged_amsc4(oracle_lib):
-    """L=24 with 48 temperatures: AMSC4 needs 6 words per site and stages
-    them through HBM; CAMSC keeps its 2 words resident."""
+    """L=24 with 48 temperatures: AMSC4 needs 6 words per site and AMSC3 5,
+    staged through HBM; CAMSC keeps its 2 words resident."""
     L, n_T, seed = 24, 48, 4
     J = inputs.couplings(L, 4, seed)
     ref = None
-    for layout in ("camsc", "amsc4"):
+    for layout in ("camsc", "amsc4", "amsc3"):
         sim, orc, st, _, _ = run_pair(oracle_lib, L, 4, n_T, seed, 3, 2, layout=layout, t_min=0.35, rids=[2],
                                       couplings=J)
         if ref is None:
