@@ -31,6 +31,7 @@ class _OrcSim(ctypes.Structure):
         ("spins", _i8p), ("temp_of_slot", _i32p), ("Urun", _i64p),
         ("flip_tries", _i64p), ("flip_acc", _i64p),
         ("swap_tries", _i64p), ("swap_acc", _i64p),
+        ("h", ctypes.c_double),
     ]
 
 
@@ -70,6 +71,10 @@ def lib():
         L.orc_observables.restype = None
         L.orc_measure.argtypes = [ctypes.POINTER(_OrcSim), _i64p, _i64p, ctypes.POINTER(ctypes.c_uint64), _i64p]
         L.orc_measure.restype = None
+        L.orc_magnetization.argtypes = [ctypes.POINTER(_OrcSim), _i32p]
+        L.orc_magnetization.restype = None
+        L.orc_flip_threshold_h.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        L.orc_flip_threshold_h.restype = ctypes.c_uint32
         _lib = L
     return _lib
 
@@ -95,6 +100,11 @@ def flip_draw(seed, rng, i, t, r, c, slot):
     """The flip draw of (realization id r, copy c, slot, sweep t, site i)."""
     return int(lib().orc_flip_draw(int(seed) & (2 ** 64 - 1), RNGS.get(rng, rng), int(i), int(t), int(r), int(c),
                                    int(slot)))
+
+
+def flip_threshold_h(beta, u, S, h):
+    """Threshold of a flip with cost 12 - 4u + 2h(2S - 1) (2^32 - 1 when the cost is <= 0)."""
+    return int(lib().orc_flip_threshold_h(float(beta), int(u), int(S), float(h)))
 
 
 def flip_threshold(beta, u):
@@ -132,7 +142,7 @@ class OracleSim:
     rid: realization ids (Philox counter word 2), default 0..R-1.
     """
 
-    def __init__(self, L, couplings, betas, seed, rid=None, track_energy=False, stats=False, rng="words"):
+    def __init__(self, L, couplings, betas, seed, rid=None, track_energy=False, stats=False, rng="words", h=0.0):
         self.L = int(L)
         self.N = self.L ** 3
         self.J = np.ascontiguousarray(couplings, dtype=np.int8)
@@ -159,6 +169,9 @@ class OracleSim:
         self.rng = RNGS.get(rng, rng)
         assert self.rng in (RNG_WORDS, RNG_PLANES)
         s.L, s.n_T, s.R, s.seed, s.t, s.rng = self.L, self.n_T, self.R, self.seed, 0, self.rng
+        self.h = float(h)
+        assert abs(self.h) <= 8.0 and self.h * 4.0 == round(self.h * 4.0), "h must be a multiple of 1/4 in [-8, 8]"
+        s.h = self.h
         s.rid = _ptr(self.rid, ctypes.c_int32)
         s.J = _ptr(self.J, ctypes.c_int8)
         s.betas = _ptr(self.betas, ctypes.c_double)
@@ -190,6 +203,12 @@ class OracleSim:
         overlap = np.zeros((self.R, self.n_T), dtype=np.int32)
         lib().orc_observables(ctypes.byref(self._s), _ptr(energy, ctypes.c_int32), _ptr(overlap, ctypes.c_int32))
         return energy, overlap
+
+    def magnetization(self):
+        """sum_i s_i [R][2][n_T] by temperature index."""
+        m = np.zeros((self.R, 2, self.n_T), dtype=np.int32)
+        lib().orc_magnetization(ctypes.byref(self._s), _ptr(m, ctypes.c_int32))
+        return m
 
     def new_measurements(self):
         """Zeroed accumulators: count, sum_q2 [R][n_T], sum_q4 [R][n_T][2] (lo, hi), sum_c [R][n_T][L]."""

@@ -11,13 +11,16 @@
  * and its own lattice indexing, and it stores one spin per byte (int8, +-1).
  *
  * What it computes (paper sections in brackets):
- *   - H = -sum_<ij> J_ij s_i s_j over the 3N nearest-neighbour bonds of a
- *     periodic L^3 simple cubic lattice, h = 0 [Sec. 2.2, Eq. 1].
+ *   - H = -sum_<ij> J_ij s_i s_j - h sum_i s_i over the 3N nearest-neighbour
+ *     bonds of a periodic L^3 simple cubic lattice [Sec. 2.2, Eq. 1]; the
+ *     field h is a multiple of 1/4 so that every energy difference the swap
+ *     step needs is an exact multiple of 1/2.
  *   - Single-spin-flip Metropolis with acceptance min(1, exp(-beta dE))
  *     [Sec. 2.3], visited as a checkerboard of sublattices updated one after
  *     the other [Sec. 3.1]; odd L uses three colour classes (see below).
  *   - dE is a function of the number u of unsatisfied bonds around the site
- *     only: dE = 12 - 4u (the XOR form of the local energy, Sec. 4.3, Eq. e).
+ *     and of its spin: dE = 12 - 4u + 2h s (the XOR form of the local energy,
+ *     Sec. 4.3, Eq. e; the spin enters through the 2E+S column, Sec. 4.3.1).
  *   - The flip probability is taken from a table indexed by temperature and
  *     local energy [Sec. 4.3.1], converted to 32-bit unsigned integers and
  *     compared with the raw integer output of the random number generator
@@ -153,6 +156,13 @@ uint32_t orc_flip_threshold(double beta, int u)
 {
     if (u >= 3) return 0xFFFFFFFFu;
     double dE = (double)(12 - 4 * u);
+    return orc_prob_to_u32(exp(-(beta * dE)));
+}
+
+uint32_t orc_flip_threshold_h(double beta, int u, int S, double h)
+{
+    double dE = (double)(12 - 4 * u) + 2.0 * h * (double)(2 * S - 1);
+    if (dE <= 0.0) return 0xFFFFFFFFu;
     return orc_prob_to_u32(exp(-(beta * dE)));
 }
 
@@ -300,13 +310,15 @@ static void orc_stage(orc_sim *sim, int colour, uint32_t t)
                             if (orc_colour(L, x, y, z) != colour) continue;
                             int i = orc_site(L, x, y, z);
                             int u = orc_local_unsat(L, J, s, i);
+                            int S = s[i] > 0;
+                            double dE = (double)(12 - 4 * u) + 2.0 * sim->h * (double)(2 * S - 1);
                             int flip;
-                            if (u >= 3) {
+                            if (dE <= 0.0) {
                                 flip = 1;
                             } else {
                                 uint32_t draw = orc_flip_draw(sim->seed, sim->rng, (uint32_t)i, t,
                                                               (uint32_t)sim->rid[r], c, slot);
-                                flip = draw < orc_flip_threshold(beta, u);
+                                flip = draw < orc_flip_threshold_h(beta, u, S, sim->h);
                             }
                             if (sim->flip_tries) {
                                 sim->flip_tries[k * 7 + u] += 1;
@@ -333,26 +345,32 @@ static void orc_swap_pass(orc_sim *sim, int r, int c, uint32_t t)
     const int8_t *J = orc_couplings(sim, r);
     int32_t *temp_of_slot = orc_perm(sim, r, c);
     int32_t slot_of_temp[ORC_MAX_TEMPS];
-    int64_t U[ORC_MAX_TEMPS];
+    int64_t U[ORC_MAX_TEMPS], up[ORC_MAX_TEMPS];
+    int N = sim->L * sim->L * sim->L;
+    int64_t m = (int64_t)(4.0 * sim->h);   /* exact: h is a multiple of 1/4 */
     for (int slot = 0; slot < n_T; ++slot) {
         slot_of_temp[temp_of_slot[slot]] = slot;
-        U[slot] = orc_unsat_bonds(sim->L, J, orc_spins(sim, r, c, slot));
+        const int8_t *s = orc_spins(sim, r, c, slot);
+        U[slot] = orc_unsat_bonds(sim->L, J, s);
+        up[slot] = 0;
+        for (int i = 0; i < N; ++i) up[slot] += s[i] > 0;
     }
     for (int k = 0; k + 1 < n_T; ++k) {
         int a = slot_of_temp[k], b = slot_of_temp[k + 1];
-        int64_t d = U[a] - U[b];
+        /* E = 2U - 3N - h M with M = 2 up - N, so 2 (E_a - E_b) = D exactly */
+        int64_t D = 4 * (U[a] - U[b]) - m * (up[a] - up[b]);
         double dbeta = sim->betas[k] - sim->betas[k + 1];
-        /* accept with min(1, exp(2 dbeta d)): certain when dbeta * d >= 0,
-         * decided from the signs so that no rounding enters */
-        int favourable = (dbeta == 0.0) || (d == 0) || ((dbeta > 0.0) == (d > 0));
+        /* accept with min(1, exp(dbeta (E_a - E_b))): certain when
+         * dbeta * D >= 0, decided from the signs so that no rounding enters */
+        int favourable = (dbeta == 0.0) || (D == 0) || ((dbeta > 0.0) == (D > 0));
         int accept;
         if (favourable) {
             accept = 1;
         } else {
             uint32_t draw = orc_draw(sim->seed, (uint32_t)k, t, (uint32_t)sim->rid[r],
                                      orc_c3(ORC_DOMAIN_SWAP, c, 0), 0);
-            int64_t n = d < 0 ? -d : d;
-            accept = draw < orc_swap_threshold(fabs(dbeta), n);
+            double dEabs = 0.5 * (double)(D < 0 ? -D : D);   /* |E_a - E_b| */
+            accept = draw < orc_prob_to_u32(exp(-(fabs(dbeta) * dEabs)));
         }
         if (sim->swap_tries) {
             sim->swap_tries[k] += 1;
@@ -473,4 +491,19 @@ void orc_measure(const orc_sim *sim, int64_t *count, int64_t *sum_q2, uint64_t *
             }
         }
     }
+}
+
+void orc_magnetization(const orc_sim *sim, int32_t *magnetization)
+{
+    int N = sim->L * sim->L * sim->L, n_T = sim->n_T;
+    for (int r = 0; r < sim->R; ++r)
+        for (int c = 0; c < 2; ++c) {
+            const int32_t *temp_of_slot = orc_perm(sim, r, c);
+            for (int slot = 0; slot < n_T; ++slot) {
+                const int8_t *s = orc_spins(sim, r, c, slot);
+                int32_t M = 0;
+                for (int i = 0; i < N; ++i) M += s[i];
+                magnetization[((size_t)r * 2 + c) * n_T + temp_of_slot[slot]] = M;
+            }
+        }
 }

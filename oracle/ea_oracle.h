@@ -34,6 +34,7 @@ typedef struct {
     int64_t *flip_acc;       /* [n_T][7] accepted flips (with flip_tries)        */
     int64_t *swap_tries;     /* [n_T-1] swap attempts per pair or NULL           */
     int64_t *swap_acc;       /* [n_T-1] accepted swaps (with swap_tries)         */
+    double h;                /* external field, a multiple of 1/4 (|h| <= 8)     */
 } orc_sim;
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -52,6 +53,12 @@ void orc_reset_running_energy(orc_sim *sim);
 int orc_sweep(orc_sim *sim, int64_t n_sweeps, int swap_every);
 /* energy [R][2][n_T] by temperature index; overlap [R][n_T] (either may be NULL) */
 void orc_observables(const orc_sim *sim, int32_t *energy, int32_t *overlap);
+/* magnetization sum_i s_i [R][2][n_T] by temperature index */
+void orc_magnetization(const orc_sim *sim, int32_t *magnetization);
+/* flip cost 12 - 4u + 2h(2S - 1) for a spin with bit S (s = 2S - 1) and u
+ * unsatisfied bonds; the flip is certain when it is <= 0, otherwise it is
+ * taken iff draw < floor(2^32 exp(-beta cost)) */
+uint32_t orc_flip_threshold_h(double beta, int u, int S, double h);
 
 /* one measurement of the overlap moments and plane-sum autocorrelations,
  * added to count/sum_q2 [R][n_T], sum_q4 [R][n_T][2] (lo, hi), sum_c [R][n_T][L] */

@@ -94,3 +94,28 @@ def zero_temperature_sweeps(L, J, s, n):
             flip = cls[u[cls] >= 3]
             s[flip] = -s[flip]
     return s.astype(np.int8)
+
+
+def enumerate_energy_magnetization(L, J):
+    """Bond energy and magnetization of every one of the 2^N states (small L only)."""
+    N = L ** 3
+    E = np.empty(2 ** N, dtype=np.int64)
+    M = np.empty(2 ** N, dtype=np.int64)
+    for n, bits in enumerate(itertools.product((1, -1), repeat=N)):
+        s = np.array(bits[::-1], dtype=np.int64)
+        E[n] = energy(L, J, s)
+        M[n] = s.sum()
+    return E, M
+
+
+def zero_temperature_sweeps_field(L, J, s, n, h):
+    """Metropolis at beta -> infinity in a field h: a site flips iff its cost
+    12 - 4u + 2 h s <= 0; the colour classes are updated in order."""
+    s = np.array(s, dtype=np.int64)
+    for _ in range(n):
+        for cls in colour_classes(L):
+            u = local_field_unsat(L, J, s)
+            cost = 12 - 4 * u[cls] + 2.0 * h * s[cls]
+            flip = cls[cost <= 0]
+            s[flip] = -s[flip]
+    return s.astype(np.int8)

@@ -397,3 +397,105 @@ def test_binder_and_xi_closed_forms(oracle_lib):
         acc2 = (np.ones((1, 1), np.int64), np.array([[q2]]), np.zeros((1, 1, 2), np.uint64), Cd[None, None, :])
         _, xl = oracle_lib.binder_and_xi(acc2, L)
         assert abs(xl[0] * L - xi) < 1e-9
+
+
+# --------------------------------------------------------------------------
+# External field h (Eq. 1), a multiple of 1/4
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("h", [0.75, -1.25])
+def test_exact_boltzmann_with_field_L2(oracle_lib, h):
+    """Joint distribution of (bond energy, magnetization) at every temperature
+    index against exact enumeration of the 2^8 states with weights
+    exp(-beta (E - h M)), and the expected swap acceptance of every pair."""
+    L, R = 2, 24
+    J1 = inputs.couplings(L, 1, seed=77)[0]
+    J = np.repeat(J1[None], R, axis=0)
+    betas = np.array([1.0, 0.7, 0.45, 0.3])
+    n_T = len(betas)
+    sim = _sim(oracle_lib, L, J, betas, seed=5, stats=True, h=h)
+    Eb, Mg = bf.enumerate_energy_magnetization(L, J1)
+    Etot = Eb - h * Mg
+    keys = sorted(set(zip(Eb.tolist(), Mg.tolist())))
+    index = {k: n for n, k in enumerate(keys)}
+    sim.sweep(200, 1)
+    sim.swap_tries[...] = 0
+    sim.swap_acc[...] = 0
+    n_batches, per_batch = 20, 500
+    hist = np.zeros((n_batches, n_T, len(keys)))
+    swap_rate = np.zeros((n_batches, n_T - 1))
+    for b in range(n_batches):
+        tries0, acc0 = sim.swap_tries.copy(), sim.swap_acc.copy()
+        for _ in range(per_batch):
+            sim.sweep(1, 1)
+            E, _ = sim.observables()
+            M = sim.magnetization()
+            for k in range(n_T):
+                for e, m in zip(E[:, :, k].ravel().tolist(), M[:, :, k].ravel().tolist()):
+                    hist[b, k, index[(e, m)]] += 1
+        swap_rate[b] = (sim.swap_acc - acc0) / (sim.swap_tries - tries0)
+    hist /= hist.sum(axis=2, keepdims=True)
+    state_key = np.array([index[(e, m)] for e, m in zip(Eb.tolist(), Mg.tolist())])
+    for k in range(n_T):
+        w = np.exp(-betas[k] * (Etot - Etot.min()))
+        p = np.bincount(state_key, weights=w, minlength=len(keys))
+        p /= p.sum()
+        mean = hist[:, k].mean(axis=0)
+        err = hist[:, k].std(axis=0, ddof=1) / math.sqrt(n_batches)
+        assert np.all(np.abs(mean - p) <= 5 * err + 2e-3), (k, mean, p)
+    for k in range(n_T - 1):
+        wk = np.exp(-betas[k] * (Etot - Etot.min()))
+        wk1 = np.exp(-betas[k + 1] * (Etot - Etot.min()))
+        pk, pk1 = wk / wk.sum(), wk1 / wk1.sum()
+        dE = Etot[:, None] - Etot[None, :]
+        expect = float(np.sum(pk[:, None] * pk1[None, :] * np.minimum(1.0, np.exp((betas[k] - betas[k + 1]) * dE))))
+        mean = swap_rate[:, k].mean()
+        err = swap_rate[:, k].std(ddof=1) / math.sqrt(n_batches)
+        assert abs(mean - expect) <= 5 * err + 2e-3, (k, mean, expect)
+
+
+@pytest.mark.parametrize("L,h", [(4, 0.25), (5, -1.5), (4, 3.0)])
+def test_zero_temperature_limit_with_field(oracle_lib, L, h):
+    """beta = 60 makes every threshold of a positive cost (>= 1/2) zero: the
+    chain is the quench 'flip iff 12 - 4u + 2 h s <= 0'."""
+    J = inputs.couplings(L, 1, seed=19)
+    sim = _sim(oracle_lib, L, J, np.array([60.0, 70.0]), h=h)
+    s0 = sim.spins.copy()
+    sim.sweep(4, 0)
+    for c in range(2):
+        for slot in range(2):
+            assert np.array_equal(sim.spins[0, c, slot],
+                                  bf.zero_temperature_sweeps_field(L, J[0], s0[0, c, slot], 4, h))
+
+
+def test_field_reversal_symmetry(oracle_lib):
+    """Reversing every spin and the field leaves every flip cost and every
+    energy difference unchanged: the reversed chain is the reversed image of
+    the original, swaps included, bit for bit."""
+    for L in (4, 5):
+        J = inputs.couplings(L, 2, seed=31)
+        betas = inputs.geometric_betas(7, 0.4, 2.0)
+        a = _sim(oracle_lib, L, J, betas, seed=8, h=0.75)
+        b = _sim(oracle_lib, L, J, betas, seed=8, h=-0.75)
+        b.set_state(-a.spins, a.temp_of_slot, 0)
+        for _ in range(3):
+            a.sweep(6, 2)
+            b.sweep(6, 2)
+            assert np.array_equal(b.spins, -a.spins)
+            assert np.array_equal(b.temp_of_slot, a.temp_of_slot)
+            assert np.array_equal(b.magnetization(), -a.magnetization())
+
+
+@pytest.mark.parametrize("h,beta", [(2.0, 1.5), (-2.0, 3.0)])
+def test_frozen_ferromagnet_in_field(oracle_lib, h, beta):
+    """All J = +1, every spin +1: the cheapest flip costs 12 + 2h > 0, and at
+    these beta its threshold is 0, so the state never changes: E = -3N,
+    M = N through sweeps and swaps."""
+    L = 4
+    N = L ** 3
+    assert oracle_lib.flip_threshold_h(beta, 0, 1, h) == 0
+    J = inputs.ferro_couplings(L, 2)
+    sim = _sim(oracle_lib, L, J, np.array([beta, beta * 1.2, beta * 1.5]), h=h)
+    sim.set_state(np.ones_like(sim.spins), sim.temp_of_slot, 0)
+    sim.sweep(30, 1)
+    assert np.all(sim.spins == 1)
+    assert np.all(sim.observables()[0] == -3 * N) and np.all(sim.magnetization() == N)
