@@ -100,6 +100,11 @@ typedef struct ea_options {
     int rng;             /* flip-draw stream: EA_RNG_WORDS (default) or EA_RNG_PLANES
                             (CAMSC only); both give each flip the acceptance law
                             P(draw < threshold) = threshold / 2^32                      */
+    double field;        /* external field h of Eq. 1 (H gains -h sum_i s_i): a multiple of
+                            1/4 in [-8, 8], so that every energy difference the swap step
+                            needs is exact; default 0.  The flip cost becomes
+                            12 - 4u + 2h s and the swap step compares E = 2U - 3N - h M.
+                            Needs EA_RNG_WORDS                                              */
     void *stream;        /* hipStream_t to run on; NULL = the default stream            */
     /* optional device allocator (e.g. backed by a framework's caching allocator);
        both NULL = hipMalloc / hipFree.  dev_alloc returns NULL on failure.            */
@@ -228,6 +233,9 @@ int ea_sim_footprint(const ea_sim *sim, size_t *bytes);
  * q_k = sum_i s_i(copy 0 at temperature k) s_i(copy 1 at temperature k).
  * Either pointer may be NULL.  Synchronous. */
 int ea_observables(ea_sim *sim, int32_t *energy, int32_t *overlap);
+/* Magnetization M = sum_i s_i [R][2][n_T] by temperature index (with a field
+ * the total energy is energy - h M).  Synchronous. */
+int ea_magnetization(ea_sim *sim, int32_t *magnetization);
 
 /* Read the full state: spins int8 [R][2][n_T][L^3] (+1/-1, indexed by slot),
  * temp_of_slot int32 [R][2][n_T], sweeps_done.  Any pointer may be NULL.

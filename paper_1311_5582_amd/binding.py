@@ -33,7 +33,7 @@ class Options(ctypes.Structure):
     _fields_ = [
         ("layout", ctypes.c_int), ("block_threads", ctypes.c_int),
         ("words_resident", ctypes.c_int), ("split", ctypes.c_int), ("rng", ctypes.c_int),
-        ("stream", ctypes.c_void_p),
+        ("field", ctypes.c_double), ("stream", ctypes.c_void_p),
         ("dev_alloc", _ALLOC_FN), ("dev_free", _FREE_FN), ("alloc_ctx", ctypes.c_void_p),
     ]
 
@@ -111,6 +111,7 @@ def lib():
             "ea_sim_footprint": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_size_t)]),
             "ea_sim_info": (ctypes.c_int, [P, i32p, i32p, i32p, ctypes.POINTER(ctypes.c_size_t)]),
             "ea_measure": (ctypes.c_int, [P]),
+            "ea_magnetization": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int32)]),
             "ea_measure_read": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                                ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64)]),
             "ea_measure_reset": (ctypes.c_int, [P]),
@@ -189,7 +190,7 @@ class Sim:
     """One job: R realizations x 2 copies x n_T temperature slots on the GPU."""
 
     def __init__(self, L, couplings, betas, seed, layout="camsc", block_threads=0, words_resident=0,
-                 stream=None, torch_memory=True, split=True, rng="words"):
+                 stream=None, torch_memory=True, split=True, rng="words", h=0.0):
         L = int(L)
         J = np.ascontiguousarray(couplings, dtype=np.int8)
         if J.ndim != 3 or J.shape[1:] != (L ** 3, 3):
@@ -203,6 +204,7 @@ class Sim:
         # True/"auto": library choice; False: one workgroup per ladder; "always": split when possible
         opt.split = {True: 0, "auto": 0, False: 1, "never": 1, "always": 2}[split]
         opt.rng = RNGS[rng] if isinstance(rng, str) else int(rng)
+        opt.field = float(h)
         self._alloc = None
         torch = _torch_gpu() if (torch_memory or stream is not None) else None
         if stream is not None:
@@ -255,6 +257,12 @@ class Sim:
         s = np.ascontiguousarray(spins, dtype=np.int8)
         p = np.ascontiguousarray(temp_of_slot, dtype=np.int32)
         check(lib().ea_set_state(self._h, _p(s, ctypes.c_int8), _p(p, ctypes.c_int32), int(sweeps_done)))
+
+    def magnetization(self):
+        """sum_i s_i [R][2][n_T] by temperature index."""
+        m = np.zeros((self.R, 2, self.n_T), np.int32)
+        check(lib().ea_magnetization(self._h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return m
 
     def measure(self):
         """Add one measurement of the current state to the device accumulators."""
@@ -339,6 +347,12 @@ class Plan:
 
     def run(self, n_steps=1):
         check(lib().ea_plan_run(self._h, int(n_steps)))
+
+    def magnetization(self):
+        """sum_i s_i [R][2][n_T] by temperature index."""
+        m = np.zeros((self.R, 2, self.n_T), np.int32)
+        check(lib().ea_magnetization(self._h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return m
 
     def measure(self):
         """Add one measurement of the current state to the device accumulators."""

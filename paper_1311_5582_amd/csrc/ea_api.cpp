@@ -55,6 +55,29 @@ uint32_t swap_thr(double dbeta_abs, int64_t n)
     return prob_to_u32(std::exp(-(2.0 * dbeta_abs * (double)n)));
 }
 
+// Flip cost 12 - 4u + 2h(2S - 1); the table entry of a cost <= 0 is never read
+// (those flips are certain).
+uint32_t flip_thr_h(double beta, int u, int S, double h)
+{
+    const double dE = (double)(12 - 4 * u) + 2.0 * h * (double)(2 * S - 1);
+    if (dE <= 0.0) return 0xFFFFFFFFu;
+    return prob_to_u32(std::exp(-(beta * dE)));
+}
+
+// Swap threshold for an energy difference |E_a - E_b| = g n / 2, where n
+// indexes the table and g = gcd(4, 4h) (g = 4 without a field: |dE| = 2n).
+uint32_t swap_thr_g(double dbeta_abs, int64_t n, int g)
+{
+    return prob_to_u32(std::exp(-(dbeta_abs * (0.5 * (double)((int64_t)g * n)))));
+}
+
+int field_scale(int m)
+{
+    const int a = m < 0 ? -m : m;
+    if (a == 0 || a % 4 == 0) return 4;
+    return a % 2 == 0 ? 2 : 1;
+}
+
 }  // namespace ea
 
 namespace ea {
@@ -192,9 +215,11 @@ int device_grid(int kv, int bt, size_t lds, int n_units, int *grid)
 
 // Swap tables per pair k: entries n = 0.. while the threshold is non-zero
 // (|U_a - U_b| <= 3N caps the length).  sthr may be NULL to size only.
-int build_swap_tables(const double *betas, int n_T, int N, std::vector<uint32_t> *sthr, std::vector<int32_t> *soff,
-                      std::vector<int32_t> *slen, std::vector<int32_t> *ssgn, int64_t *total)
+int build_swap_tables(const double *betas, int n_T, int N, int m, std::vector<uint32_t> *sthr,
+                      std::vector<int32_t> *soff, std::vector<int32_t> *slen, std::vector<int32_t> *ssgn,
+                      int64_t *total)
 {
+    const int g = field_scale(m);
     if (soff) soff->assign(kMaxTemps, 0);
     if (slen) slen->assign(kMaxTemps, 0);
     if (ssgn) ssgn->assign(kMaxTemps, 0);
@@ -207,16 +232,17 @@ int build_swap_tables(const double *betas, int n_T, int N, std::vector<uint32_t>
         if (soff) (*soff)[k] = (int32_t)count;
         if (sg == 0) continue;
         const double dabs = std::fabs(db);
-        const int64_t cap = 3 * (int64_t)N;
+        // |2 (E_a - E_b)| = |4 dU - m d(up)| <= 12 N + |m| N
+        const int64_t cap = (12 * (int64_t)N + (int64_t)(m < 0 ? -m : m) * N) / g;
         int64_t n = 0;
         for (; n <= cap; ++n) {
-            const uint32_t v = swap_thr(dabs, n);
+            const uint32_t v = swap_thr_g(dabs, n, g);
             if (v == 0) break;
             if (sthr) sthr->push_back(v);
         }
         // the thresholds decrease with n; check that the zero tail stays zero
-        for (int64_t m = n; m <= std::min(cap, n + 64); ++m)
-            if (swap_thr(dabs, m) != 0) return fail(EA_EINVAL, "non-monotone swap table for pair %d", k);
+        for (int64_t q = n; q <= std::min(cap, n + 64); ++q)
+            if (swap_thr_g(dabs, q, g) != 0) return fail(EA_EINVAL, "non-monotone swap table for pair %d", k);
         if (slen) (*slen)[k] = (int32_t)n;
         count += n;
     }
@@ -320,6 +346,9 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
     if (opt.rng != EA_RNG_WORDS && opt.rng != EA_RNG_PLANES) return fail(EA_EINVAL, "unknown rng %d", opt.rng);
     if (opt.rng == EA_RNG_PLANES && opt.layout != EA_LAYOUT_CAMSC)
         return fail(EA_EINVAL, "plane draws need the CAMSC layout");
+    if (!(std::fabs(opt.field) <= 8.0) || 4.0 * opt.field != std::floor(4.0 * opt.field))
+        return fail(EA_EINVAL, "field %g is not a multiple of 1/4 in [-8, 8]", opt.field);
+    if (opt.rng == EA_RNG_PLANES && opt.field != 0.0) return fail(EA_EINVAL, "plane draws need field 0");
     if ((opt.dev_alloc == nullptr) != (opt.dev_free == nullptr))
         return fail(EA_EINVAL, "dev_alloc and dev_free must be given together");
     for (int k = 0; k < n_T; ++k)
@@ -350,15 +379,22 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
 
     const int ladders = 2 * n_realizations;
     // tables
+    const double hf = opt.field;
+    const int m = (int)(4.0 * hf);   // exact: validated as a multiple of 1/4
+    // columns 2E + S; a certain flip (cost <= 0) keeps 0: the kernels never read it
     std::vector<uint32_t> fthr((size_t)n_T * kThrCols, 0u);
+    int a_first[2] = {7, 7};   // smallest E whose flip is certain, per spin bit S (7: none)
+    for (int S = 0; S < 2; ++S)
+        for (int E = 6; E >= 0; --E)
+            if ((double)(12 - 4 * E) + 2.0 * hf * (double)(2 * S - 1) <= 0.0) a_first[S] = E;
     for (int k = 0; k < n_T; ++k)
-        for (int col = 0; col < kThrCols; ++col) {
-            const int E = col >> 1;
-            fthr[(size_t)k * kThrCols + col] = E < 3 ? flip_thr(betas[k], E) : 0u;
+        for (int col = 0; col < 14; ++col) {
+            const int E = col >> 1, S = col & 1;
+            fthr[(size_t)k * kThrCols + col] = E < a_first[S] ? flip_thr_h(betas[k], E, S, hf) : 0u;
         }
     std::vector<int32_t> soff, slen, ssgn;
     std::vector<uint32_t> sthr;
-    if (int rc = build_swap_tables(betas, n_T, N, &sthr, &soff, &slen, &ssgn, nullptr)) return bail(rc);
+    if (int rc = build_swap_tables(betas, n_T, N, m, &sthr, &soff, &slen, &ssgn, nullptr)) return bail(rc);
     // couplings as 6 incidence bits per site
     std::vector<uint8_t> j6((size_t)n_realizations * N);
     for (int r = 0; r < n_realizations; ++r) {
@@ -421,6 +457,12 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
     h.n_sweeps = 0; h.swap_every = 0; h.ladders = ladders; h.block_threads = bt;
     h.seg_bits = 4;
     h.rng = opt.rng;
+    h.field_m = m;
+    h.field_g = field_scale(m);
+    h.always_add0 = (uint32_t)(8 - a_first[0]) * 0x11111111u;
+    h.always_add1 = (uint32_t)(8 - a_first[1]) * 0x11111111u;
+    h.always_col0 = 2 * a_first[0];
+    h.always_col1 = 2 * a_first[1] + 1;
     h.invL = 1.0f / (float)L;
     h.invH = 1.0f / (float)(L / 2 > 0 ? L / 2 : 1);
     s->swap_total = (int64_t)sthr.size();
@@ -443,7 +485,7 @@ int ea_job_footprint(int L, const double *betas, int n_T, int n_realizations, in
         (layout < EA_LAYOUT_CAMSC || layout > EA_LAYOUT_AMSC1))
         return fail(EA_EINVAL, "ea_job_footprint: bad arguments");
     int64_t total = 0;
-    if (int rc = build_swap_tables(betas, n_T, L * L * L, nullptr, nullptr, nullptr, nullptr, &total)) return rc;
+    if (int rc = build_swap_tables(betas, n_T, L * L * L, 0, nullptr, nullptr, nullptr, nullptr, &total)) return rc;
     *bytes = job_footprint_bytes(L, n_T, n_realizations, layout, total);
     return EA_OK;
 }
@@ -580,12 +622,27 @@ int ea_observables(ea_sim *s, int32_t *energy, int32_t *overlap)
     const size_t ne = (size_t)s->R * 2 * s->n_T, nq = (size_t)s->R * s->n_T;
     int32_t *d = nullptr;
     EA_HIP(hipMalloc(&d, (ne + nq) * sizeof(int32_t)));
-    hipError_t e = launch_observables(s->d_job, s->h, s->layout, d, d + ne, s->stream);
+    hipError_t e = launch_observables(s->d_job, s->h, s->layout, d, d + ne, nullptr, s->stream);
     if (e == hipSuccess && energy) e = hipMemcpyAsync(energy, d, ne * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess && overlap) e = hipMemcpyAsync(overlap, d + ne, nq * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     (void)hipFree(d);
     if (e != hipSuccess) return fail(EA_EDEVICE, "observables failed: %s", hipGetErrorString(e));
+    return check_split_error(s);
+}
+
+int ea_magnetization(ea_sim *s, int32_t *magnetization)
+{
+    if (!s || !magnetization) return fail(EA_EINVAL, "ea_magnetization: NULL argument");
+    EA_HIP(hipSetDevice(s->device));
+    const size_t ne = (size_t)s->R * 2 * s->n_T;
+    int32_t *d = nullptr;
+    EA_HIP(hipMalloc(&d, ne * sizeof(int32_t)));
+    hipError_t e = launch_observables(s->d_job, s->h, s->layout, nullptr, nullptr, d, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(magnetization, d, ne * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(EA_EDEVICE, "magnetization failed: %s", hipGetErrorString(e));
     return check_split_error(s);
 }
 

@@ -30,6 +30,9 @@ int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 uint32_t prob_to_u32(double p);
 uint32_t flip_thr(double beta, int u);
 uint32_t swap_thr(double dbeta_abs, int64_t n);
+uint32_t flip_thr_h(double beta, int u, int S, double h);
+uint32_t swap_thr_g(double dbeta_abs, int64_t n, int g);
+int field_scale(int m);   // g = gcd(4, m), 4 for m = 0
 
 struct DeviceAlloc {
     void *(*alloc)(size_t, void *) = nullptr;
@@ -38,7 +41,7 @@ struct DeviceAlloc {
 };
 
 int wgs_per_cu(size_t lds, int bt);
-int build_swap_tables(const double *betas, int n_T, int N, std::vector<uint32_t> *sthr, std::vector<int32_t> *soff,
+int build_swap_tables(const double *betas, int n_T, int N, int m, std::vector<uint32_t> *sthr, std::vector<int32_t> *soff,
                       std::vector<int32_t> *slen, std::vector<int32_t> *ssgn, int64_t *total);
 size_t job_footprint_bytes(int L, int n_T, int R, int layout, int64_t swap_entries);
 int device_grid(int kv, int bt, size_t lds, int n_units, int *grid);   // kv: kernel_variant()

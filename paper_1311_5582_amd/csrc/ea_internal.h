@@ -74,6 +74,12 @@ struct JobDesc {
     uint64_t *xchg;           // [ladders][2][kMaxTemps] (sweep index + 1) << 32 | slot energy, split workgroups
     uint32_t *error;          // set to non-zero if a split exchange timed out
     int32_t rng;              // EA_RNG_WORDS or EA_RNG_PLANES (CAMSC only)
+    int32_t field_m;          // 4h (the field h is a multiple of 1/4); 0 without a field
+    int32_t field_g;          // gcd(4, field_m): slot value W = (4U - m up) / g indexes the swap tables
+    uint32_t always_add0;     // (8 - a_S) in every 4-bit segment: E + this >= 8 iff E >= a_S,
+    uint32_t always_add1;     //   a_S = smallest E whose flip is certain for spin bit S
+    int32_t always_col0;      // the same as a column 2E+S: certain iff 2E+S >= always_col[S]
+    int32_t always_col1;
     int32_t pad_;
 };
 
@@ -93,6 +99,7 @@ struct LdsLayout {
     uint32_t acc;     // [kMaxTemps] u32 accepted swaps of this unit
     uint32_t mask;    // [kMaxTemps] u64 speculative accept bits
     uint32_t ptab;    // [2 words][3 E][32 planes] u32 bit-sliced thresholds by slot (EA_RNG_PLANES)
+    uint32_t up;      // [kMaxTemps] i32 spins up per slot (with a field)
     uint32_t spin;    // [words][N] u32 spin words
     uint32_t stab;    // [swap_entries] u32 swap tables (optional)
     uint32_t sites;   // [site_entries] u32 packed coordinates (optional)
@@ -115,7 +122,8 @@ __host__ __device__ inline LdsLayout lds_layout(int N, int words, int swap_entri
     l.acc = l.ssgn + kMaxTemps * 4;
     l.mask = l.acc + kMaxTemps * 4;
     l.ptab = l.mask + kMaxTemps * 8;
-    l.spin = l.ptab + 2 * 3 * 32 * 4;
+    l.up = l.ptab + 2 * 3 * 32 * 4;
+    l.spin = l.up + kMaxTemps * 4;
     l.stab = l.spin + (uint32_t)words * (uint32_t)N * 4u;
     l.sites = l.stab + (uint32_t)swap_entries * 4u;
     l.j6 = l.sites + (uint32_t)site_entries * 4u;
@@ -138,7 +146,7 @@ hipError_t launch_sweep_split(const JobDesc *d_job, int ladders, int parts, int 
                               uint32_t *d_queue, hipStream_t s);
 int sweep_split_max_blocks_per_cu(int parts, int kv, int block_threads, size_t lds);
 hipError_t launch_observables(const JobDesc *d_job, const JobDesc &h_job, int layout, int32_t *d_energy,
-                              int32_t *d_overlap, hipStream_t s);
+                              int32_t *d_overlap, int32_t *d_magnet, hipStream_t s);
 hipError_t launch_unpack(const JobDesc *d_job, const JobDesc &h_job, int layout, int8_t *d_spins, hipStream_t s);
 hipError_t launch_measure(const JobDesc *d_job, const JobDesc &h_job, int layout, int64_t *count, int64_t *sum_q2,
                           uint64_t *sum_q4, int64_t *sum_c, hipStream_t s);

@@ -135,6 +135,7 @@ struct Smem {
     uint32_t *acc;    // accepted swaps per pair in this unit
     uint64_t *mask;   // speculative accept bits per pair
     uint32_t *ptab;   // [2][3][32] bit-sliced thresholds by slot (plane draws)
+    int32_t *up;      // spins up per slot (with a field)
     uint32_t *spin;   // [words_resident][N]
     uint32_t *stab;   // swap tables (when cached)
     uint32_t *sites;  // odd-L site list (when cached)
@@ -152,6 +153,7 @@ __device__ __forceinline__ Smem carve(uint8_t *base, int N, int words, int swap_
     s.sot = (int32_t *)(base + l.sot);
     s.draw = (uint32_t *)(base + l.draw);
     s.ptab = (uint32_t *)(base + l.ptab);
+    s.up = (int32_t *)(base + l.up);
     s.soff = (int32_t *)(base + l.soff);
     s.slen = (int32_t *)(base + l.slen);
     s.ssgn = (int32_t *)(base + l.ssgn);
@@ -366,6 +368,29 @@ __device__ __forceinline__ void reduce_planes8_add(const uint32_t (&P8)[8], int 
     }
 }
 
+// Certain flips (cost <= 0).  Without a field they are the slots with E >= 3;
+// with a field h the bound depends on the spin: E >= a_S for spin bit S.
+struct Field {
+    bool on;
+    uint32_t add0, add1;   // (8 - a_S) per 4-bit segment
+    int col0, col1;        // certain iff column 2E+S >= col_S
+};
+
+__device__ __forceinline__ Field field_of(const JobDesc &jd)
+{
+    return Field{jd.field_m != 0, jd.always_add0, jd.always_add1, jd.always_col0, jd.always_col1};
+}
+
+// Segments (4 bits, bit 0 = S in Sb) of E >= a_S: E + (8 - a_S) reaches bit 3
+// without leaving the segment (E <= 6).
+__device__ __forceinline__ uint32_t certain_segments(uint32_t E, uint32_t Sb, const Field &fd)
+{
+    constexpr uint32_t M = 0x11111111u;
+    const uint32_t ge0 = ((E + fd.add0) >> 3) & M;
+    const uint32_t ge1 = ((E + fd.add1) >> 3) & M;
+    return (ge1 & Sb) | (ge0 & ~Sb);
+}
+
 // ---------------------------------------------------------------------------
 // Metropolis update of one site for the `gw` resident words (word index g0..).
 // ---------------------------------------------------------------------------
@@ -380,8 +405,8 @@ __device__ __forceinline__ void reduce_planes8_add(const uint32_t (&P8)[8], int 
 template <int LAYOUT, bool ACC = false, bool SPLIT = false, int RNG = 0>
 __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int N, int gw, int g0, int n_T,
                                             uint32_t t, uint32_t r, uint32_t c3base, uint32_t k0, uint32_t k1,
-                                            uint32_t segw, uint32_t (*P)[8] = nullptr, int np = 0, int gb = 0,
-                                            int ngr_own = 0)
+                                            uint32_t segw, const Field &fd, uint32_t (*P)[8] = nullptr, int np = 0,
+                                            int gb = 0, int ngr_own = 0)
 {
     constexpr uint32_t M = 0x11111111u;
     const uint32_t j6 = sm.j6[nb.i];
@@ -447,7 +472,13 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
                 const uint32_t E = ((e0 >> k) & M) + ((e1 >> k) & M) + ((e2 >> k) & M) + ((e3 >> k) & M) +
                                    ((e4 >> k) & M) + ((e5 >> k) & M);
                 X[k] = (E << 1) | ((S >> k) & M);
-                always |= (((X[k] + 0x22222222u) >> 3) & M) << k;   // 2E+S >= 6  <=>  E >= 3
+            }
+            if (!fd.on) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) always |= (((X[k] + 0x22222222u) >> 3) & M) << k;   // 2E+S >= 6 <=> E >= 3
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) always |= certain_segments((X[k] >> 1) & 0x77777777u, X[k] & M, fd) << k;
             }
             const int slot0 = wg * 32;
             const int left = n_T - slot0;
@@ -490,7 +521,7 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
             // AMSC4: 4-bit segments throughout; 2E+S is formed for all slots at once.
             const uint32_t E = e0 + e1 + e2 + e3 + e4 + e5;
             const uint32_t X = (E << 1) | S;
-            const uint32_t always = ((X + 0x22222222u) >> 3) & M;
+            const uint32_t always = fd.on ? certain_segments(E, S, fd) : ((X + 0x22222222u) >> 3) & M;
             const int slot0 = wg * 8;
             const int left = n_T - slot0;
             const uint32_t valid = left >= 8 ? M : (M & ((1u << (4 * left)) - 1u));
@@ -512,9 +543,7 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
             uint32_t flip = 0;
             U4 blk{0u, 0u, 0u, 0u};
             int cur = -1;
-#pragma unroll
-            for (int j = 0; j < SPW; ++j) {
-                if (j >= n) break;
+            for (int j = 0; j < n; ++j) {
                 const int slot = slot0 + j;
                 if ((slot >> 2) != cur) {   // uniform across the wave
                     cur = slot >> 2;
@@ -526,10 +555,11 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
                 else
                     E = ((e0 >> j) & 1u) + ((e1 >> j) & 1u) + ((e2 >> j) & 1u) + ((e3 >> j) & 1u) +
                         ((e4 >> j) & 1u) + ((e5 >> j) & 1u);
-                const uint32_t col = (E << 1) | ((S >> (j * STR)) & 1u);
+                const uint32_t sbit = (S >> (j * STR)) & 1u;
+                const uint32_t col = (E << 1) | sbit;
                 const int q = slot & 3;
                 const uint32_t dr = q == 0 ? blk.x : (q == 1 ? blk.y : (q == 2 ? blk.z : blk.w));
-                const bool f = col >= 6u || dr < rows[j * kThrCols + col];
+                const bool f = (int)col >= (sbit ? fd.col1 : fd.col0) || dr < rows[j * kThrCols + col];
                 flip |= (f ? 1u : 0u) << (j * STR);
             }
             sw[nb.i] = S ^ flip;
@@ -616,6 +646,42 @@ __device__ __forceinline__ void count_unsat_word(const uint32_t *words, const ui
     }
 }
 
+// Spins up per slot for one word, added into U[slot0 + b] (the same plane
+// counters and wave reduction as the bond counts, one bit per site).
+template <int LAYOUT, int NP>
+__device__ void count_up_word_np(const uint32_t *words, int N, int slot0, int n_T, int *U)
+{
+    constexpr int SPW = Layout<LAYOUT>::kSlotsPerWord;
+    constexpr int STR = Layout<LAYOUT>::kStride;
+    uint32_t P[14];
+#pragma unroll
+    for (int p = 0; p < 14; ++p) P[p] = 0;
+    for (int idx = threadIdx.x; idx < N; idx += blockDim.x) {
+        uint32_t carry = words[idx] & Layout<LAYOUT>::kKeep;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const uint32_t tt = P[p] & carry;
+            P[p] ^= carry;
+            carry = tt;
+        }
+    }
+    reduce_planes_add<NP, STR>(P, min(SPW, n_T - slot0), U + slot0);
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ void count_up_word(const uint32_t *words, int N, int slot0, int n_T, int np, int *U)
+{
+    switch (np) {
+        case 2: count_up_word_np<LAYOUT, 2>(words, N, slot0, n_T, U); break;
+        case 3: count_up_word_np<LAYOUT, 3>(words, N, slot0, n_T, U); break;
+        case 4: count_up_word_np<LAYOUT, 4>(words, N, slot0, n_T, U); break;
+        case 5: count_up_word_np<LAYOUT, 5>(words, N, slot0, n_T, U); break;
+        case 6: count_up_word_np<LAYOUT, 6>(words, N, slot0, n_T, U); break;
+        case 7: count_up_word_np<LAYOUT, 7>(words, N, slot0, n_T, U); break;
+        default: count_up_word_np<LAYOUT, 8>(words, N, slot0, n_T, U); break;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Sweep kernel.
 //
@@ -693,6 +759,7 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
             sm.perm[tid] = tid < n_T ? jd.temp_of_slot[ladder * kMaxTemps + tid] : 0;
             sm.acc[tid] = 0;
             sm.U[tid] = 0;
+            sm.up[tid] = 0;
             sm.mask[tid] = 0ull;
             sm.soff[tid] = jd.swap_off[tid];
             sm.slen[tid] = jd.swap_len[tid];
@@ -722,7 +789,8 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
         // CAMSC on a bipartite lattice with every word resident: the slot
         // energies come out of the last colour class of the swap sweep
         const int np_b = planes_for_class(half, nthr);
-        const bool fused_energy = LAYOUT == 0 && even && NW == 1 && np_b <= 8;
+        const Field fd = field_of(jd);
+        const bool fused_energy = LAYOUT == 0 && even && NW == 1 && np_b <= 8 && !fd.on;
         // slot groups this workgroup decides (all of them unless split)
         const int ngr_own = SPLIT ? ((n_T + 3) >> 2) / PARTS : 0;
         const int gb = SPLIT ? part * ngr_own : 0;
@@ -752,17 +820,17 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                     if (even) {
                         for (int j = tid; j < half; j += nthr)
                             update_site<LAYOUT, false, SPLIT, RNG>(sm, checker_site(j, 0, L, invH, invL), N, gw, g0, n_T,
-                                                              ts, r, c3flip, k0, k1, segw, nullptr, 0, gb, ngr_own);
+                                                              ts, r, c3flip, k0, k1, segw, fd, nullptr, 0, gb, ngr_own);
                         __syncthreads();
                         if (fused_energy && swap_now && s == chunk - 1) {
                             for (int j = tid; j < half; j += nthr)
                                 update_site<LAYOUT, true, SPLIT, RNG>(sm, checker_site(j, 1, L, invH, invL), N, gw, g0,
-                                                                 n_T, ts, r, c3flip, k0, k1, segw, P, np_b, gb,
+                                                                 n_T, ts, r, c3flip, k0, k1, segw, fd, P, np_b, gb,
                                                                  ngr_own);
                         } else {
                             for (int j = tid; j < half; j += nthr)
                                 update_site<LAYOUT, false, SPLIT, RNG>(sm, checker_site(j, 1, L, invH, invL), N, gw, g0,
-                                                                  n_T, ts, r, c3flip, k0, k1, segw, nullptr, 0, gb,
+                                                                  n_T, ts, r, c3flip, k0, k1, segw, fd, nullptr, 0, gb,
                                                                   ngr_own);
                         }
                         __syncthreads();
@@ -771,7 +839,7 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                             const int end = jd.class_off[c + 1];
                             for (int it = jd.class_off[c] + tid; it < end; it += nthr)
                                 update_site<LAYOUT, false, false, RNG>(sm, neighbours_packed(slist[it], L), N, gw, g0, n_T, ts, r,
-                                                    c3flip, k0, k1, segw);
+                                                    c3flip, k0, k1, segw, fd);
                             __syncthreads();
                         }
                     }
@@ -780,9 +848,11 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                     if (fused_energy) {
                         reduce_planes8_add<1>(P[0], np_b, s_hi - s_lo, sm.U, s_lo);
                     } else {
-                        for (int w = 0; w < gw; ++w)
+                        for (int w = 0; w < gw; ++w) {
                             count_unsat_word<LAYOUT>(sm.spin + (size_t)w * N, sm.j6, N, L, invL, (g0 + w) * SPW, n_T,
                                                      np, sm.U);
+                            if (fd.on) count_up_word<LAYOUT>(sm.spin + (size_t)w * N, N, (g0 + w) * SPW, n_T, np, sm.up);
+                        }
                     }
                 }
                 if (n_groups > 1) {
@@ -794,6 +864,15 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                 // ---- replica-exchange pass after sweep t + chunk - 1 ----
                 const uint32_t tswap = t + (uint32_t)chunk - 1u;
                 const int pairs = n_T - 1;
+                if (fd.on) {
+                    // with a field the slot value is W = (4U - m up) / g, so that
+                    // 2 (E_a - E_b) = g (W_a - W_b) (exact: g divides both terms)
+                    __syncthreads();
+                    if (tid < kMaxTemps) {
+                        sm.U[tid] = (4 * sm.U[tid] - jd.field_m * sm.up[tid]) / jd.field_g;
+                        sm.up[tid] = 0;
+                    }
+                }
                 if (SPLIT) {
                     // Publish own slots' energies and collect the partners'.
                     // Each word carries its sweep tag, so plain relaxed
@@ -900,7 +979,10 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                 }
             } else if (swap_now) {
                 __syncthreads();
-                if (tid < kMaxTemps) sm.U[tid] = 0;
+                if (tid < kMaxTemps) {
+                    sm.U[tid] = 0;
+                    sm.up[tid] = 0;
+                }
                 __syncthreads();
             }
             t += (uint32_t)chunk;
@@ -1034,19 +1116,21 @@ __global__ void __launch_bounds__(256) measure_kernel(const JobDesc *__restrict_
 // ---------------------------------------------------------------------------
 template <int LAYOUT>
 __global__ void __launch_bounds__(512) observables_kernel(const JobDesc *__restrict__ jd_ptr, int32_t *energy,
-                                                          int32_t *overlap)
+                                                          int32_t *overlap, int32_t *magnet)
 {
     constexpr int SPW = Layout<LAYOUT>::kSlotsPerWord;
     constexpr int STR = Layout<LAYOUT>::kStride;
     __shared__ int s_U[2][kMaxTemps];
     __shared__ int s_diff[kMaxTemps];
     __shared__ int s_sot[2][kMaxTemps];
+    __shared__ int s_up[2][kMaxTemps];
     const JobDesc &jd = *jd_ptr;
     const int r = blockIdx.x;
     const int N = jd.N, n_T = jd.n_T, NW = jd.NW;
     const int tid = threadIdx.x;
     if (tid < kMaxTemps) {
         s_U[0][tid] = s_U[1][tid] = 0;
+        s_up[0][tid] = s_up[1][tid] = 0;
         s_diff[tid] = 0;
     }
     __syncthreads();
@@ -1059,8 +1143,11 @@ __global__ void __launch_bounds__(512) observables_kernel(const JobDesc *__restr
     const uint8_t *j6 = jd.j6 + (size_t)r * N;
     for (int c = 0; c < 2; ++c)
         for (int w = 0; w < NW; ++w)
+        {
             count_unsat_word<LAYOUT>(jd.spins + ((size_t)(2 * r + c) * NW + w) * N, j6, N, jd.L, jd.invL, w * SPW,
                                      n_T, np, s_U[c]);
+            if (magnet) count_up_word<LAYOUT>(jd.spins + ((size_t)(2 * r + c) * NW + w) * N, N, w * SPW, n_T, np, s_up[c]);
+        }
     // overlap between the copies at equal temperature index
     const uint32_t *s0 = jd.spins + (size_t)(2 * r) * NW * N;
     const uint32_t *s1 = jd.spins + (size_t)(2 * r + 1) * NW * N;
@@ -1078,6 +1165,7 @@ __global__ void __launch_bounds__(512) observables_kernel(const JobDesc *__restr
     if (tid < 2 * n_T) {
         const int c = tid / n_T, k = tid % n_T;
         if (energy) energy[((size_t)r * 2 + c) * n_T + k] = 2 * s_U[c][s_sot[c][k]] - 3 * N;
+        if (magnet) magnet[((size_t)r * 2 + c) * n_T + k] = 2 * s_up[c][s_sot[c][k]] - N;
     }
     if (tid < n_T && overlap) overlap[(size_t)r * n_T + tid] = N - 2 * s_diff[tid];
 }
@@ -1215,14 +1303,14 @@ int sweep_split_max_blocks_per_cu(int parts, int kv, int block_threads, size_t l
 }
 
 hipError_t launch_observables(const JobDesc *d_job, const JobDesc &h, int layout, int32_t *d_energy,
-                              int32_t *d_overlap, hipStream_t s)
+                              int32_t *d_overlap, int32_t *d_magnet, hipStream_t s)
 {
     const int R = h.ladders / 2;
     // AMSC1 words are stored like CAMSC words
     switch (storage_layout(layout)) {
-        case 0: hipLaunchKernelGGL(observables_kernel<0>, dim3(R), dim3(512), 0, s, d_job, d_energy, d_overlap); break;
-        case 1: hipLaunchKernelGGL(observables_kernel<1>, dim3(R), dim3(512), 0, s, d_job, d_energy, d_overlap); break;
-        default: hipLaunchKernelGGL(observables_kernel<2>, dim3(R), dim3(512), 0, s, d_job, d_energy, d_overlap); break;
+        case 0: hipLaunchKernelGGL(observables_kernel<0>, dim3(R), dim3(512), 0, s, d_job, d_energy, d_overlap, d_magnet); break;
+        case 1: hipLaunchKernelGGL(observables_kernel<1>, dim3(R), dim3(512), 0, s, d_job, d_energy, d_overlap, d_magnet); break;
+        default: hipLaunchKernelGGL(observables_kernel<2>, dim3(R), dim3(512), 0, s, d_job, d_energy, d_overlap, d_magnet); break;
     }
     return hipGetLastError();
 }

@@ -44,7 +44,8 @@ def test_swap_thresholds_match_oracle(lib, oracle_lib):
             assert B.swap_threshold(db, n) == oracle_lib.swap_threshold(db, n), (db, n)
 
 
-def _create(lib, L=4, n_T=4, R=1, J=None, betas=None, layout=0, block_threads=0, words_resident=0, split=0, rng=0):
+def _create(lib, L=4, n_T=4, R=1, J=None, betas=None, layout=0, block_threads=0, words_resident=0, split=0, rng=0,
+            field=0.0):
     if J is None:
         J = inputs.couplings(L, R, seed=1) if L >= 2 else np.ones((R, max(L, 1) ** 3, 3), np.int8)
     if betas is None:
@@ -55,6 +56,7 @@ def _create(lib, L=4, n_T=4, R=1, J=None, betas=None, layout=0, block_threads=0,
     lib.ea_default_options(ctypes.byref(opt))
     opt.layout, opt.block_threads, opt.words_resident, opt.split = layout, block_threads, words_resident, split
     opt.rng = rng
+    opt.field = field
     h = ctypes.c_void_p()
     rc = lib.ea_create(L, J.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
                        b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n_T, R, 7, ctypes.byref(opt),
@@ -68,6 +70,7 @@ def _create(lib, L=4, n_T=4, R=1, J=None, betas=None, layout=0, block_threads=0,
     dict(betas=[1.0, 0.0, 0.5, 0.2]), dict(betas=[1.0, -1.0, 0.5, 0.2]), dict(betas=[1.0, float("nan"), 0.5, 0.2]),
     dict(betas=[1.0, float("inf"), 0.5, 0.2]), dict(words_resident=-1), dict(split=3), dict(split=-1),
     dict(rng=2), dict(rng=-1), dict(rng=1, layout=1),
+    dict(field=0.3), dict(field=8.25), dict(field=float("nan")), dict(field=float("inf")), dict(field=0.5, rng=1),
     dict(L=32, n_T=64, words_resident=2, J=np.ones((1, 32 ** 3, 3), np.int8)),
 ])
 def test_create_rejects_invalid_arguments(lib, case):

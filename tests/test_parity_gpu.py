@@ -29,16 +29,17 @@ def _report(tag, **kw):
 
 
 def run_pair(oracle_lib, L, R, n_T, seed, sweeps, swap_every, layout="camsc", t_min=0.4, t_max=2.0,
-             rids=None, block_threads=0, words_resident=0, couplings=None, splits=None, rng="words", split=True):
+             rids=None, block_threads=0, words_resident=0, couplings=None, splits=None, rng="words", split=True,
+             h=0.0):
     """Run the GPU on all R realizations and the oracle on `rids`; compare."""
     _report("run", L=L, R=R, n_T=n_T, seed=seed, sweeps=sweeps, swap_every=swap_every, layout=layout,
-            bt=block_threads, wr=words_resident, rng=rng, split=split)
+            bt=block_threads, wr=words_resident, rng=rng, split=split, h=h)
     J = inputs.couplings(L, R, seed) if couplings is None else couplings
     betas = inputs.geometric_betas(n_T, t_min, t_max)
     rids = list(range(R)) if rids is None else list(rids)
     sim = B.Sim(L, J, betas, seed, layout=layout, block_threads=block_threads, words_resident=words_resident,
-                rng=rng, split=split)
-    orc = oracle_lib.OracleSim(L, J[rids], betas, seed, rid=np.array(rids), rng=rng)
+                rng=rng, split=split, h=h)
+    orc = oracle_lib.OracleSim(L, J[rids], betas, seed, rid=np.array(rids), rng=rng, h=h)
     s0, p0, t0 = sim.state()
     assert t0 == 0
     assert np.array_equal(s0[rids], orc.spins), "initial spins differ"
@@ -258,3 +259,22 @@ def test_repeated_temperatures(oracle_lib, rng):
     s, perm, t = sim.state()
     assert np.array_equal(perm, orc.temp_of_slot) and np.array_equal(s, orc.spins)
     assert np.array_equal(sim.observables()[0], orc.observables()[0])
+
+
+@pytest.mark.parametrize("L,R,n_T,layout,h,split", [
+    (6, 3, 16, "camsc", 0.75, True),
+    (5, 2, 22, "camsc", -1.25, True),      # odd L
+    (4, 2, 40, "camsc", 0.25, True),       # two words per site
+    (8, 1, 16, "camsc", 2.0, "always"),    # split ladders
+    (6, 2, 13, "amsc4", -0.5, True),
+    (5, 2, 23, "amsc3", 1.5, True),
+    (6, 2, 33, "amsc1", -3.0, True),
+    (4, 2, 12, "camsc", 8.0, True),        # every flip against the field is certain or impossible
+])
+def test_field_equals_oracle(oracle_lib, L, R, n_T, layout, h, split):
+    """External field h (a multiple of 1/4): flips, swaps, energies, overlaps
+    and magnetizations bit for bit the oracle's."""
+    sim, orc, *_ = run_pair(oracle_lib, L, R, n_T, 6000 + 11 * L + n_T, 19, 1, layout=layout, h=h, split=split,
+                            t_min=0.5, t_max=3.0, splits=[4, 15])
+    assert np.array_equal(sim.magnetization(), orc.magnetization())
+    print(f"[parity] field launch {sim.info()}", flush=True)
