@@ -463,19 +463,21 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
                 planes_add3(*P, E0, C1, C2, np);
             }
         } else if (LAYOUT == 0) {
-            // CAMSC: widen each 1-bit bond word into four 4-bit-segment words
-            // (segment j of word k holds slot 4j + k), sum, append S.
+            // CAMSC: sum the six 1-bit bond words as three bit planes (full
+            // adders, one bitop3 each), then widen into four 4-bit-segment words
+            // (segment j of word k holds slot 4j + k) that carry 2E+S:
+            // S | E0 << 1 | E1 << 2 | E2 << 3 of that slot.
+            const uint32_t s1 = xor3(e0, e1, e2), c1 = maj3(e0, e1, e2);
+            const uint32_t s2 = xor3(e3, e4, e5), c2 = maj3(e3, e4, e5);
+            const uint32_t E0 = s1 ^ s2, kk = s1 & s2;
+            const uint32_t E1 = xor3(c1, c2, kk), E2 = maj3(c1, c2, kk);
             uint32_t X[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                X[k] = ((S >> k) & M) | (((E0 >> k) & M) << 1) | (((E1 >> k) & M) << 2) | (((E2 >> k) & M) << 3);
             uint32_t always = 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uint32_t E = ((e0 >> k) & M) + ((e1 >> k) & M) + ((e2 >> k) & M) + ((e3 >> k) & M) +
-                                   ((e4 >> k) & M) + ((e5 >> k) & M);
-                X[k] = (E << 1) | ((S >> k) & M);
-            }
             if (!fd.on) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) always |= (((X[k] + 0x22222222u) >> 3) & M) << k;   // 2E+S >= 6 <=> E >= 3
+                always = E2 | (E1 & E0);   // E >= 3, bit s = slot s
             } else {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) always |= certain_segments((X[k] >> 1) & 0x77777777u, X[k] & M, fd) << k;
