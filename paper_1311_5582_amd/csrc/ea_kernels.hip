@@ -368,6 +368,14 @@ __device__ __forceinline__ void reduce_planes8_add(const uint32_t (&P8)[8], int 
     }
 }
 
+// Exchange the bits of a selected by m << sh with the bits of b selected by m.
+__device__ __forceinline__ void swap_bits(uint32_t &a, uint32_t &b, int sh, uint32_t m)
+{
+    const uint32_t t = ((a >> sh) ^ b) & m;
+    b ^= t;
+    a ^= t << sh;
+}
+
 // Certain flips (cost <= 0).  Without a field they are the slots with E >= 3;
 // with a field h the bound depends on the spin: E >= a_S for spin bit S.
 struct Field {
@@ -471,10 +479,13 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
             const uint32_t s2 = xor3(e3, e4, e5), c2 = maj3(e3, e4, e5);
             const uint32_t E0 = s1 ^ s2, kk = s1 & s2;
             const uint32_t E1 = xor3(c1, c2, kk), E2 = maj3(c1, c2, kk);
-            uint32_t X[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                X[k] = ((S >> k) & M) | (((E0 >> k) & M) << 1) | (((E1 >> k) & M) << 2) | (((E2 >> k) & M) << 3);
+            // word p bit k of every nibble -> word k bit p: a 4 x 4 bit transpose
+            // inside each nibble by two rounds of masked swaps
+            uint32_t X[4] = {S, E0, E1, E2};
+            swap_bits(X[0], X[2], 2, 0x33333333u);
+            swap_bits(X[1], X[3], 2, 0x33333333u);
+            swap_bits(X[0], X[1], 1, 0x55555555u);
+            swap_bits(X[2], X[3], 1, 0x55555555u);
             uint32_t always = 0;
             if (!fd.on) {
                 always = E2 | (E1 & E0);   // E >= 3, bit s = slot s
