@@ -237,17 +237,24 @@ __device__ __forceinline__ uint32_t camsc_decide_planes(uint32_t und, uint32_t m
     // byte selectors of v_perm_b32: one 16-bit field moved to bit `lo`, other bits 0
     const uint32_t sel_even = lo ? 0x01000C0Cu : 0x0C0C0100u;
     const uint32_t sel_odd = lo ? 0x03020C0Cu : 0x0C0C0302u;
+    // two blocks (16 planes) per round: a wave of 64 lanes almost never
+    // decides all its slots within 8 planes, and two independent Philox chains
+    // per half keep the SIMD busy
 #pragma unroll 1
-    for (int g = 0; g < 4; ++g) {
+    for (int g = 0; g < 4; g += 2) {
         if (__builtin_amdgcn_ballot_w64(und != 0u) == 0ull) break;   // every lane decided
-        const U4 a = philox10(site, t, r, c3 + (uint32_t)g, k0, k1);
-        U4 b = a;
-        if (NH == 2) b = philox10(site, t, r, c3 + (1u << 8) + (uint32_t)g, k0, k1);
-        const uint32_t wa[4] = {a.x, a.y, a.z, a.w};
-        const uint32_t wb[4] = {b.x, b.y, b.z, b.w};
+        const U4 a0 = philox10(site, t, r, c3 + (uint32_t)g, k0, k1);
+        const U4 a1 = philox10(site, t, r, c3 + (uint32_t)g + 1u, k0, k1);
+        U4 b0 = a0, b1 = a1;
+        if (NH == 2) {
+            b0 = philox10(site, t, r, c3 + (1u << 8) + (uint32_t)g, k0, k1);
+            b1 = philox10(site, t, r, c3 + (1u << 8) + (uint32_t)g + 1u, k0, k1);
+        }
+        const uint32_t wa[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+        const uint32_t wb[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
         const uint32_t *p0 = pt + 8 * g;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < 16; ++q) {
             uint32_t R;
             if (NH == 2)   // low halves of both blocks' word, or high halves: slots 0..15 | 16..31
                 R = __builtin_amdgcn_perm(wb[q >> 1], wa[q >> 1], (q & 1) ? 0x07060302u : 0x05040100u);
