@@ -940,8 +940,9 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                     const int len = sm.slen[kk];
                     const int off = sm.soff[kk];
                     const uint32_t dr = sm.draw[kk];
+                    const int u_here = sm.U[sm.sot[lane < n_T ? lane : 0]];   // lane j: energy at position j
                     for (int j = wave; j < pairs; j += nwaves) {
-                        const int d = sm.U[sm.sot[j]] - u_next;
+                        const int d = __builtin_amdgcn_readlane(u_here, j) - u_next;
                         const int n = d < 0 ? -d : d;
                         const uint32_t thr = len > 0 ? stab[off + min(n, len - 1)] : 0u;
                         const bool favourable = (sg == 0) || (d == 0) || ((sg > 0) == (d > 0));
