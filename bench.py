@@ -190,13 +190,14 @@ def bench_batched(B, inputs, torch, sweeps, steps):
             "units": info["units"], "uses_graph": info["uses_graph"]}
 
 
-def bench_serving(B, inputs, n_jobs, rate, quantum, sweep_scale=1.0):
-    """Poisson job trace through the continuous-batching server."""
+def bench_serving(B, inputs, n_jobs, rate, quantum, sweep_scale=1.0, max_active=0):
+    """Poisson job trace through the continuous-batching server (max_active=1:
+    the same server as a plain queue, one job on the GPU at a time)."""
     from paper_1311_5582_amd import serve
     trace = inputs.serving_trace(n_jobs=n_jobs, rate_per_s=rate)
     for j in trace:
         j["sweeps"] = max(1, int(j["sweeps"] * sweep_scale))
-    srv = B.Server(quantum_sweeps=quantum)
+    srv = B.Server(quantum_sweeps=quantum, max_active=max_active)
     recs, wall = serve.run_trace(trace, srv)
     st = srv.stats()
     srv.close()
@@ -337,6 +338,9 @@ def main():
         cap = out["serving"]["jobs"] / max(out["serving"]["wall_s"], 1e-9)
         out["serving_at_0.8_capacity"] = bench_serving(B, inputs, args.serving_jobs, 0.8 * cap,
                                                       args.serving_quantum, args.serving_scale)
+        # the first trace through a plain queue: one job on the GPU at a time
+        out["serving_queue_only"] = bench_serving(B, inputs, args.serving_jobs, 20.0, args.serving_quantum,
+                                                  args.serving_scale, max_active=1)
     if not args.no_cpu_baseline:
         threads = max(1, min(os.cpu_count() or 1, 16))
         out["cpu_baseline"] = cpu_baseline(L, n_T, cfg["t_min"], cfg["t_max"], cfg["seed"], args.cpu_sweeps, threads)
