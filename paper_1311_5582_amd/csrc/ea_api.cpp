@@ -259,7 +259,7 @@ size_t job_footprint_bytes(int L, int n_T, int R, int layout, int64_t swap_entri
     return a(ladders * NW * N * 4) + a((size_t)R * N) + a(ladders * kMaxTemps * 4) + a((size_t)n_T * kThrCols * 4) +
            a((size_t)swap_entries * 4) + 3 * a(kMaxTemps * 4) + a(N * 4) + a(2 * 4) + a(ladders * kMaxTemps * 4) +
            a(ladders * 4) + a(sizeof(JobDesc)) + a(ladders * 2 * kMaxTemps * 8) + a(4) +
-           a((size_t)R * n_T * (4 + L) * 8);
+           a((size_t)R * n_T * (4 + L) * 8) + a((size_t)R * n_T * 5 * 4);
 }
 
 // Workgroups per ladder for a lone launch: split a ladder's slot groups over
@@ -447,6 +447,9 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
         return bail(rc);
     std::vector<int64_t> meas((size_t)n_realizations * n_T * (4 + L), 0);
     if ((rc = upload(s, meas, &s->d_meas))) return bail(rc);
+    // outputs of the observables kernel: energy and magnetization [R][2][n_T], overlap [R][n_T]
+    std::vector<int32_t> obs((size_t)n_realizations * n_T * 5, 0);
+    if ((rc = upload(s, obs, &s->d_obs))) return bail(rc);
     std::vector<uint32_t> units(ladders);
     for (int l = 0; l < ladders; ++l) units[l] = (uint32_t)l;   // job 0 of a lone launch
     if ((rc = upload(s, units, &s->d_units))) return bail(rc);
@@ -620,13 +623,11 @@ int ea_observables(ea_sim *s, int32_t *energy, int32_t *overlap)
     if (!s) return fail(EA_EINVAL, "ea_observables: NULL handle");
     EA_HIP(hipSetDevice(s->device));
     const size_t ne = (size_t)s->R * 2 * s->n_T, nq = (size_t)s->R * s->n_T;
-    int32_t *d = nullptr;
-    EA_HIP(hipMalloc(&d, (ne + nq) * sizeof(int32_t)));
+    int32_t *d = s->d_obs;
     hipError_t e = launch_observables(s->d_job, s->h, s->layout, d, d + ne, nullptr, s->stream);
     if (e == hipSuccess && energy) e = hipMemcpyAsync(energy, d, ne * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess && overlap) e = hipMemcpyAsync(overlap, d + ne, nq * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    (void)hipFree(d);
     if (e != hipSuccess) return fail(EA_EDEVICE, "observables failed: %s", hipGetErrorString(e));
     return check_split_error(s);
 }
@@ -635,13 +636,11 @@ int ea_magnetization(ea_sim *s, int32_t *magnetization)
 {
     if (!s || !magnetization) return fail(EA_EINVAL, "ea_magnetization: NULL argument");
     EA_HIP(hipSetDevice(s->device));
-    const size_t ne = (size_t)s->R * 2 * s->n_T;
-    int32_t *d = nullptr;
-    EA_HIP(hipMalloc(&d, ne * sizeof(int32_t)));
+    const size_t ne = (size_t)s->R * 2 * s->n_T, nq = (size_t)s->R * s->n_T;
+    int32_t *d = s->d_obs + ne + nq;
     hipError_t e = launch_observables(s->d_job, s->h, s->layout, nullptr, nullptr, d, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(magnetization, d, ne * sizeof(int32_t), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    (void)hipFree(d);
     if (e != hipSuccess) return fail(EA_EDEVICE, "magnetization failed: %s", hipGetErrorString(e));
     return check_split_error(s);
 }

@@ -68,6 +68,7 @@ struct ea_sim {
     size_t footprint = 0;             // device bytes owned by this job
     int split_parts = 1;              // workgroups per ladder in a lone launch (1, 2 or 4)
     int64_t *d_meas = nullptr;        // measurement sums: count, q^2 [R][n_T], q^4 [R][n_T][2], C [R][n_T][L]
+    int32_t *d_obs = nullptr;         // observables outputs: energy, overlap, magnetization
 };
 
 namespace ea {
