@@ -201,7 +201,8 @@ typedef struct ea_server_options {
     int max_active;           /* admitted jobs at once, <= 4095 (0 = 4095)                        */
     int autotune;             /* 1 = tune each job mix's workgroup size (cached by shape); default 0 */
     int keep_state;           /* keep each finished job's spins and permutation on the host       */
-    int rng;                  /* EA_RNG_* flip-draw stream of every job (planes: CAMSC only)      */
+    int rng;                  /* EA_RNG_* flip-draw stream of every job (planes: CAMSC only); the
+                                 jobs run without a field                                        */
     void *stream;             /* hipStream_t; NULL = a stream owned by the server                 */
 } ea_server_options;
 
@@ -223,13 +224,16 @@ int ea_server_stats(const ea_server *sv, size_t *hbm_used, size_t *hbm_budget, i
                     int64_t *plans_built, int64_t *launches_replayed);
 void ea_server_destroy(ea_server *sv);
 
-/* Device bytes ea_create allocates for such a job (host-only computation). */
+/* Device bytes ea_create allocates for such a job without a field (a field
+ * lengthens the swap tables; ea_sim_footprint reports a live job exactly).
+ * Host-only computation. */
 int ea_job_footprint(int L, const double *betas, int n_T, int n_realizations, int layout, size_t *bytes);
 /* Device bytes a live job holds. */
 int ea_sim_footprint(const ea_sim *sim, size_t *bytes);
 
 /* Measurement (Sec. 4.1, separate kernel): energy int32 [R][2][n_T] indexed by
- * temperature index, E = 2U - 3N; overlap int32 [R][n_T]:
+ * temperature index, E = 2U - 3N (the bond part: with a field the total is
+ * E - h M, see ea_magnetization); overlap int32 [R][n_T]:
  * q_k = sum_i s_i(copy 0 at temperature k) s_i(copy 1 at temperature k).
  * Either pointer may be NULL.  Synchronous. */
 int ea_observables(ea_sim *sim, int32_t *energy, int32_t *overlap);
