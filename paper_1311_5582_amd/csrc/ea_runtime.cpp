@@ -293,11 +293,22 @@ int ea_sweep_batch(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps, con
         s->h.n_sweeps = (int32_t)n_sweeps[0];
         s->h.swap_every = swap_every[0];
         EA_HIP(hipMemcpyAsync(&s->d_job->n_sweeps, &s->h.n_sweeps, 2 * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        bool done = false;
         if (s->split_parts > 1) {
-            EA_HIP(launch_sweep_split(s->d_job, s->h.ladders, s->split_parts, kernel_variant(s->layout, s->h.rng),
-                                      s->block_threads, s->lds,
-                                      s->d_counters + 1, st));
-        } else {
+            const hipError_t e = launch_sweep_split(s->d_job, s->h.ladders, s->split_parts,
+                                                    kernel_variant(s->layout, s->h.rng), s->block_threads, s->lds,
+                                                    s->d_counters + 1, st);
+            if (e == hipSuccess) {
+                done = true;
+            } else if (e == hipErrorCooperativeLaunchTooLarge) {
+                // the workgroups cannot all be resident now (other work holds
+                // CUs): nothing was launched, so run this call unsplit
+                (void)hipGetLastError();
+            } else {
+                return fail(EA_EDEVICE, "split sweep launch failed: %s", hipGetErrorString(e));
+            }
+        }
+        if (!done) {
             int grid = 0;
             const int kv = kernel_variant(s->layout, s->h.rng);
             if (int rc = device_grid(kv, s->block_threads, s->lds, s->h.ladders, &grid)) return rc;
