@@ -166,3 +166,48 @@ def test_server_rejects_job_larger_than_budget():
     with pytest.raises(B.EAError):
         srv.submit(8, inputs.couplings(8, 2, 1), inputs.geometric_betas(8, 0.5, 2.0), 1, 10, 1)
     srv.close()
+
+
+@pytest.mark.parametrize("rng,n_jobs", [("words", 12), ("planes", 6)])
+def test_server_serving_trace_shapes(oracle_lib, rng, n_jobs):
+    """The first jobs of the benchmark's serving trace at their real shapes
+    (L 6..20 with odd L, 32..512 realizations, 16..48 temperatures so some
+    ladders span two words), sweeps cut by 50x, through the server with a
+    quantum that divides none of them and the default HBM budget.  One
+    realization of every job, chosen by its seed, is re-run by the oracle
+    (one thread per job) and compared bit for bit."""
+    import threading
+    trace = inputs.serving_trace(n_jobs=n_jobs, rate_per_s=200.0)
+    for j in trace:
+        j["sweeps"] = max(1, j["sweeps"] // 50)
+    print(f"[runtime] serving shapes rng={rng} " +
+          " ".join(f"L{j['L']}R{j['R']}T{j['n_T']}x{j['sweeps']}" for j in trace), flush=True)
+    srv = B.Server(quantum_sweeps=37, keep_state=True, rng=rng)
+    recs, wall = serve.run_trace(trace, srv)
+    assert len(recs) == len(trace)
+    picks = []
+    for jid, rec in recs.items():
+        j = rec["job"]
+        assert rec["status"] == B.JOB_DONE, rec
+        r = j["seed"] % j["R"]
+        betas = inputs.geometric_betas(j["n_T"], j["t_min"], j["t_max"])
+        J = inputs.couplings(j["L"], j["R"], j["seed"])
+        spins, perm = srv.final_state(jid)
+        E, q = srv.result(jid)
+        orc = oracle_lib.OracleSim(j["L"], J[[r]], betas, j["seed"], rid=np.array([r]), rng=rng)
+        picks.append((jid, j, r, spins, perm, E, q, orc))
+    ths = [threading.Thread(target=p[-1].sweep, args=(p[1]["sweeps"], p[1]["swap_every"])) for p in picks]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    for jid, j, r, spins, perm, E, q, orc in picks:
+        assert orc.t == j["sweeps"]
+        assert np.array_equal(perm[r], orc.temp_of_slot[0]), f"job {jid} realization {r}: permutation differs"
+        assert np.array_equal(spins[r], orc.spins[0]), f"job {jid} realization {r}: spins differ"
+        Eo, qo = orc.observables()
+        assert np.array_equal(E[r], Eo[0]) and np.array_equal(q[r], qo[0]), f"job {jid}: observables differ"
+    st = srv.stats()
+    print(f"[runtime] serving shapes stats {st} wall {wall:.3f}s", flush=True)
+    assert st["hbm_used"] == 0
+    srv.close()
