@@ -177,15 +177,16 @@ struct Ctr {
 };
 
 // CAMSC: X[k] holds 2E+S of slot 4j+k in segment j.  Returns the flip bits of
-// the 4*NG slots, bit s = slot s of the word.
-template <int NG>
+// the 4*NG slots, bit s = slot s of the word.  With PRE the NG blocks were
+// drawn beforehand (pre[g] = the block of group g).
+template <int NG, bool PRE = false>
 __device__ __forceinline__ uint32_t camsc_decide(const uint32_t X[4], const uint32_t *rows, uint32_t site,
-                                                 const Ctr &c)
+                                                 const Ctr &c, const U4 *pre = nullptr)
 {
     uint32_t F = 0;
 #pragma unroll
     for (int g = NG - 1; g >= 0; --g) {
-        const U4 rr = philox10(site, c.t, c.r, c.c3 + (uint32_t)g, c.k0, c.k1);
+        const U4 rr = PRE ? pre[g] : philox10(site, c.t, c.r, c.c3 + (uint32_t)g, c.k0, c.k1);
         const uint32_t *row = rows + 4 * g * kThrCols;
         F = (F << 1) | (rr.w < row[3 * kThrCols + field4(X[3], 4 * g, c.w)] ? 1u : 0u);
         F = (F << 1) | (rr.z < row[2 * kThrCols + field4(X[2], 4 * g, c.w)] ? 1u : 0u);
@@ -314,9 +315,12 @@ __device__ __forceinline__ void dpp_add_planes(uint32_t (&P)[14])
     P[NQ] = c;   // planes above NQ are zero before this step
 }
 
-// P += s0 + 2 s1 + 4 s2 per bit position (a per-slot count of 0..7), NP planes.
+// P += s0 + 2 s1 + 4 s2 per bit position (a per-slot count of 0..7), np planes
+// (NPC > 0: exactly NPC planes, known at compile time).
+template <int NPC = 0>
 __device__ __forceinline__ void planes_add3(uint32_t (&P)[8], uint32_t s0, uint32_t s1, uint32_t s2, int np)
 {
+    if (NPC > 0) np = NPC;
     uint32_t carry = P[0] & s0;
     P[0] ^= s0;
     const uint32_t n1 = xor3(P[1], s1, carry);
@@ -417,12 +421,17 @@ __device__ __forceinline__ uint32_t certain_segments(uint32_t E, uint32_t Sb, co
 // With SPLIT (CAMSC, one word per site) this workgroup owns only the slot
 // groups [gb, gb + ngr_own) of the word; the other groups' bits in its LDS
 // copy are never read for its own decisions (slots do not interact).
-template <int LAYOUT, bool ACC = false, bool SPLIT = false, int RNG = 0>
+// NPC > 0 fixes the number of plane counters at compile time.
+//
+// With PRE (CAMSC words, SPLIT) the Philox blocks of the own groups were drawn
+// beforehand: pre[g] is the block of own group g (at most four).
+template <int LAYOUT, bool ACC = false, bool SPLIT = false, int RNG = 0, bool PRE = false, int NPC = 0>
 __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int N, int gw, int g0, int n_T,
                                             uint32_t t, uint32_t r, uint32_t c3base, uint32_t k0, uint32_t k1,
                                             uint32_t segw, const Field &fd, uint32_t (*P)[8] = nullptr, int np = 0,
-                                            int gb = 0, int ngr_own = 0)
+                                            int gb = 0, int ngr_own = 0, const U4 *pre = nullptr)
 {
+    static_assert(!PRE || (SPLIT && LAYOUT == 0 && RNG == 0), "pre-drawn blocks: split CAMSC words only");
     constexpr uint32_t M = 0x11111111u;
     const uint32_t j6 = sm.j6[nb.i];
     // all-ones mask for an antiferromagnetic incidence ("multiply the coupling
@@ -475,7 +484,7 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
                 // bit planes of 6 - E: (E0, ~(E1 ^ E0), ~(E2 ^ (E1 & E0)))
                 const uint32_t C1 = (flip & ~(E1 ^ E0)) | (~flip & E1);
                 const uint32_t C2 = (flip & ~(E2 ^ (E1 & E0))) | (~flip & E2);
-                planes_add3(*P, E0, C1, C2, np);
+                planes_add3<NPC>(*P, E0, C1, C2, np);
             }
         } else if (LAYOUT == 0) {
             // CAMSC: sum the six 1-bit bond words as three bit planes (full
@@ -516,26 +525,34 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
                 valid &= (ngr_own >= 8 ? 0xFFFFFFFFu : ((1u << (4 * ngr_own)) - 1u)) << (4 * gb);
             }
             uint32_t F;
-            switch (ngr) {
-                case 8: F = camsc_decide<8>(X, rows, nb.i, c); break;
-                case 7: F = camsc_decide<7>(X, rows, nb.i, c); break;
-                case 6: F = camsc_decide<6>(X, rows, nb.i, c); break;
-                case 5: F = camsc_decide<5>(X, rows, nb.i, c); break;
-                case 4: F = camsc_decide<4>(X, rows, nb.i, c); break;
-                case 3: F = camsc_decide<3>(X, rows, nb.i, c); break;
-                case 2: F = camsc_decide<2>(X, rows, nb.i, c); break;
-                default: F = camsc_decide<1>(X, rows, nb.i, c); break;
+            if (SPLIT) {   // a split ladder owns at most four groups
+                switch (ngr) {
+                    case 4: F = camsc_decide<4, PRE>(X, rows, nb.i, c, pre); break;
+                    case 3: F = camsc_decide<3, PRE>(X, rows, nb.i, c, pre); break;
+                    case 2: F = camsc_decide<2, PRE>(X, rows, nb.i, c, pre); break;
+                    default: F = camsc_decide<1, PRE>(X, rows, nb.i, c, pre); break;
+                }
+            } else {
+                switch (ngr) {
+                    case 8: F = camsc_decide<8>(X, rows, nb.i, c); break;
+                    case 7: F = camsc_decide<7>(X, rows, nb.i, c); break;
+                    case 6: F = camsc_decide<6>(X, rows, nb.i, c); break;
+                    case 5: F = camsc_decide<5>(X, rows, nb.i, c); break;
+                    case 4: F = camsc_decide<4>(X, rows, nb.i, c); break;
+                    case 3: F = camsc_decide<3>(X, rows, nb.i, c); break;
+                    case 2: F = camsc_decide<2>(X, rows, nb.i, c); break;
+                    default: F = camsc_decide<1>(X, rows, nb.i, c); break;
+                }
             }
             if (SPLIT) F <<= 4 * gb;
             const uint32_t flip = (F | always) & valid;
             sw[nb.i] = S ^ flip;
             if (ACC) {
-                const uint32_t a0 = e0 ^ flip, a1 = e1 ^ flip, a2 = e2 ^ flip;
-                const uint32_t a3 = e3 ^ flip, a4 = e4 ^ flip, a5 = e5 ^ flip;
-                const uint32_t s1 = xor3(a0, a1, a2), c1 = maj3(a0, a1, a2);
-                const uint32_t s2 = xor3(a3, a4, a5), c2 = maj3(a3, a4, a5);
-                const uint32_t b0 = s1 ^ s2, k = s1 & s2;
-                planes_add3(*P, b0, xor3(c1, c2, k), maj3(c1, c2, k), np);
+                // unsatisfied bonds after the update: E if kept, 6 - E if flipped
+                // (bit planes of 6 - E as in the plane-draw branch above)
+                const uint32_t C1 = (flip & ~(E1 ^ E0)) | (~flip & E1);
+                const uint32_t C2 = (flip & ~(E2 ^ (E1 & E0))) | (~flip & E2);
+                planes_add3<NPC>(*P, E0, C1, C2, np);
             }
         } else if (LAYOUT == 1) {
             // AMSC4: 4-bit segments throughout; 2E+S is formed for all slots at once.
@@ -633,6 +650,46 @@ __device__ void count_unsat_word_np(const uint32_t *words, const uint8_t *j6, in
     reduce_planes_add<NP, STR>(P, min(SPW, n_T - slot0), U + slot0);
 }
 
+// One ballot of the swap pass's acceptance words for up to 32 temperatures:
+// lane k of half hf (lane = 32 hf + k) evaluates pair k for the start position
+// j = 2i + hf, so the ballot holds col[2i] in its low and col[2i + 1] in its
+// high 32 bits; bit k of col[j] is set when pair k (k >= j) would swap the
+// configuration carried up from position j.  uj: energy at position j;
+// u_next: energy at position k + 1; the pair's draw, sign of dbeta, table
+// length and offset in drk, sg, len, off.  Without GUARD the table is in LDS
+// and is read unconditionally (an index past its end still falls inside the
+// workgroup's LDS, and the value is then unused).
+template <bool GUARD>
+__device__ __forceinline__ uint64_t swap_ballot(const uint32_t *tab, int uj, int u_next, uint32_t drk, int sg,
+                                                int len, int off, int k, int j, bool live)
+{
+    const int d = uj - u_next;
+    const int n = d < 0 ? -d : d;
+    const int lenm1 = len > 0 ? len - 1 : 0;
+    uint32_t thr;
+    if (GUARD)
+        thr = len > 0 ? tab[off + min(n, lenm1)] : 0u;
+    else
+        thr = tab[off + min(n, lenm1)];
+    const bool favourable = (sg == 0) || (d == 0) || ((sg > 0) == (d > 0));
+    return __ballot(live && k >= j && (favourable || (n < len && drk < thr)));
+}
+
+// The Philox blocks of the NG own groups (counter groups c3 .. c3 + NG - 1) of
+// sweep t at site j of colour class 0 (j < half).
+template <int NG>
+__device__ __forceinline__ void predraw_site(U4 (&st)[4], int j, int L, float invH, float invL, uint32_t t,
+                                             uint32_t r, uint32_t c3, uint32_t k0, uint32_t k1)
+{
+    // the site is the same at every swap point: keep the compiler from hoisting
+    // its partial rounds out of the sweep loop (they would stay live through
+    // every sweep)
+    asm volatile("" : "+v"(j));
+    const uint32_t site = checker_site(j, 0, L, invH, invL).i;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) st[g] = philox10(site, t, r, c3 + (uint32_t)g, k0, k1);
+}
+
 // Bit planes needed so that no lane's per-slot count overflows.
 __device__ __forceinline__ int planes_for(int N, int nthr)
 {
@@ -724,6 +781,9 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
 {
     constexpr int SPW = Layout<LAYOUT>::kSlotsPerWord;
     constexpr bool SPLIT = PARTS > 1;
+    // Split ladders with word draws run the swap pass in wave 0 alone while
+    // the other waves draw the next sweep's first colour class.
+    constexpr bool PREDRAW = SPLIT && RNG == 0;
     static_assert(!SPLIT || LAYOUT == 0, "split ladders are CAMSC only");
     static_assert(RNG == 0 || LAYOUT == 0, "plane draws are CAMSC only");
     extern __shared__ __align__(16) uint8_t smem_raw[];
@@ -816,6 +876,7 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
         const int gb = SPLIT ? part * ngr_own : 0;
         const int s_lo = SPLIT ? 4 * gb : 0;
         const int s_hi = SPLIT ? min(n_T, 4 * (gb + ngr_own)) : n_T;
+        bool c0_done = false;   // class 0 of sweep t already ran (after the last swap pass)
         while (remaining > 0) {
             int chunk = remaining;
             bool swap_now = false;
@@ -838,15 +899,25 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                 for (int s = 0; s < chunk; ++s) {
                     const uint32_t ts = t + (uint32_t)s;
                     if (even) {
-                        for (int j = tid; j < half; j += nthr)
-                            update_site<LAYOUT, false, SPLIT, RNG>(sm, checker_site(j, 0, L, invH, invL), N, gw, g0, n_T,
-                                                              ts, r, c3flip, k0, k1, segw, fd, nullptr, 0, gb, ngr_own);
-                        __syncthreads();
-                        if (fused_energy && swap_now && s == chunk - 1) {
+                        if (!(PREDRAW && s == 0 && c0_done)) {
                             for (int j = tid; j < half; j += nthr)
-                                update_site<LAYOUT, true, SPLIT, RNG>(sm, checker_site(j, 1, L, invH, invL), N, gw, g0,
-                                                                 n_T, ts, r, c3flip, k0, k1, segw, fd, P, np_b, gb,
-                                                                 ngr_own);
+                                update_site<LAYOUT, false, SPLIT, RNG>(sm, checker_site(j, 0, L, invH, invL), N, gw, g0,
+                                                                  n_T, ts, r, c3flip, k0, k1, segw, fd, nullptr, 0, gb,
+                                                                  ngr_own);
+                            __syncthreads();
+                        }
+                        if (fused_energy && swap_now && s == chunk - 1) {
+                            if (np_b == 4) {   // at most two sites per lane
+                                for (int j = tid; j < half; j += nthr)
+                                    update_site<LAYOUT, true, SPLIT, RNG, false, 4>(sm, checker_site(j, 1, L, invH, invL),
+                                                                                  N, gw, g0, n_T, ts, r, c3flip, k0, k1,
+                                                                                  segw, fd, P, np_b, gb, ngr_own);
+                            } else {
+                                for (int j = tid; j < half; j += nthr)
+                                    update_site<LAYOUT, true, SPLIT, RNG>(sm, checker_site(j, 1, L, invH, invL), N, gw,
+                                                                     g0, n_T, ts, r, c3flip, k0, k1, segw, fd, P, np_b,
+                                                                     gb, ngr_own);
+                            }
                         } else {
                             for (int j = tid; j < half; j += nthr)
                                 update_site<LAYOUT, false, SPLIT, RNG>(sm, checker_site(j, 1, L, invH, invL), N, gw, g0,
@@ -880,123 +951,261 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                     for (int idx = tid; idx < gw * N; idx += nthr) g_spin[(size_t)g0 * N + idx] = sm.spin[idx];
                 }
             }
+            c0_done = false;
             if (swap_now && n_T > 1) {
                 // ---- replica-exchange pass after sweep t + chunk - 1 ----
                 const uint32_t tswap = t + (uint32_t)chunk - 1u;
                 const int pairs = n_T - 1;
-                if (fd.on) {
-                    // with a field the slot value is W = (4U - m up) / g, so that
-                    // 2 (E_a - E_b) = g (W_a - W_b) (exact: g divides both terms)
-                    __syncthreads();
-                    if (tid < kMaxTemps) {
-                        sm.U[tid] = (4 * sm.U[tid] - jd.field_m * sm.up[tid]) / jd.field_g;
-                        sm.up[tid] = 0;
-                    }
-                }
-                if (SPLIT) {
-                    // Publish own slots' energies and collect the partners'.
-                    // Each word carries its sweep tag, so plain relaxed
-                    // atomics suffice: no fence, no cache write-back.
-                    __syncthreads();   // own energies are complete
+                if (PREDRAW) {
+                    // Wave 0 publishes this workgroup's slot values and draws the
+                    // next sweep's first colour class (as every wave does) before
+                    // it collects the partners' values; then all waves compute the
+                    // acceptance words and wave 0 walks the pass.
+                    __syncthreads();   // own slots' energies are complete
+                    const bool next = remaining > chunk;
                     const uint32_t tag = tswap + 1u;
                     uint64_t *xb = jd.xchg + ((size_t)ladder * 2 + ((tswap / (uint32_t)se) & 1u)) * kMaxTemps;
-                    if (tid >= s_lo && tid < s_hi)
-                        __hip_atomic_store(&xb[tid], ((uint64_t)tag << 32) | (uint32_t)sm.U[tid], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    if (tid < n_T && (tid < s_lo || tid >= s_hi)) {
-                        uint32_t spins = 0;
-                        uint64_t v;
-                        // bounded: after any timeout (error set) nobody waits long again
-                        while ((uint32_t)((v = __hip_atomic_load(&xb[tid], __ATOMIC_RELAXED,
-                                                                 __HIP_MEMORY_SCOPE_AGENT)) >> 32) != tag) {
-                            if (++spins > kSpinLimit ||
-                                ((spins & 255u) == 0u &&
-                                 __hip_atomic_load(jd.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
-                                atomicOr(jd.error, 1u);
-                                v = 0;
-                                break;
-                            }
-                            __builtin_amdgcn_s_sleep(1);
+                    int u = 0;
+                    if (wave == 0) {
+                        u = sm.U[lane];
+                        if (fd.on) u = (4 * u - jd.field_m * sm.up[lane]) / jd.field_g;   // W, as below
+                        if (lane >= s_lo && lane < s_hi)
+                            __hip_atomic_store(&xb[lane], ((uint64_t)tag << 32) | (uint32_t)u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    if (wave == nwaves - 1 && lane < pairs)
+                        sm.draw[lane] = philox10((uint32_t)lane, tswap, r, c3swap, k0, k1).x;
+                    // the next sweep's draws at this thread's first site of class 0
+                    // now, at its second one while wave 0 walks the pass
+                    U4 st[2][4];
+                    const uint32_t tn = tswap + 1u, c3n = c3flip + (uint32_t)gb;
+                    if (next && tid < half) {
+                        switch (ngr_own) {
+                            case 4: predraw_site<4>(st[0], tid, L, invH, invL, tn, r, c3n, k0, k1); break;
+                            case 3: predraw_site<3>(st[0], tid, L, invH, invL, tn, r, c3n, k0, k1); break;
+                            case 2: predraw_site<2>(st[0], tid, L, invH, invL, tn, r, c3n, k0, k1); break;
+                            default: predraw_site<1>(st[0], tid, L, invH, invL, tn, r, c3n, k0, k1); break;
                         }
-                        sm.U[tid] = (int32_t)(uint32_t)v;
                     }
-                }
-                // the last wave draws (wave 0 may still be waiting for partners)
-                if (wave == nwaves - 1 && lane < pairs)
-                    sm.draw[lane] = philox10((uint32_t)lane, tswap, r, c3swap, k0, k1).x;
-                __syncthreads();   // slot energies U and swap draws are in
-                // Bit k of col[j]: would pair k swap if the configuration that
-                // sat at position j before the pass had been carried up to k
-                // (j <= k)?  Waves take start positions j in turn, lanes the
-                // pairs k, so one ballot is col[j].  No data-dependent branch:
-                // a pair's table length is uniform and a non-empty table has
-                // entry 0.
-                {
-                    const int k = lane;
-                    const bool live = k < pairs;
-                    const int kk = live ? k : 0;
-                    const int u_next = sm.U[sm.sot[kk + 1]];
-                    const int sg = sm.ssgn[kk];
-                    const int len = sm.slen[kk];
-                    const int off = sm.soff[kk];
-                    const uint32_t dr = sm.draw[kk];
-                    const int u_here = sm.U[sm.sot[lane < n_T ? lane : 0]];   // lane j: energy at position j
-                    for (int j = wave; j < pairs; j += nwaves) {
-                        const int d = __builtin_amdgcn_readlane(u_here, j) - u_next;
-                        const int n = d < 0 ? -d : d;
-                        const uint32_t thr = len > 0 ? stab[off + min(n, len - 1)] : 0u;
-                        const bool favourable = (sg == 0) || (d == 0) || ((sg > 0) == (d > 0));
-                        const bool acc = live && k >= j && (favourable || (n < len && dr < thr));
-                        const uint64_t col = __ballot(acc);
-                        if (lane == 0) sm.mask[j] = col;
+                    if (wave == 0) {
+                        if (lane < n_T && (lane < s_lo || lane >= s_hi)) {
+                            uint32_t spins = 0;
+                            uint64_t v;
+                            while ((uint32_t)((v = __hip_atomic_load(&xb[lane], __ATOMIC_RELAXED,
+                                                                     __HIP_MEMORY_SCOPE_AGENT)) >> 32) != tag) {
+                                if (++spins > kSpinLimit ||
+                                    ((spins & 255u) == 0u &&
+                                     __hip_atomic_load(jd.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
+                                    atomicOr(jd.error, 1u);
+                                    v = 0;
+                                    break;
+                                }
+                                __builtin_amdgcn_s_sleep(1);
+                            }
+                            u = (int32_t)(uint32_t)v;
+                        }
+                        sm.U[lane] = u;   // every slot's value (n_T <= 32 here: one word per site)
                     }
-                }
-                __syncthreads();
-                if (wave == 0) {
-                    // The ascending pass, visiting only its rejections: from
-                    // restart point j the next rejected pair is the first k >= j
-                    // whose bit is clear in col[j], and after a rejection at k
-                    // the carried configuration restarts at k + 1.
-                    const uint64_t col = sm.mask[lane];
-                    sm.mask[lane] = 0ull;   // consumed; ready for the next swap point
-                    const uint64_t open = ~col & ((1ull << pairs) - 1ull) & (~0ull << lane);   // pairs <= 63
-                    const int nr = open ? (int)__builtin_ctzll(open) : 64;
-                    uint64_t rej = 0;
-                    int cj = 0;
-                    for (;;) {   // cj grows every turn: at most `pairs` turns
-                        const int r = __builtin_amdgcn_readlane(nr, cj);
-                        if (r >= pairs) break;
-                        rej |= 1ull << r;
-                        cj = r + 1;
+                    __syncthreads();   // slot values and the pairs' draws are in
+                    {
+                        // acceptance words: wave w takes the ballots i = w, w + nwaves, ... < 16
+                        const int k = lane & 31, hf = lane >> 5;
+                        const bool live = k < pairs;
+                        const int kk = live ? k : 0;
+                        const int u_next = sm.U[sm.sot[kk + 1]];
+                        const int sg = sm.ssgn[kk], len = sm.slen[kk], off = sm.soff[kk];
+                        const uint32_t drk = sm.draw[kk];
+                        for (int i = wave; i < 16; i += nwaves) {
+                            const int j = 2 * i + hf;
+                            const int uj = sm.U[sm.sot[j < n_T ? j : 0]];
+                            const uint64_t b =
+                                n_swap_lds ? swap_ballot<false>(sm.stab, uj, u_next, drk, sg, len, off, k, j, live)
+                                           : swap_ballot<true>(jd.swap_thr, uj, u_next, drk, sg, len, off, k, j, live);
+                            if (lane == 0) sm.mask[i] = b;
+                        }
                     }
-                    // lane k: pair k accepted -> the configuration from position k+1
-                    // comes down; rejected -> the carried one stays (it started at the
-                    // last restart point at or below k)
-                    int src;
-                    if (lane < pairs && !((rej >> lane) & 1ull)) {
-                        src = lane + 1;
-                    } else {
-                        const uint64_t starts = ((rej << 1) | 1ull) & (lane >= 63 ? ~0ull : ((2ull << lane) - 1ull));
-                        src = 63 - __clzll((long long)starts);
-                    }
-                    if (lane == pairs) src = cj;
-                    const int newslot = lane < n_T ? sm.sot[src] : 0;
-                    if (lane < pairs && src == lane + 1) sm.acc[lane] += 1u;
-                    if (lane < n_T) {
-                        sm.sot[lane] = newslot;
-                        sm.perm[newslot] = lane;
-                        // the slot now at temperature `lane` takes that temperature's row
-                        const uint4 *from = (const uint4 *)(sm.fthr + lane * kThrCols);
-                        uint4 *to = (uint4 *)(sm.thr + newslot * kThrCols);
+                    __syncthreads();   // acceptance words are in
+                    if (wave == 0) {
+                        // lane j: col[j]; the ascending pass over its rejections, as below
+                        const uint64_t w2 = sm.mask[lane >> 1];
+                        const uint32_t colv = lane < 32 ? ((lane & 1) ? (uint32_t)(w2 >> 32) : (uint32_t)w2) : 0u;
+                        const uint32_t open = lane < 32 ? ~colv & ((1u << pairs) - 1u) & (~0u << lane) : 0u;
+                        const int nr = open ? (int)__builtin_ctz(open) : 64;
+                        uint32_t rej = 0;
+                        int cj = 0;
+                        for (;;) {   // cj grows every turn: at most `pairs` turns
+                            const int rr = __builtin_amdgcn_readlane(nr, cj);
+                            if (rr >= pairs) break;
+                            rej |= 1u << rr;
+                            cj = rr + 1;
+                        }
+                        int src;
+                        if (lane < pairs && !((rej >> lane) & 1u)) {
+                            src = lane + 1;
+                        } else {
+                            const uint32_t starts = ((rej << 1) | 1u) & (lane >= 31 ? ~0u : ((2u << lane) - 1u));
+                            src = 31 - __clz((int)starts);
+                        }
+                        if (lane == pairs) src = cj;
+                        const int newslot = lane < n_T ? sm.sot[src] : 0;
+                        if (lane < pairs && src == lane + 1) sm.acc[lane] += 1u;
+                        if (lane < n_T) {
+                            sm.sot[lane] = newslot;
+                            sm.perm[newslot] = lane;
+                            const uint4 *from = (const uint4 *)(sm.fthr + lane * kThrCols);
+                            uint4 *to = (uint4 *)(sm.thr + newslot * kThrCols);
 #pragma unroll
-                        for (int c = 0; c < kThrCols / 4; ++c) to[c] = from[c];
+                            for (int c = 0; c < kThrCols / 4; ++c) to[c] = from[c];
+                        }
+                        sm.U[lane] = 0;   // consumed
+                        sm.up[lane] = 0;
                     }
-                    sm.U[lane] = 0;   // consumed
-                }
-                __syncthreads();
-                if (RNG == 1) {
-                    build_ptab(sm, NW, wave, nwaves, lane);
+                    if (next && tid + nthr < half) {
+                        const int j1 = tid + nthr;
+                        switch (ngr_own) {
+                            case 4: predraw_site<4>(st[1], j1, L, invH, invL, tn, r, c3n, k0, k1); break;
+                            case 3: predraw_site<3>(st[1], j1, L, invH, invL, tn, r, c3n, k0, k1); break;
+                            case 2: predraw_site<2>(st[1], j1, L, invH, invL, tn, r, c3n, k0, k1); break;
+                            default: predraw_site<1>(st[1], j1, L, invH, invL, tn, r, c3n, k0, k1); break;
+                        }
+                    }
+                    __syncthreads();   // temperature rows of the new permutation are in
+                    if (next) {
+                        // class 0 of the next sweep (so that the blocks need not
+                        // stay live across the loop)
+                        int j0 = tid;
+                        asm volatile("" : "+v"(j0));   // as in predraw_site
+                        if (j0 < half)
+                            update_site<LAYOUT, false, SPLIT, RNG, PREDRAW>(sm, checker_site(j0, 0, L, invH, invL), N,
+                                                                            1, 0, n_T, tn, r, c3flip, k0, k1, segw, fd,
+                                                                            nullptr, 0, gb, ngr_own, st[0]);
+                        if (j0 + nthr < half)
+                            update_site<LAYOUT, false, SPLIT, RNG, PREDRAW>(sm, checker_site(j0 + nthr, 0, L, invH,
+                                                                                             invL),
+                                                                            N, 1, 0, n_T, tn, r, c3flip, k0, k1, segw,
+                                                                            fd, nullptr, 0, gb, ngr_own, st[1]);
+                        for (int j = tid + 2 * nthr; j < half; j += nthr)
+                            update_site<LAYOUT, false, SPLIT, RNG>(sm, checker_site(j, 0, L, invH, invL), N, 1, 0, n_T,
+                                                                  tn, r, c3flip, k0, k1, segw, fd, nullptr, 0, gb,
+                                                                  ngr_own);
+                        __syncthreads();
+                        c0_done = true;
+                    }
+                } else {
+                    if (fd.on) {
+                        // with a field the slot value is W = (4U - m up) / g, so that
+                        // 2 (E_a - E_b) = g (W_a - W_b) (exact: g divides both terms)
+                        __syncthreads();
+                        if (tid < kMaxTemps) {
+                            sm.U[tid] = (4 * sm.U[tid] - jd.field_m * sm.up[tid]) / jd.field_g;
+                            sm.up[tid] = 0;
+                        }
+                    }
+                    if (SPLIT) {
+                        // Publish own slots' energies and collect the partners'.
+                        // Each word carries its sweep tag, so plain relaxed
+                        // atomics suffice: no fence, no cache write-back.
+                        __syncthreads();   // own energies are complete
+                        const uint32_t tag = tswap + 1u;
+                        uint64_t *xb = jd.xchg + ((size_t)ladder * 2 + ((tswap / (uint32_t)se) & 1u)) * kMaxTemps;
+                        if (tid >= s_lo && tid < s_hi)
+                            __hip_atomic_store(&xb[tid], ((uint64_t)tag << 32) | (uint32_t)sm.U[tid], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        if (tid < n_T && (tid < s_lo || tid >= s_hi)) {
+                            uint32_t spins = 0;
+                            uint64_t v;
+                            // bounded: after any timeout (error set) nobody waits long again
+                            while ((uint32_t)((v = __hip_atomic_load(&xb[tid], __ATOMIC_RELAXED,
+                                                                     __HIP_MEMORY_SCOPE_AGENT)) >> 32) != tag) {
+                                if (++spins > kSpinLimit ||
+                                    ((spins & 255u) == 0u &&
+                                     __hip_atomic_load(jd.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
+                                    atomicOr(jd.error, 1u);
+                                    v = 0;
+                                    break;
+                                }
+                                __builtin_amdgcn_s_sleep(1);
+                            }
+                            sm.U[tid] = (int32_t)(uint32_t)v;
+                        }
+                    }
+                    // the last wave draws (wave 0 may still be waiting for partners)
+                    if (wave == nwaves - 1 && lane < pairs)
+                        sm.draw[lane] = philox10((uint32_t)lane, tswap, r, c3swap, k0, k1).x;
+                    __syncthreads();   // slot energies U and swap draws are in
+                    // Bit k of col[j]: would pair k swap if the configuration that
+                    // sat at position j before the pass had been carried up to k
+                    // (j <= k)?  Waves take start positions j in turn, lanes the
+                    // pairs k, so one ballot is col[j].  No data-dependent branch:
+                    // a pair's table length is uniform and a non-empty table has
+                    // entry 0.
+                    {
+                        const int k = lane;
+                        const bool live = k < pairs;
+                        const int kk = live ? k : 0;
+                        const int u_next = sm.U[sm.sot[kk + 1]];
+                        const int sg = sm.ssgn[kk];
+                        const int len = sm.slen[kk];
+                        const int off = sm.soff[kk];
+                        const uint32_t dr = sm.draw[kk];
+                        const int u_here = sm.U[sm.sot[lane < n_T ? lane : 0]];   // lane j: energy at position j
+                        for (int j = wave; j < pairs; j += nwaves) {
+                            const int d = __builtin_amdgcn_readlane(u_here, j) - u_next;
+                            const int n = d < 0 ? -d : d;
+                            const uint32_t thr = len > 0 ? stab[off + min(n, len - 1)] : 0u;
+                            const bool favourable = (sg == 0) || (d == 0) || ((sg > 0) == (d > 0));
+                            const bool acc = live && k >= j && (favourable || (n < len && dr < thr));
+                            const uint64_t col = __ballot(acc);
+                            if (lane == 0) sm.mask[j] = col;
+                        }
+                    }
                     __syncthreads();
+                    if (wave == 0) {
+                        // The ascending pass, visiting only its rejections: from
+                        // restart point j the next rejected pair is the first k >= j
+                        // whose bit is clear in col[j], and after a rejection at k
+                        // the carried configuration restarts at k + 1.
+                        const uint64_t col = sm.mask[lane];
+                        sm.mask[lane] = 0ull;   // consumed; ready for the next swap point
+                        const uint64_t open = ~col & ((1ull << pairs) - 1ull) & (~0ull << lane);   // pairs <= 63
+                        const int nr = open ? (int)__builtin_ctzll(open) : 64;
+                        uint64_t rej = 0;
+                        int cj = 0;
+                        for (;;) {   // cj grows every turn: at most `pairs` turns
+                            const int r = __builtin_amdgcn_readlane(nr, cj);
+                            if (r >= pairs) break;
+                            rej |= 1ull << r;
+                            cj = r + 1;
+                        }
+                        // lane k: pair k accepted -> the configuration from position k+1
+                        // comes down; rejected -> the carried one stays (it started at the
+                        // last restart point at or below k)
+                        int src;
+                        if (lane < pairs && !((rej >> lane) & 1ull)) {
+                            src = lane + 1;
+                        } else {
+                            const uint64_t starts = ((rej << 1) | 1ull) & (lane >= 63 ? ~0ull : ((2ull << lane) - 1ull));
+                            src = 63 - __clzll((long long)starts);
+                        }
+                        if (lane == pairs) src = cj;
+                        const int newslot = lane < n_T ? sm.sot[src] : 0;
+                        if (lane < pairs && src == lane + 1) sm.acc[lane] += 1u;
+                        if (lane < n_T) {
+                            sm.sot[lane] = newslot;
+                            sm.perm[newslot] = lane;
+                            // the slot now at temperature `lane` takes that temperature's row
+                            const uint4 *from = (const uint4 *)(sm.fthr + lane * kThrCols);
+                            uint4 *to = (uint4 *)(sm.thr + newslot * kThrCols);
+    #pragma unroll
+                            for (int c = 0; c < kThrCols / 4; ++c) to[c] = from[c];
+                        }
+                        sm.U[lane] = 0;   // consumed
+                    }
+                    __syncthreads();
+                    if (RNG == 1) {
+                        build_ptab(sm, NW, wave, nwaves, lane);
+                        __syncthreads();
+                    }
                 }
             } else if (swap_now) {
                 __syncthreads();
