@@ -291,6 +291,14 @@ __device__ __forceinline__ void build_ptab(const Smem &sm, int NW, int wave, int
     }
 }
 
+// Exchange the bits of a selected by m << sh with the bits of b selected by m.
+__device__ __forceinline__ void swap_bits(uint32_t &a, uint32_t &b, int sh, uint32_t m)
+{
+    const uint32_t t = ((a >> sh) ^ b) & m;
+    b ^= t;
+    a ^= t << sh;
+}
+
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ uint32_t dpp_src(uint32_t v)
 {
@@ -379,12 +387,65 @@ __device__ __forceinline__ void reduce_planes8_add(const uint32_t (&P8)[8], int 
     }
 }
 
-// Exchange the bits of a selected by m << sh with the bits of b selected by m.
-__device__ __forceinline__ void swap_bits(uint32_t &a, uint32_t &b, int sh, uint32_t m)
+// Wave-sum of four plane counters whose per-lane counts stay below 16, for the
+// nslots <= 16 slots first .. first + nslots - 1 (first a multiple of 4),
+// added into U[first + b].  The planes become one byte per slot (a bit
+// transpose inside each nibble), DPP sums inside each row of 16 lanes keep a
+// byte below 256, and the four row sums are added in 16-bit fields.
+__device__ __forceinline__ void reduce_planes4_bytes_add(const uint32_t (&P8)[8], int nslots, int *U, int first)
 {
-    const uint32_t t = ((a >> sh) ^ b) & m;
-    b ^= t;
-    a ^= t << sh;
+    uint32_t X[4] = {P8[0], P8[1], P8[2], P8[3]};
+    // nibble m of X[q] <- the count of slot 4m + q
+    swap_bits(X[0], X[2], 2, 0x33333333u);
+    swap_bits(X[1], X[3], 2, 0x33333333u);
+    swap_bits(X[0], X[1], 1, 0x55555555u);
+    swap_bits(X[2], X[3], 1, 0x55555555u);
+    // byte m of Z[q] <- the count of slot first + 4m + q
+    uint32_t Z[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t y = (X[q] >> first) & 0xFFFFu;
+        const uint32_t t = (y | (y << 8)) & 0x00FF00FFu;
+        Z[q] = (t | (t << 4)) & 0x0F0F0F0Fu;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Z[q] += dpp_src<0x111, 0xF>(Z[q]);   // row_shr:1
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Z[q] += dpp_src<0x112, 0xF>(Z[q]);   // row_shr:2
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Z[q] += dpp_src<0x114, 0xF>(Z[q]);   // row_shr:4
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Z[q] += dpp_src<0x118, 0xF>(Z[q]);   // row_shr:8
+    // W[2q + h] fields f = 0, 1 <- byte 2f + h of Z[q]: slot first + 4(2f + h) + q
+    uint32_t W[8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        W[2 * q] = Z[q] & 0x00FF00FFu;
+        W[2 * q + 1] = (Z[q] >> 8) & 0x00FF00FFu;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) W[k] += dpp_src<0x142, 0xA>(W[k]);   // row_bcast:15 into rows 1, 3
+#pragma unroll
+    for (int k = 0; k < 8; ++k) W[k] += dpp_src<0x143, 0xC>(W[k]);   // row_bcast:31 into rows 2, 3
+    // lane b: slot first + b = first + 4m + q with m = 2f + h (selects on
+    // values, not on array elements, so that nothing goes to scratch memory)
+    const int b = threadIdx.x & 15;
+    const int q = b & 3, h = (b >> 2) & 1, f = b >> 3;
+    const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)W[0], 63);
+    const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane((int)W[1], 63);
+    const uint32_t w2 = (uint32_t)__builtin_amdgcn_readlane((int)W[2], 63);
+    const uint32_t w3 = (uint32_t)__builtin_amdgcn_readlane((int)W[3], 63);
+    const uint32_t w4 = (uint32_t)__builtin_amdgcn_readlane((int)W[4], 63);
+    const uint32_t w5 = (uint32_t)__builtin_amdgcn_readlane((int)W[5], 63);
+    const uint32_t w6 = (uint32_t)__builtin_amdgcn_readlane((int)W[6], 63);
+    const uint32_t w7 = (uint32_t)__builtin_amdgcn_readlane((int)W[7], 63);
+    const uint32_t a0 = h ? w1 : w0, a1 = h ? w3 : w2;
+    const uint32_t a2 = h ? w5 : w4, a3 = h ? w7 : w6;
+    const uint32_t c0 = (q & 1) ? a1 : a0, c1 = (q & 1) ? a3 : a2;
+    const uint32_t v = (q & 2) ? c1 : c0;
+    const int cnt = (int)((v >> (16 * f)) & 0xFFFFu);
+    const int lane = threadIdx.x & 63;
+    if (lane < nslots && cnt) atomicAdd(&U[first + lane], cnt);
 }
 
 // Certain flips (cost <= 0).  Without a field they are the slots with E >= 3;
@@ -937,7 +998,10 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                 }
                 if (swap_now) {
                     if (fused_energy) {
-                        reduce_planes8_add<1>(P[0], np_b, s_hi - s_lo, sm.U, s_lo);
+                        if (np_b == 4 && s_hi - s_lo <= 16)
+                            reduce_planes4_bytes_add(P[0], s_hi - s_lo, sm.U, s_lo);
+                        else
+                            reduce_planes8_add<1>(P[0], np_b, s_hi - s_lo, sm.U, s_lo);
                     } else {
                         for (int w = 0; w < gw; ++w) {
                             count_unsat_word<LAYOUT>(sm.spin + (size_t)w * N, sm.j6, N, L, invL, (g0 + w) * SPW, n_T,
@@ -1031,9 +1095,15 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                         const uint32_t colv = lane < 32 ? ((lane & 1) ? (uint32_t)(w2 >> 32) : (uint32_t)w2) : 0u;
                         const uint32_t open = lane < 32 ? ~colv & ((1u << pairs) - 1u) & (~0u << lane) : 0u;
                         const int nr = open ? (int)__builtin_ctz(open) : 64;
+                        // pairs rejected right at their restart point: a run of them is
+                        // taken in one step (common among the low temperatures)
+                        const uint32_t imm = (uint32_t)__ballot(lane < pairs && !((colv >> lane) & 1u));
                         uint32_t rej = 0;
                         int cj = 0;
                         for (;;) {   // cj grows every turn: at most `pairs` turns
+                            const int run = __builtin_ctz(~(imm >> cj));   // imm has no bit at or above pairs
+                            rej |= ((1u << run) - 1u) << cj;
+                            cj += run;
                             const int rr = __builtin_amdgcn_readlane(nr, cj);
                             if (rr >= pairs) break;
                             rej |= 1u << rr;
