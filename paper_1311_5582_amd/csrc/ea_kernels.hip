@@ -1239,9 +1239,14 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                         sm.mask[lane] = 0ull;   // consumed; ready for the next swap point
                         const uint64_t open = ~col & ((1ull << pairs) - 1ull) & (~0ull << lane);   // pairs <= 63
                         const int nr = open ? (int)__builtin_ctzll(open) : 64;
+                        // a run of pairs rejected right at their restart point is one step
+                        const uint64_t imm = __ballot(lane < pairs && !((col >> lane) & 1ull));
                         uint64_t rej = 0;
                         int cj = 0;
                         for (;;) {   // cj grows every turn: at most `pairs` turns
+                            const int run = __builtin_ctzll(~(imm >> cj));   // imm has no bit at or above pairs
+                            rej |= ((1ull << run) - 1ull) << cj;
+                            cj += run;
                             const int r = __builtin_amdgcn_readlane(nr, cj);
                             if (r >= pairs) break;
                             rej |= 1ull << r;
