@@ -968,7 +968,7 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                             __syncthreads();
                         }
                         if (fused_energy && swap_now && s == chunk - 1) {
-                            if (np_b == 4) {   // at most two sites per lane
+                            if (RNG == 0 && np_b == 4) {   // at most two sites per lane
                                 for (int j = tid; j < half; j += nthr)
                                     update_site<LAYOUT, true, SPLIT, RNG, false, 4>(sm, checker_site(j, 1, L, invH, invL),
                                                                                   N, gw, g0, n_T, ts, r, c3flip, k0, k1,
