@@ -223,6 +223,24 @@ def test_split_ladders_equal_unsplit(oracle_lib, L, R, n_T, swap_every):
     assert np.array_equal(a.swap_acceptance(), b.swap_acceptance())
 
 
+@pytest.mark.parametrize("L,R,n_T,swap_every,bt,rids", [
+    (8, 64, 32, 1, 64, [0, 37, 63]),   # 2 parts x 4 own groups, four class-0 sites per thread (two drawn ahead)
+    (16, 1, 32, 1, 256, None),         # 4 parts, eight sites per thread: wider plane counters, generic reduction
+    (12, 2, 24, 1, 512, None),         # 2 parts x 3 own groups, 864 sites per class: a ragged second site
+    (10, 1, 16, 2, 128, None),         # 4 parts x 1 own group, PT every second sweep
+])
+def test_split_launch_shapes(oracle_lib, L, R, n_T, swap_every, bt, rids):
+    """Split ladders at workgroup sizes that give a thread more or fewer than
+    the two class-0 sites whose next-sweep draws the swap step makes ahead of
+    time, and every number of own slot groups: the oracle's chain, with calls
+    that end right after a swap point and mid-interval."""
+    sim, *_ = run_pair(oracle_lib, L, R, n_T, 7000 + 7 * L + n_T, 21, swap_every, split="always", block_threads=bt,
+                       rids=rids, splits=[1, 9, 11])
+    info = sim.info()
+    print(f"[parity] split launch {info}", flush=True)
+    assert info["split_parts"] > 1 and info["block_threads"] == bt
+
+
 @pytest.mark.parametrize("L,R,n_T,swap_every,split,bt,wr", [
     (8, 1, 16, 1, True, 0, 0),        # the single small job
     (6, 3, 13, 1, False, 0, 0),       # ragged: one partial half
