@@ -143,8 +143,8 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T,
  * ea_set_state. */
 int ea_sweep(ea_sim *sim, int64_t n_sweeps, int swap_every);
 
-/* One launch over the ladders of several jobs of uneven size (north-star
- * batching; Sec. 3.3 maps realizations to workgroups).  n_sweeps[j] and
+/* One launch over the ladders of several jobs of uneven size (Sec. 3.3 maps
+ * realizations to workgroups; here the ladders of all jobs share one queue).  n_sweeps[j] and
  * swap_every[j] apply to sims[j] exactly as in ea_sweep; each job's results
  * equal those of running it alone.  All sims must live on the current device
  * and share one layout; the launch uses sims[0]'s stream. */
