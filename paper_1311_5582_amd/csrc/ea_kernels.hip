@@ -985,7 +985,10 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                                                                   n_T, ts, r, c3flip, k0, k1, segw, fd, nullptr, 0, gb,
                                                                   ngr_own);
                         }
-                        __syncthreads();
+                        // after the summing class a wave goes straight on to reduce its
+                        // own counters (registers and atomics on U only); the barrier
+                        // that follows the reduction covers the spins as well
+                        if (!(fused_energy && swap_now && s == chunk - 1)) __syncthreads();
                     } else {
                         for (int c = 0; c < jd.n_classes; ++c) {
                             const int end = jd.class_off[c + 1];
