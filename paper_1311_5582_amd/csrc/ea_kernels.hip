@@ -769,6 +769,114 @@ __device__ __forceinline__ int planes_for_class(int n_sites, int nthr)
     return np;
 }
 
+// Two sites of one colour class at once (CAMSC, one word per site, word draws,
+// no field): the same steps as update_site, with both sites' loads first and
+// both stores last so that their Philox chains share one straight-line block.
+// Legal because two sites of one class are never neighbours: neither reads the
+// other's spin.  NG = the slot groups decided (the own groups when SPLIT).
+template <bool ACC, bool SPLIT, int NG, int NPC>
+__device__ __forceinline__ void update_pair_camsc(const Smem &sm, const Nbrs &na, const Nbrs &nb, int n_T,
+                                                  uint32_t t, uint32_t r, uint32_t c3base, uint32_t k0, uint32_t k1,
+                                                  uint32_t segw, uint32_t (*P)[8], int np, int gb, int ngr_own)
+{
+    const Nbrs nn[2] = {na, nb};
+    uint32_t *sw = sm.spin;
+    uint32_t S[2], V[2][6], J[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        J[q] = sm.j6[nn[q].i];
+        S[q] = sw[nn[q].i];
+        V[q][0] = sw[nn[q].xp];
+        V[q][1] = sw[nn[q].xm];
+        V[q][2] = sw[nn[q].yp];
+        V[q][3] = sw[nn[q].ym];
+        V[q][4] = sw[nn[q].zp];
+        V[q][5] = sw[nn[q].zm];
+    }
+    uint32_t valid = n_T >= 32 ? 0xFFFFFFFFu : ((1u << n_T) - 1u);
+    const uint32_t *rows = sm.thr;
+    Ctr c{t, r, c3base, k0, k1, segw};
+    if (SPLIT) {
+        rows += 4 * gb * kThrCols;
+        c.c3 += (uint32_t)gb;
+        valid &= (ngr_own >= 8 ? 0xFFFFFFFFu : ((1u << (4 * ngr_own)) - 1u)) << (4 * gb);
+    }
+    uint32_t out[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        uint32_t e[6];
+#pragma unroll
+        for (int d = 0; d < 6; ++d) e[d] = S[q] ^ V[q][d] ^ (0u - ((J[q] >> d) & 1u));
+        const uint32_t s1 = xor3(e[0], e[1], e[2]), c1 = maj3(e[0], e[1], e[2]);
+        const uint32_t s2 = xor3(e[3], e[4], e[5]), c2 = maj3(e[3], e[4], e[5]);
+        const uint32_t E0 = s1 ^ s2, kk = s1 & s2;
+        const uint32_t E1 = xor3(c1, c2, kk), E2 = maj3(c1, c2, kk);
+        uint32_t X[4] = {S[q], E0, E1, E2};
+        swap_bits(X[0], X[2], 2, 0x33333333u);
+        swap_bits(X[1], X[3], 2, 0x33333333u);
+        swap_bits(X[0], X[1], 1, 0x55555555u);
+        swap_bits(X[2], X[3], 1, 0x55555555u);
+        const uint32_t always = E2 | (E1 & E0);   // E >= 3
+        if (SPLIT) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) X[k] >>= 4 * gb;
+        }
+        uint32_t F = camsc_decide<NG>(X, rows, (uint32_t)nn[q].i, c);
+        if (SPLIT) F <<= 4 * gb;
+        const uint32_t flip = (F | always) & valid;
+        out[q] = S[q] ^ flip;
+        if (ACC) {
+            const uint32_t C1 = (flip & ~(E1 ^ E0)) | (~flip & E1);
+            const uint32_t C2 = (flip & ~(E2 ^ (E1 & E0))) | (~flip & E2);
+            planes_add3<NPC>(*P, E0, C1, C2, np);
+        }
+    }
+    sw[nn[0].i] = out[0];
+    sw[nn[1].i] = out[1];
+}
+
+// One colour class of an even lattice: a split ladder with word draws and no
+// field takes the sites of a thread two at a time, everything else one at a
+// time (pairing measured slower where a workgroup holds the whole ladder).
+template <int LAYOUT, bool ACC, bool SPLIT, int RNG, int NPC, int NG>
+__device__ __forceinline__ void class_pass_ng(const Smem &sm, int c, int tid, int nthr, int half, int L, float invH,
+                                              float invL, int N, int gw, int g0, int n_T, uint32_t t, uint32_t r,
+                                              uint32_t c3base, uint32_t k0, uint32_t k1, uint32_t segw,
+                                              const Field &fd, uint32_t (*P)[8], int np, int gb, int ngr_own)
+{
+    int j = tid;
+    for (; j + nthr < half; j += 2 * nthr)
+        update_pair_camsc<ACC, SPLIT, NG, NPC>(sm, checker_site(j, c, L, invH, invL),
+                                               checker_site(j + nthr, c, L, invH, invL), n_T, t, r, c3base, k0, k1,
+                                               segw, P, np, gb, ngr_own);
+    if (j < half)
+        update_site<LAYOUT, ACC, SPLIT, RNG, false, NPC>(sm, checker_site(j, c, L, invH, invL), N, gw, g0, n_T, t, r,
+                                                        c3base, k0, k1, segw, fd, P, np, gb, ngr_own);
+}
+
+template <int LAYOUT, bool ACC, bool SPLIT, int RNG, int NPC = 0>
+__device__ __forceinline__ void class_pass(const Smem &sm, int c, int tid, int nthr, int half, int L, float invH,
+                                           float invL, int N, int NW, int gw, int g0, int n_T, uint32_t t, uint32_t r,
+                                           uint32_t c3base, uint32_t k0, uint32_t k1, uint32_t segw, const Field &fd,
+                                           uint32_t (*P)[8], int np, int gb, int ngr_own)
+{
+    if (SPLIT && LAYOUT == 0 && RNG == 0 && NW == 1 && !fd.on) {
+        const int ng = ngr_own;
+#define EA_PASS(G) class_pass_ng<LAYOUT, ACC, SPLIT, RNG, NPC, G>(sm, c, tid, nthr, half, L, invH, invL, N, gw, g0, \
+                       n_T, t, r, c3base, k0, k1, segw, fd, P, np, gb, ngr_own)
+        switch (ng) {
+            case 1: EA_PASS(1); return;
+            case 2: EA_PASS(2); return;
+            case 3: EA_PASS(3); return;
+            default: EA_PASS(4); return;   // a split ladder owns at most four groups
+        }
+#undef EA_PASS
+    }
+    for (int j = tid; j < half; j += nthr)
+        update_site<LAYOUT, ACC, SPLIT, RNG, false, NPC>(sm, checker_site(j, c, L, invH, invL), N, gw, g0, n_T, t, r,
+                                                        c3base, k0, k1, segw, fd, P, np, gb, ngr_own);
+}
+
 template <int LAYOUT>
 __device__ __forceinline__ void count_unsat_word(const uint32_t *words, const uint8_t *j6, int N, int L, float invL,
                                                  int slot0, int n_T, int np, int *U)
@@ -961,27 +1069,22 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                     const uint32_t ts = t + (uint32_t)s;
                     if (even) {
                         if (!(PREDRAW && s == 0 && c0_done)) {
-                            for (int j = tid; j < half; j += nthr)
-                                update_site<LAYOUT, false, SPLIT, RNG>(sm, checker_site(j, 0, L, invH, invL), N, gw, g0,
+                            class_pass<LAYOUT, false, SPLIT, RNG>(sm, 0, tid, nthr, half, L, invH, invL, N, NW, gw, g0,
                                                                   n_T, ts, r, c3flip, k0, k1, segw, fd, nullptr, 0, gb,
                                                                   ngr_own);
                             __syncthreads();
                         }
                         if (fused_energy && swap_now && s == chunk - 1) {
-                            if (RNG == 0 && np_b == 4) {   // at most two sites per lane
-                                for (int j = tid; j < half; j += nthr)
-                                    update_site<LAYOUT, true, SPLIT, RNG, false, 4>(sm, checker_site(j, 1, L, invH, invL),
-                                                                                  N, gw, g0, n_T, ts, r, c3flip, k0, k1,
-                                                                                  segw, fd, P, np_b, gb, ngr_own);
-                            } else {
-                                for (int j = tid; j < half; j += nthr)
-                                    update_site<LAYOUT, true, SPLIT, RNG>(sm, checker_site(j, 1, L, invH, invL), N, gw,
+                            if (RNG == 0 && np_b == 4)   // at most two sites per lane
+                                class_pass<LAYOUT, true, SPLIT, RNG, 4>(sm, 1, tid, nthr, half, L, invH, invL, N, NW,
+                                                                        gw, g0, n_T, ts, r, c3flip, k0, k1, segw, fd, P,
+                                                                        np_b, gb, ngr_own);
+                            else
+                                class_pass<LAYOUT, true, SPLIT, RNG>(sm, 1, tid, nthr, half, L, invH, invL, N, NW, gw,
                                                                      g0, n_T, ts, r, c3flip, k0, k1, segw, fd, P, np_b,
                                                                      gb, ngr_own);
-                            }
                         } else {
-                            for (int j = tid; j < half; j += nthr)
-                                update_site<LAYOUT, false, SPLIT, RNG>(sm, checker_site(j, 1, L, invH, invL), N, gw, g0,
+                            class_pass<LAYOUT, false, SPLIT, RNG>(sm, 1, tid, nthr, half, L, invH, invL, N, NW, gw, g0,
                                                                   n_T, ts, r, c3flip, k0, k1, segw, fd, nullptr, 0, gb,
                                                                   ngr_own);
                         }
