@@ -773,11 +773,13 @@ __device__ __forceinline__ int planes_for_class(int n_sites, int nthr)
 // no field): the same steps as update_site, with both sites' loads first and
 // both stores last so that their Philox chains share one straight-line block.
 // Legal because two sites of one class are never neighbours: neither reads the
-// other's spin.  NG = the slot groups decided (the own groups when SPLIT).
-template <bool ACC, bool SPLIT, int NG, int NPC>
+// other's spin.  NG = the slot groups decided (the own groups when SPLIT);
+// with PRE the blocks were drawn beforehand (prea, preb as in update_site).
+template <bool ACC, bool SPLIT, int NG, int NPC, bool PRE = false>
 __device__ __forceinline__ void update_pair_camsc(const Smem &sm, const Nbrs &na, const Nbrs &nb, int n_T,
                                                   uint32_t t, uint32_t r, uint32_t c3base, uint32_t k0, uint32_t k1,
-                                                  uint32_t segw, uint32_t (*P)[8], int np, int gb, int ngr_own)
+                                                  uint32_t segw, uint32_t (*P)[8], int np, int gb, int ngr_own,
+                                                  const U4 *prea = nullptr, const U4 *preb = nullptr)
 {
     const Nbrs nn[2] = {na, nb};
     uint32_t *sw = sm.spin;
@@ -821,7 +823,7 @@ __device__ __forceinline__ void update_pair_camsc(const Smem &sm, const Nbrs &na
 #pragma unroll
             for (int k = 0; k < 4; ++k) X[k] >>= 4 * gb;
         }
-        uint32_t F = camsc_decide<NG>(X, rows, (uint32_t)nn[q].i, c);
+        uint32_t F = camsc_decide<NG, PRE>(X, rows, (uint32_t)nn[q].i, c, q == 0 ? prea : preb);
         if (SPLIT) F <<= 4 * gb;
         const uint32_t flip = (F | always) & valid;
         out[q] = S[q] ^ flip;
@@ -1251,15 +1253,31 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                         // stay live across the loop)
                         int j0 = tid;
                         asm volatile("" : "+v"(j0));   // as in predraw_site
-                        if (j0 < half)
-                            update_site<LAYOUT, false, SPLIT, RNG, PREDRAW>(sm, checker_site(j0, 0, L, invH, invL), N,
-                                                                            1, 0, n_T, tn, r, c3flip, k0, k1, segw, fd,
-                                                                            nullptr, 0, gb, ngr_own, st[0]);
-                        if (j0 + nthr < half)
-                            update_site<LAYOUT, false, SPLIT, RNG, PREDRAW>(sm, checker_site(j0 + nthr, 0, L, invH,
-                                                                                             invL),
-                                                                            N, 1, 0, n_T, tn, r, c3flip, k0, k1, segw,
-                                                                            fd, nullptr, 0, gb, ngr_own, st[1]);
+                        if (j0 + nthr < half && !fd.on) {   // both sites in one block, as in class_pass
+                            const Nbrs na = checker_site(j0, 0, L, invH, invL);
+                            const Nbrs nb = checker_site(j0 + nthr, 0, L, invH, invL);
+#define EA_PAIR(G) update_pair_camsc<false, SPLIT, G, 0, PREDRAW>(sm, na, nb, n_T, tn, r, c3flip, k0, k1, segw, \
+                                                                 nullptr, 0, gb, ngr_own, st[0], st[1])
+                            switch (ngr_own) {
+                                case 1: EA_PAIR(1); break;
+                                case 2: EA_PAIR(2); break;
+                                case 3: EA_PAIR(3); break;
+                                default: EA_PAIR(4); break;
+                            }
+#undef EA_PAIR
+                        } else {
+                            if (j0 < half)
+                                update_site<LAYOUT, false, SPLIT, RNG, PREDRAW>(sm, checker_site(j0, 0, L, invH, invL),
+                                                                                N, 1, 0, n_T, tn, r, c3flip, k0, k1,
+                                                                                segw, fd, nullptr, 0, gb, ngr_own,
+                                                                                st[0]);
+                            if (j0 + nthr < half)
+                                update_site<LAYOUT, false, SPLIT, RNG, PREDRAW>(sm, checker_site(j0 + nthr, 0, L,
+                                                                                                 invH, invL),
+                                                                                N, 1, 0, n_T, tn, r, c3flip, k0, k1,
+                                                                                segw, fd, nullptr, 0, gb, ngr_own,
+                                                                                st[1]);
+                        }
                         for (int j = tid + 2 * nthr; j < half; j += nthr)
                             update_site<LAYOUT, false, SPLIT, RNG>(sm, checker_site(j, 0, L, invH, invL), N, 1, 0, n_T,
                                                                   tn, r, c3flip, k0, k1, segw, fd, nullptr, 0, gb,
