@@ -279,8 +279,10 @@ static int choose_split(const ea_sim *s, int split_opt)
         if (ngr % parts != 0 || ladders * parts > cus) continue;
         // never more workgroups than CUs (measured: 4 parts x 512 threads, two per CU, is
         // slower than 2 parts x 1024); a small lattice is latency-bound: the exchange
-        // costs more than the split saves
-        if (split_opt == 0 && (int64_t)s->N * (ngr / parts) < 2048) continue;
+        // costs more than the split saves unless each part keeps enough work (measured
+        // with PT every sweep: 4 parts pay off from 1024 site-groups per part, 2 parts
+        // from 2048)
+        if (split_opt == 0 && (int64_t)s->N * (ngr / parts) < 4096 / parts) continue;
         const int blocks = (ladders + 7) / 8 * 8 * parts;
         const int per_cu = sweep_split_max_blocks_per_cu(parts, kernel_variant(s->layout, s->h.rng),
                                                          s->block_threads, s->lds);
