@@ -296,3 +296,19 @@ def test_field_equals_oracle(oracle_lib, L, R, n_T, layout, h, split):
                             t_min=0.5, t_max=3.0, splits=[4, 15])
     assert np.array_equal(sim.magnetization(), orc.magnetization())
     print(f"[parity] field launch {sim.info()}", flush=True)
+
+
+@pytest.mark.parametrize("L,R,n_T,parts", [
+    (16, 64, 32, 2),   # the benchmark job: 128 ladders, so 4 parts would exceed the CUs
+    (8, 4, 32, 4),     # each of 4 parts keeps 2 groups x 512 sites
+    (8, 1, 16, 1),     # too little work per part: the exchange would cost more than the split saves
+    (24, 2, 48, 1),    # two words per site: split ladders need one
+])
+def test_split_choice(L, R, n_T, parts):
+    """The automatic choice of workgroups per ladder on a 256-CU device."""
+    import torch
+    if torch.cuda.get_device_properties(0).multi_processor_count != 256:
+        pytest.skip("the choice depends on the number of compute units")
+    sim = B.Sim(L, inputs.couplings(L, R, 3), inputs.geometric_betas(n_T, 0.5, 2.0), 3)
+    assert sim.info()["split_parts"] == parts
+    sim.close()
