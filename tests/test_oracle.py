@@ -324,6 +324,86 @@ def test_exact_boltzmann_distribution_L2(oracle_lib, stream):
 
 
 # --------------------------------------------------------------------------
+# Observables by temperature index and the initial-spin stream
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("L", [2, 3, 4])
+def test_observables_by_temperature_index(oracle_lib, L):
+    """Energy and overlap per temperature index (Sec. 4.1 measurement; the
+    overlap between the two copies that enters the Binder ratio of Sec. 5.3)
+    for random spins and a different random slot permutation in every
+    ladder, against numpy: E[r][c][k] = H of copy c's slot at temperature k,
+    q[r][k] = sum_i s_i(copy 0 at T_k) s_i(copy 1 at T_k).
+
+    Plausible mistakes this catches, each checked by planting it in a copy of
+    the oracle: looking copy 1's slot up through copy 0's permutation;
+    summing s0 * s0 (or s1 * s1) in place of s0 * s1; indexing q or E by slot
+    instead of by temperature; using temp_of_slot where its inverse is meant."""
+    rng = np.random.default_rng(500 + L)
+    R, n_T = 3, 7
+    J = inputs.couplings(L, R, seed=40 + L)
+    sim = _sim(oracle_lib, L, J, inputs.geometric_betas(n_T, 0.5, 2.0))
+    for _ in range(3):
+        spins = rng.choice(np.array([-1, 1], dtype=np.int8), size=sim.spins.shape)
+        perm = np.stack([np.stack([rng.permutation(n_T) for _ in range(2)]) for _ in range(R)]).astype(np.int32)
+        # the two copies of a realization never share a permutation here
+        for r in range(R):
+            while np.array_equal(perm[r, 0], perm[r, 1]):
+                perm[r, 1] = rng.permutation(n_T)
+        sim.set_state(spins, perm, 0)
+        E, q = sim.observables()
+        for r in range(R):
+            slot_at = [np.empty(n_T, dtype=np.int64) for _ in range(2)]
+            for c in range(2):
+                for slot in range(n_T):
+                    slot_at[c][perm[r, c, slot]] = slot
+            for k in range(n_T):
+                a, b = slot_at[0][k], slot_at[1][k]
+                expect_q = int(np.dot(spins[r, 0, a].astype(np.int64), spins[r, 1, b].astype(np.int64)))
+                assert q[r, k] == expect_q, (r, k)
+                for c in range(2):
+                    assert E[r, c, k] == bf.energy(L, J[r], spins[r, c, slot_at[c][k]]), (r, c, k)
+
+
+def test_initial_spins_from_rocrand_blocks(oracle_lib, rocrand_probe):
+    """orc_init's spins rebuilt from rocRAND's Philox4x32-10 blocks with the
+    initial-spin stream of the library's header: spin (realization id r,
+    copy c, slot s, site i) is +1 iff bit 0 of word s & 3 of
+    block(c0 = i, c1 = 0, c2 = r, c3 = 2 << 28 | c << 24 | s >> 2) is set,
+    key (lo32(seed), hi32(seed)); the permutation starts as the identity.
+
+    Plausible mistakes this catches: a wrong domain or copy bit in c3;
+    counting slot groups by slot instead of slot >> 2; the wrong output word
+    or bit; the realization index in place of its id; the seed halves
+    swapped."""
+    L, n_T = 3, 6                     # a ragged last slot group
+    rids = np.array([5, 9], dtype=np.int32)
+    seed = 0x0123456789ABCDEF
+    J = inputs.couplings(L, len(rids), seed=3)
+    sim = _sim(oracle_lib, L, J, inputs.geometric_betas(n_T, 0.5, 2.0), seed=seed, rid=rids)
+    N = L ** 3
+    rows, index = [], []
+    for r_idx, rid in enumerate(rids):
+        for c in range(2):
+            for g in range((n_T + 3) // 4):
+                for i in range(N):
+                    rows.append((i, 0, int(rid), (2 << 28) | (c << 24) | g, seed & 0xFFFFFFFF, seed >> 32))
+                    index.append((r_idx, c, g, i))
+    text = "\n".join(" ".join(str(v) for v in row) for row in rows) + "\n"
+    res = subprocess.run([rocrand_probe], input=text, capture_output=True, text=True, check=True)
+    blocks = [list(map(int, line.split())) for line in res.stdout.strip().splitlines()]
+    assert len(blocks) == len(rows)
+    expect = np.zeros_like(sim.spins)
+    for (r_idx, c, g, i), blk in zip(index, blocks):
+        for w in range(4):
+            s = 4 * g + w
+            if s < n_T:
+                expect[r_idx, c, s, i] = 1 if blk[w] & 1 else -1
+    assert np.array_equal(sim.spins, expect)
+    assert np.array_equal(sim.temp_of_slot, np.tile(np.arange(n_T, dtype=np.int32), (len(rids), 2, 1)))
+    assert sim.t == 0
+
+
+# --------------------------------------------------------------------------
 # Measurements: overlap moments and plane-sum autocorrelations (Sec. 5)
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("L", [2, 3, 4, 5])
