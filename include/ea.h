@@ -60,6 +60,7 @@ extern "C" {
 #define EA_ENOMEM   -2   /* a device or host allocation failed                    */
 #define EA_EDEVICE  -3   /* a HIP call failed (message names it)                  */
 #define EA_ESTATE   -4   /* the handle cannot do this now (e.g. sweep counter full) */
+#define EA_EBUSY    -5   /* the job is held by another live plan (ea_plan_create)  */
 
 /* spin layouts (Sec. 4.3.3) */
 #define EA_LAYOUT_CAMSC 0  /* 1 bit per temperature slot, 32 slots per 32-bit word; the
@@ -147,7 +148,8 @@ int ea_sweep(ea_sim *sim, int64_t n_sweeps, int swap_every);
  * realizations to workgroups; here the ladders of all jobs share one queue).  n_sweeps[j] and
  * swap_every[j] apply to sims[j] exactly as in ea_sweep; each job's results
  * equal those of running it alone.  All sims must live on the current device
- * and share one layout; the launch uses sims[0]'s stream. */
+ * and share one layout; the launch uses sims[0]'s stream, after the work
+ * already queued on every job's own stream, and returns when it is done. */
 int ea_sweep_batch(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps,
                    const int *swap_every);
 
@@ -159,8 +161,10 @@ int ea_sweep_batch(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps,
  * in device memory, so every replay continues each job's random stream: the
  * results equal those of ea_sweep on each job alone.  The workgroup size is
  * opt->block_threads, or picked by timing candidates on scratch copies of the
- * jobs (results never depend on it).  The jobs must outlive the plan and must
- * not be swept through other calls while a plan run is in flight. */
+ * jobs (results never depend on it).  A job belongs to at most one live plan
+ * (EA_EBUSY otherwise).  Each run is ordered after the work queued on the
+ * jobs' own streams, and later work queued there is ordered after the run.
+ * Destroying a job while a plan holds it makes ea_plan_run return EA_ESTATE. */
 typedef struct ea_plan ea_plan;
 typedef struct ea_plan_options {
     int block_threads;   /* 0 = autotune (or, with autotune = 0, the largest planned size) */
@@ -241,20 +245,28 @@ int ea_observables(ea_sim *sim, int32_t *energy, int32_t *overlap);
  * the total energy is energy - h M).  Synchronous. */
 int ea_magnetization(ea_sim *sim, int32_t *magnetization);
 
-/* Read the full state: spins int8 [R][2][n_T][L^3] (+1/-1, indexed by slot),
- * temp_of_slot int32 [R][2][n_T], sweeps_done.  Any pointer may be NULL.
- * Synchronous.  With ea_set_state this is checkpoint/resume: the stream is
- * counter-based, so a resumed run continues bit-identically. */
+/* Spin dump (Sec. 4.1: the configurations are copied out of the simulation
+ * kernel's state for measurements and analysis on the host).  Read the full
+ * state: spins int8 [R][2][n_T][L^3] (+1/-1, indexed by slot), temp_of_slot
+ * int32 [R][2][n_T] (Sec. 4.3.1: a slot keeps its spins and changes
+ * temperature on an accepted swap), sweeps_done.  Any pointer may be NULL.
+ * Synchronous.  Uses a temporary device buffer of R*2*n_T*L^3 bytes
+ * (EA_ENOMEM if it cannot be had).  With ea_set_state this is
+ * checkpoint/resume: the stream is counter-based, so a resumed run continues
+ * bit-identically. */
 int ea_state(ea_sim *sim, int8_t *spins, int32_t *temp_of_slot, int64_t *sweeps_done);
 
-/* Overwrite the state (same shapes; temp_of_slot must be a permutation of
- * 0..n_T-1 in every ladder, sweeps_done in [0, 2^32)).  EA_EINVAL leaves the
- * state unchanged. */
+/* Restore a spin dump (the inverse of ea_state, Sec. 4.1).  Overwrite the
+ * state (same shapes; temp_of_slot must be a permutation of 0..n_T-1 in
+ * every ladder, sweeps_done in [0, 2^32)).  EA_EINVAL leaves the state
+ * unchanged.  The measurement accumulators and swap counts are kept. */
 int ea_set_state(ea_sim *sim, const int8_t *spins, const int32_t *temp_of_slot,
                  int64_t sweeps_done);
 
 /* Accepted swaps per (realization, copy, pair k) since creation, uint64
- * [R][2][n_T-1] (n_T = 1: nothing written).  Synchronous. */
+ * [R][2][n_T-1] (n_T = 1: nothing written); the device counts in 64 bits.
+ * Synchronous.  (Sec. 2.4: the acceptance rate of each adjacent pair is what
+ * a temperature ladder is tuned by.) */
 int ea_swap_acceptance(ea_sim *sim, uint64_t *accepted);
 
 /* ---- Measurements of the spin-glass order (Sec. 5: Binder ratio of the overlap,

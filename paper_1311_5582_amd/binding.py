@@ -17,7 +17,7 @@ ROOT = os.path.dirname(PKG)
 LIB_PATH = os.path.join(PKG, "libea_mi355x.so")
 HEADER = os.path.join(ROOT, "include", "ea.h")
 
-EA_OK, EA_EINVAL, EA_ENOMEM, EA_EDEVICE, EA_ESTATE = 0, -1, -2, -3, -4
+EA_OK, EA_EINVAL, EA_ENOMEM, EA_EDEVICE, EA_ESTATE, EA_EBUSY = 0, -1, -2, -3, -4, -5
 LAYOUT_CAMSC, LAYOUT_AMSC4 = 0, 1
 LAYOUT_AMSC3, LAYOUT_AMSC1 = 2, 3
 LAYOUTS = {"camsc": LAYOUT_CAMSC, "amsc4": LAYOUT_AMSC4, "amsc3": LAYOUT_AMSC3, "amsc1": LAYOUT_AMSC1}
@@ -347,40 +347,6 @@ class Plan:
 
     def run(self, n_steps=1):
         check(lib().ea_plan_run(self._h, int(n_steps)))
-
-    def magnetization(self):
-        """sum_i s_i [R][2][n_T] by temperature index."""
-        m = np.zeros((self.R, 2, self.n_T), np.int32)
-        check(lib().ea_magnetization(self._h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
-        return m
-
-    def measure(self):
-        """Add one measurement of the current state to the device accumulators."""
-        check(lib().ea_measure(self._h))
-
-    def measurements(self):
-        """(count, sum_q2 [R][n_T], sum_q4 [R][n_T][2] uint64 lo/hi, sum_c [R][n_T][L])."""
-        R, n_T, L = self.R, self.n_T, self.L
-        count = np.zeros((R, n_T), np.int64)
-        q2 = np.zeros((R, n_T), np.int64)
-        q4 = np.zeros((R, n_T, 2), np.uint64)
-        c = np.zeros((R, n_T, L), np.int64)
-        check(lib().ea_measure_read(self._h, count.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                    q2.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                    q4.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
-                                    c.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
-        return count, q2, q4, c
-
-    def reset_measurements(self):
-        check(lib().ea_measure_reset(self._h))
-
-    def binder_xi(self):
-        """Binder ratio and xi / L per temperature index."""
-        g = np.zeros(self.n_T, np.float64)
-        x = np.zeros(self.n_T, np.float64)
-        check(lib().ea_binder_xi(self._h, g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                 x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
-        return g, x
 
     def info(self):
         bt, grid, units, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

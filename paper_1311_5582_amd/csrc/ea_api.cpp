@@ -99,6 +99,31 @@ int dev_alloc(ea_sim *s, size_t bytes, void **out)
     return EA_OK;
 }
 
+// A temporary device buffer from the job's allocator (not counted in its footprint).
+int temp_alloc(ea_sim *s, size_t bytes, void **out)
+{
+    bytes = std::max<size_t>(bytes, 16);
+    void *p = nullptr;
+    if (s->da.alloc) {
+        p = s->da.alloc(bytes, s->da.ctx);
+        if (!p) return fail(EA_ENOMEM, "device allocator returned NULL for %zu bytes", bytes);
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) return fail(EA_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    *out = p;
+    return EA_OK;
+}
+
+void temp_free(ea_sim *s, void *p)
+{
+    if (!p) return;
+    if (s->da.release)
+        s->da.release(p, s->da.ctx);
+    else
+        (void)hipFree(p);
+}
+
 void release_all(ea_sim *s)
 {
     for (void *p : s->owned) {
@@ -257,7 +282,7 @@ size_t job_footprint_bytes(int L, int n_T, int R, int layout, int64_t swap_entri
     const size_t N = (size_t)L * L * L, ladders = 2 * (size_t)R;
     const size_t NW = (size_t)(n_T + slots_per_word(layout) - 1) / slots_per_word(layout);
     return a(ladders * NW * N * 4) + a((size_t)R * N) + a(ladders * kMaxTemps * 4) + a((size_t)n_T * kThrCols * 4) +
-           a((size_t)swap_entries * 4) + 3 * a(kMaxTemps * 4) + a(N * 4) + a(2 * 4) + a(ladders * kMaxTemps * 4) +
+           a((size_t)swap_entries * 4) + 3 * a(kMaxTemps * 4) + a(N * 4) + a(2 * 4) + a(ladders * kMaxTemps * 8) +
            a(ladders * 4) + a(sizeof(JobDesc)) + a(ladders * 2 * kMaxTemps * 8) + a(4) +
            a((size_t)R * n_T * (4 + L) * 8) + a((size_t)R * n_T * 5 * 4);
 }
@@ -290,6 +315,22 @@ static int choose_split(const ea_sim *s, int split_opt)
         return parts;
     }
     return 1;
+}
+
+int order_streams(ea_sim *const *sims, int n_sims, hipStream_t st, bool after)
+{
+    for (int j = 0; j < n_sims; ++j) {
+        ea_sim *s = sims[j];
+        if (s->stream == st) continue;
+        if (after) {
+            EA_HIP(hipEventRecord(s->ev, st));
+            EA_HIP(hipStreamWaitEvent(s->stream, s->ev, 0));
+        } else {
+            EA_HIP(hipEventRecord(s->ev, s->stream));
+            EA_HIP(hipStreamWaitEvent(st, s->ev, 0));
+        }
+    }
+    return EA_OK;
 }
 
 int check_split_error(ea_sim *s)
@@ -375,9 +416,16 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
     s->user_stream = opt.stream != nullptr;
     s->da.alloc = opt.dev_alloc; s->da.release = opt.dev_free; s->da.ctx = opt.alloc_ctx;
 
-    auto bail = [s](int rc) { release_all(s); delete s; return rc; };
+    auto bail = [s](int rc) {
+        release_all(s);
+        if (s->ev) (void)hipEventDestroy(s->ev);
+        delete s;
+        return rc;
+    };
     hipError_t he = hipGetDevice(&s->device);
     if (he != hipSuccess) return bail(fail(EA_EDEVICE, "hipGetDevice failed: %s", hipGetErrorString(he)));
+    he = hipEventCreateWithFlags(&s->ev, hipEventDisableTiming);
+    if (he != hipSuccess) return bail(fail(EA_EDEVICE, "hipEventCreate failed: %s", hipGetErrorString(he)));
 
     const int ladders = 2 * n_realizations;
     // tables
@@ -441,7 +489,7 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
     std::vector<uint32_t> counters(2, 0u);
     if ((rc = upload(s, counters, &s->d_counters))) return bail(rc);
     h.sweep_ctr = s->d_counters;
-    std::vector<uint32_t> acc((size_t)ladders * kMaxTemps, 0u);
+    std::vector<uint64_t> acc((size_t)ladders * kMaxTemps, 0u);
     if ((rc = upload(s, acc, &h.swap_acc))) return bail(rc);
     std::vector<uint64_t> xchg((size_t)ladders * 2 * kMaxTemps, 0);
     std::vector<uint32_t> err(1, 0u);
@@ -601,7 +649,9 @@ void ea_destroy(ea_sim *s)
     if (!s) return;
     (void)hipSetDevice(s->device);
     (void)hipStreamSynchronize(s->stream);
+    if (s->plan) plan_forget_job(s->plan, s);
     release_all(s);
+    if (s->ev) (void)hipEventDestroy(s->ev);
     delete s;
 }
 
@@ -655,12 +705,12 @@ int ea_state(ea_sim *s, int8_t *spins, int32_t *temp_of_slot, int64_t *sweeps_do
     hipError_t e = hipSuccess;
     if (spins) {
         const size_t n = (size_t)ladders * s->n_T * s->N;
-        int8_t *d = nullptr;
-        EA_HIP(hipMalloc(&d, n));
-        e = launch_unpack(s->d_job, s->h, s->layout, d, s->stream);
+        void *d = nullptr;
+        if (int rc = temp_alloc(s, n, &d)) return rc;
+        e = launch_unpack(s->d_job, s->h, s->layout, (int8_t *)d, s->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(spins, d, n, hipMemcpyDeviceToHost, s->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-        (void)hipFree(d);
+        temp_free(s, d);
         if (e != hipSuccess) return fail(EA_EDEVICE, "state readout failed: %s", hipGetErrorString(e));
     }
     if (temp_of_slot) {
@@ -699,11 +749,11 @@ int ea_set_state(ea_sim *s, const int8_t *spins, const int32_t *temp_of_slot, in
         }
     }
     EA_HIP(hipSetDevice(s->device));
-    int8_t *d = nullptr;
-    EA_HIP(hipMalloc(&d, n));
+    void *d = nullptr;
+    if (int rc = temp_alloc(s, n, &d)) return rc;
     const uint32_t t = (uint32_t)sweeps_done;
     hipError_t e = hipMemcpyAsync(d, spins, n, hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = launch_pack(s->d_job, s->h, s->layout, d, s->stream);
+    if (e == hipSuccess) e = launch_pack(s->d_job, s->h, s->layout, (const int8_t *)d, s->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->h.temp_of_slot, perm.data(), perm.size() * 4, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(s->d_counters, &t, sizeof t, hipMemcpyHostToDevice, s->stream);
@@ -712,7 +762,7 @@ int ea_set_state(ea_sim *s, const int8_t *spins, const int32_t *temp_of_slot, in
     // a valid state clears an earlier exchange timeout
     if (e == hipSuccess) e = hipMemsetAsync(s->h.error, 0, sizeof(uint32_t), s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    (void)hipFree(d);
+    temp_free(s, d);
     if (e != hipSuccess) return fail(EA_EDEVICE, "state upload failed: %s", hipGetErrorString(e));
     s->t = sweeps_done;
     return EA_OK;
@@ -723,8 +773,8 @@ int ea_swap_acceptance(ea_sim *s, uint64_t *accepted)
     if (!s || !accepted) return fail(EA_EINVAL, "ea_swap_acceptance: NULL argument");
     EA_HIP(hipSetDevice(s->device));
     const int ladders = 2 * s->R;
-    std::vector<uint32_t> acc((size_t)ladders * kMaxTemps);
-    EA_HIP(hipMemcpyAsync(acc.data(), s->h.swap_acc, acc.size() * 4, hipMemcpyDeviceToHost, s->stream));
+    std::vector<uint64_t> acc((size_t)ladders * kMaxTemps);
+    EA_HIP(hipMemcpyAsync(acc.data(), s->h.swap_acc, acc.size() * 8, hipMemcpyDeviceToHost, s->stream));
     EA_HIP(hipStreamSynchronize(s->stream));
     for (int l = 0; l < ladders; ++l)
         for (int k = 0; k + 1 < s->n_T; ++k)

@@ -69,8 +69,15 @@ struct ea_sim {
     int split_parts = 1;              // workgroups per ladder in a lone launch (1, 2 or 4)
     int64_t *d_meas = nullptr;        // measurement sums: count, q^2 [R][n_T], q^4 [R][n_T][2], C [R][n_T][L]
     int32_t *d_obs = nullptr;         // observables outputs: energy, overlap, magnetization
+    hipEvent_t ev = nullptr;          // orders launches on other streams (batches, plans) with this job's stream
+    ea_plan *plan = nullptr;          // the live plan that holds this job, if any
 };
 
 namespace ea {
 int check_split_error(ea_sim *s);
+// Make `st` wait for the work queued so far on each job's own stream, or each
+// job's stream wait for the work queued so far on `st` (after = true).
+int order_streams(ea_sim *const *sims, int n_sims, hipStream_t st, bool after);
+// A job held by a live plan is being destroyed: the plan drops it and refuses to run.
+void plan_forget_job(ea_plan *p, ea_sim *s);
 }

@@ -56,7 +56,7 @@ struct JobDesc {
     const int32_t *swap_sgn;  // [kMaxTemps] sign of beta_k - beta_{k+1}
     const uint32_t *sites;    // [N] packed x | y<<8 | z<<16, grouped by colour class
     uint32_t *sweep_ctr;      // sweeps done (next sweep index); advanced after each launch
-    uint32_t *swap_acc;       // [ladders][kMaxTemps] accepted swaps per pair
+    uint64_t *swap_acc;       // [ladders][kMaxTemps] accepted swaps per pair
     int32_t class_off[4];     // colour class c = sites[class_off[c] .. class_off[c+1])
     uint32_t key0, key1;      // Philox key
     int32_t L, N, n_T, NW;    // NW = words per site
@@ -145,6 +145,7 @@ hipError_t launch_sweep(const JobDesc *d_jobs, int n_jobs, const uint32_t *d_uni
 hipError_t launch_sweep_split(const JobDesc *d_job, int ladders, int parts, int kv, int block_threads, size_t lds,
                               uint32_t *d_queue, hipStream_t s);
 int sweep_split_max_blocks_per_cu(int parts, int kv, int block_threads, size_t lds);
+
 hipError_t launch_observables(const JobDesc *d_job, const JobDesc &h_job, int layout, int32_t *d_energy,
                               int32_t *d_overlap, int32_t *d_magnet, hipStream_t s);
 hipError_t launch_unpack(const JobDesc *d_job, const JobDesc &h_job, int layout, int8_t *d_spins, hipStream_t s);

@@ -189,13 +189,13 @@ static int autotune_bt(const std::vector<JobDesc> &descs, const std::vector<size
         void *sp = nullptr, *pm = nullptr, *ac = nullptr, *ct = nullptr;
         hipError_t e = hipMalloc(&sp, spin_bytes);
         if (e == hipSuccess) bufs.push_back(sp), e = hipMalloc(&pm, (size_t)d.ladders * kMaxTemps * 4);
-        if (e == hipSuccess) bufs.push_back(pm), e = hipMalloc(&ac, (size_t)d.ladders * kMaxTemps * 4);
+        if (e == hipSuccess) bufs.push_back(pm), e = hipMalloc(&ac, (size_t)d.ladders * kMaxTemps * 8);
         if (e == hipSuccess) bufs.push_back(ac), e = hipMalloc(&ct, 8);
         if (e == hipSuccess) bufs.push_back(ct);
         if (e == hipSuccess) e = hipMemcpyAsync(sp, d.spins, spin_bytes, hipMemcpyDeviceToDevice, st);
         if (e == hipSuccess)
             e = hipMemcpyAsync(pm, d.temp_of_slot, (size_t)d.ladders * kMaxTemps * 4, hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess) e = hipMemsetAsync(ac, 0, (size_t)d.ladders * kMaxTemps * 4, st);
+        if (e == hipSuccess) e = hipMemsetAsync(ac, 0, (size_t)d.ladders * kMaxTemps * 8, st);
         if (e == hipSuccess) e = hipMemcpyAsync(ct, d.sweep_ctr, 4, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) {
             cleanup();
@@ -203,7 +203,7 @@ static int autotune_bt(const std::vector<JobDesc> &descs, const std::vector<size
         }
         d.spins = (uint32_t *)sp;
         d.temp_of_slot = (int32_t *)pm;
-        d.swap_acc = (uint32_t *)ac;
+        d.swap_acc = (uint64_t *)ac;
         d.sweep_ctr = (uint32_t *)ct;
         work += (int64_t)d.ladders * d.N * d.n_T;
     }
@@ -274,7 +274,17 @@ struct ea_plan {
     bool use_graph = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    bool lost_job = false;   // a job was destroyed while the plan held it
 };
+
+namespace ea {
+void plan_forget_job(ea_plan *p, ea_sim *s)
+{
+    (void)hipStreamSynchronize(p->stream);   // no replay may still read the job
+    p->sims.erase(std::remove(p->sims.begin(), p->sims.end(), s), p->sims.end());
+    p->lost_job = true;
+}
+}  // namespace ea
 
 extern "C" {
 
@@ -332,6 +342,8 @@ int ea_sweep_batch(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps, con
     }
     LaunchSet ls;
     int rc = launchset_build(ls, descs, lds, kernel_variant(s0->layout, s0->h.rng), 0, st);
+    // the launch runs on sims[0]'s stream: first let it wait for the other jobs' streams
+    if (rc == EA_OK) rc = order_streams(sims, n_sims, st, false);
     if (rc == EA_OK) rc = launchset_launch(ls, st);
     if (rc == EA_OK) {
         hipError_t e = hipStreamSynchronize(st);
@@ -364,6 +376,8 @@ int ea_plan_create(ea_sim *const *sims, int n_sims, int sweeps_per_step, const i
     if (int rc = validate_jobs(sims, n_sims, ns.data(), swap_every)) return rc;
     if (opt.block_threads != 0 && (opt.block_threads < 64 || opt.block_threads > kMaxBlock || opt.block_threads % 64))
         return fail(EA_EINVAL, "block_threads=%d must be a multiple of 64 in [64, %d]", opt.block_threads, kMaxBlock);
+    for (int j = 0; j < n_sims; ++j)
+        if (sims[j]->plan) return fail(EA_EBUSY, "sims[%d] is held by another live plan", j);
     EA_HIP(hipSetDevice(sims[0]->device));
     ea_plan *p = new (std::nothrow) ea_plan;
     if (!p) return fail(EA_ENOMEM, "host allocation failed");
@@ -418,6 +432,7 @@ int ea_plan_create(ea_sim *const *sims, int n_sims, int sweeps_per_step, const i
         if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
         if (e != hipSuccess) return bail(fail(EA_EDEVICE, "graph capture failed: %s", hipGetErrorString(e)));
     }
+    for (ea_sim *s : p->sims) s->plan = p;
     *out = p;
     return EA_OK;
 }
@@ -426,16 +441,22 @@ int ea_plan_run(ea_plan *p, int64_t n_steps)
 {
     if (!p) return fail(EA_EINVAL, "ea_plan_run: NULL plan");
     if (n_steps < 0) return fail(EA_EINVAL, "n_steps < 0");
+    if (p->lost_job) return fail(EA_ESTATE, "a job of this plan was destroyed; destroy the plan");
     const int64_t add = n_steps * p->sweeps_per_step;
     for (ea_sim *s : p->sims)
         if (s->t + add >= ((int64_t)1 << 32)) return fail(EA_ESTATE, "a job's sweep counter would reach 2^32");
     EA_HIP(hipSetDevice(p->device));
+    if (n_steps == 0) return EA_OK;
+    // order the replays after the work already queued on the jobs' own streams,
+    // and later work on those streams after the replays
+    if (int rc = order_streams(p->sims.data(), (int)p->sims.size(), p->stream, false)) return rc;
     for (int64_t k = 0; k < n_steps; ++k) {
         if (p->exec)
             EA_HIP(hipGraphLaunch(p->exec, p->stream));
         else if (int rc = launchset_launch(p->ls, p->stream))
             return rc;
     }
+    if (int rc = order_streams(p->sims.data(), (int)p->sims.size(), p->stream, true)) return rc;
     for (ea_sim *s : p->sims) s->t += add;
     if (!p->user_stream) EA_HIP(hipStreamSynchronize(p->stream));
     return EA_OK;
@@ -457,6 +478,8 @@ void ea_plan_destroy(ea_plan *p)
     if (!p) return;
     (void)hipSetDevice(p->device);
     (void)hipStreamSynchronize(p->stream);
+    for (ea_sim *s : p->sims)
+        if (s->plan == p) s->plan = nullptr;
     launchset_free(p->ls);
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);

@@ -4,6 +4,7 @@ oracle's (two independent implementations of Sec. 4.3.1-4.3.2), and invalid
 arguments are rejected before any device call."""
 import ctypes
 import math
+import os
 
 import numpy as np
 import pytest
@@ -129,3 +130,39 @@ def test_job_footprint_host_only(lib):
     # the spin words dominate: 2R ladders x words x N x 4 bytes
     assert more - big >= 2 * 4 * 16 ** 3 * 4
     assert B.job_footprint(16, betas, 4, "amsc4") > big
+
+
+def test_status_codes_match_header():
+    """Every status code of include/ea.h has the same value in the binding."""
+    import re
+    text = open(B.HEADER).read()
+    codes = dict((m.group(1), int(m.group(2))) for m in re.finditer(r"#define\s+(EA_E[A-Z]+|EA_OK)\s+(-?\d+)", text))
+    assert set(codes) >= {"EA_OK", "EA_EINVAL", "EA_ENOMEM", "EA_EDEVICE", "EA_ESTATE", "EA_EBUSY"}
+    for name, value in codes.items():
+        assert getattr(B, name) == value, name
+    assert len(set(codes.values())) == len(codes)
+
+
+def test_plan_binding_calls_only_plan_functions():
+    """A plan handle is not a job handle: every library call the Plan class
+    makes is an ea_plan_* function (passing an ea_plan* where the ABI expects
+    an ea_sim* would launch kernels on a garbage descriptor)."""
+    import inspect
+    import re
+    src = inspect.getsource(B.Plan)
+    calls = set(re.findall(r"lib\(\)\.(ea_[a-z_0-9]+)\(", src))
+    assert calls, "Plan makes no library call"
+    assert all(c.startswith("ea_plan_") or c == "ea_default_plan_options" for c in calls), calls
+    for name in ("measure", "measurements", "reset_measurements", "binder_xi", "magnetization", "observables",
+                 "state"):
+        assert not hasattr(B.Plan, name), name
+
+
+def test_swap_acceptance_is_64_bit_in_the_header():
+    """The per-pair accepted-swap counts cross the ABI as uint64 and the
+    header states that the device counts in 64 bits (no wrap at 2^32)."""
+    text = open(B.HEADER).read()
+    assert "int ea_swap_acceptance(ea_sim *sim, uint64_t *accepted);" in text
+    assert "the device counts in 64 bits" in text
+    internal = open(os.path.join(B.PKG, "csrc", "ea_internal.h")).read()
+    assert "uint64_t *swap_acc;" in internal
