@@ -153,6 +153,25 @@ int ea_sweep(ea_sim *sim, int64_t n_sweeps, int swap_every);
 int ea_sweep_batch(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps,
                    const int *swap_every);
 
+/* For callers that cannot allocate device memory: code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * ordering and results as ea_sweep_batch, but the launch's work-queue counter,
+ * job descriptors and ladder list live in a static workspace of the library
+ * (about 1.1 MB, one copy per device, held until the process ends) instead of
+ * buffers allocated per call; no device memory is allocated or freed.
+ * Limits: at most EA_NOALLOC_MAX_JOBS jobs, and at most EA_NOALLOC_MAX_LADDERS
+ * ladders (2 x realizations) over the jobs with n_sweeps > 0; beyond them
+ * EA_EINVAL and nothing runs.  A single job takes ea_sweep's lone launch,
+ * which uses only the job's own buffers.  Every call on one device shares
+ * that device's workspace and keeps the last call's contents: calls that
+ * overlap in time on one device (several host threads) race and must be
+ * serialised by the caller; calls made one after another are safe, since
+ * each returns only when its launch is done. */
+#define EA_NOALLOC_MAX_JOBS    256
+#define EA_NOALLOC_MAX_LADDERS 262144
+int ea_sweep_batch_noalloc(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps,
+                           const int *swap_every);
+
 /* ---- Launch plans: one step over several jobs, captured once and replayed ----
  * A plan freezes a job list and a step (sweeps_per_step sweeps of every job,
  * with swap_every[j] for job j, as ea_sweep would run them) into one

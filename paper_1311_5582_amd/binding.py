@@ -77,6 +77,7 @@ def lib():
                                          ctypes.POINTER(Options), ctypes.POINTER(P)]),
             "ea_sweep": (ctypes.c_int, [P, ctypes.c_int64, ctypes.c_int]),
             "ea_sweep_batch": (ctypes.c_int, [ctypes.POINTER(P), ctypes.c_int, i64p, i32p]),
+            "ea_sweep_batch_noalloc": (ctypes.c_int, [ctypes.POINTER(P), ctypes.c_int, i64p, i32p]),
             "ea_observables": (ctypes.c_int, [P, i32p, i32p]),
             "ea_state": (ctypes.c_int, [P, i8p, i32p, i64p]),
             "ea_set_state": (ctypes.c_int, [P, i8p, i32p, ctypes.c_int64]),
@@ -316,6 +317,16 @@ def sweep_batch(sims, n_sweeps, swap_every):
     ns = np.ascontiguousarray(n_sweeps, dtype=np.int64)
     se = np.ascontiguousarray(swap_every, dtype=np.int32)
     check(lib().ea_sweep_batch(hs, n, _p(ns, ctypes.c_int64), _p(se, ctypes.c_int32)))
+
+
+def sweep_batch_noalloc(sims, n_sweeps, swap_every):
+    """sweep_batch through the entry point that allocates no device memory
+    (its launch arrays live in the library's static per-device workspace)."""
+    n = len(sims)
+    hs = (ctypes.c_void_p * n)(*[s.handle.value for s in sims])
+    ns = np.ascontiguousarray(n_sweeps, dtype=np.int64)
+    se = np.ascontiguousarray(swap_every, dtype=np.int32)
+    check(lib().ea_sweep_batch_noalloc(hs, n, _p(ns, ctypes.c_int64), _p(se, ctypes.c_int32)))
 
 
 def job_footprint(L, betas, n_realizations, layout="camsc"):

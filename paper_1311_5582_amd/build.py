@@ -10,7 +10,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libea_mi355x.so")
-SOURCES = [os.path.join(PKG, "csrc", f) for f in ("ea_kernels.hip", "ea_api.cpp", "ea_runtime.cpp", "ea_server.cpp")]
+SOURCES = [os.path.join(PKG, "csrc", f) for f in ("ea_kernels.hip", "ea_workspace.hip", "ea_api.cpp", "ea_runtime.cpp", "ea_server.cpp")]
 ARCH = os.environ.get("EA_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -30,15 +30,19 @@ def hipcc():
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
+    import concurrent.futures as cf
+    objs, cmds = [], []
     for src in SOURCES:
         obj = os.path.join(PKG, "csrc", os.path.basename(src) + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
-        cmd = [hipcc()] + HIPCC_FLAGS + lang + ["-c", src, "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append([hipcc()] + HIPCC_FLAGS + ["-x", "hip", "-c", src, "-o", obj])
         objs.append(obj)
+    # the translation units are independent: compile them side by side
+    with cf.ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as ex:
+        for cmd in cmds:
+            if verbose:
+                print(" ".join(cmd), flush=True)
+        for f in [ex.submit(subprocess.run, cmd, check=True) for cmd in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

@@ -155,4 +155,16 @@ hipError_t launch_pack(const JobDesc *d_job, const JobDesc &h_job, int layout, c
 hipError_t sweep_set_lds(int kv, size_t lds);
 int sweep_max_blocks_per_cu(int kv, int block_threads, size_t lds);
 
+// Static workspace of the allocation-free batch launch (ea_sweep_batch_noalloc):
+// work-queue counter, job descriptors and unit list of one launch, at fixed
+// offsets.  One copy per device, held until the process ends.
+constexpr int kNoallocMaxJobs = 256;
+constexpr int kNoallocMaxUnits = 1 << 18;
+constexpr size_t kNoallocQueueOff = 0;
+constexpr size_t kNoallocDescOff = 256;
+constexpr size_t kNoallocUnitOff = (kNoallocDescOff + kNoallocMaxJobs * sizeof(JobDesc) + 255) / 256 * 256;
+constexpr size_t kNoallocBytes = kNoallocUnitOff + (size_t)kNoallocMaxUnits * 4;
+// Device address of the workspace on the current device (looked up once per device).
+hipError_t noalloc_workspace(void **ptr);
+
 }  // namespace ea

@@ -46,10 +46,12 @@ static int min_block_threads(int N)
     return ((N + 84) / 85 + 63) / 64 * 64;
 }
 
-// descs[j] describes job j for this launch (n_sweeps/swap_every already set).
-// bt = 0 takes the largest planned size among the jobs.
-static int launchset_build(LaunchSet &ls, const std::vector<JobDesc> &descs, const std::vector<size_t> &lds_per_job,
-                           int layout, int bt, hipStream_t st)
+// Host part of a launch over descs (descs[j] describes job j with n_sweeps and
+// swap_every already set): the unit list, ladders of the most work first, the
+// workgroup size (bt = 0: the largest planned size among the jobs), LDS bytes
+// and grid.
+static int launchset_plan(LaunchSet &ls, const std::vector<JobDesc> &descs, const std::vector<size_t> &lds_per_job,
+                          int layout, int bt, std::vector<uint32_t> *units)
 {
     ls.layout = layout;
     ls.n_jobs = (int)descs.size();
@@ -74,11 +76,21 @@ static int launchset_build(LaunchSet &ls, const std::vector<JobDesc> &descs, con
     if (ls.bt < need_bt) return fail(EA_EINVAL, "block_threads=%d is below %d needed by a job", ls.bt, need_bt);
     ls.lds = lds;
     ls.n_units = (int)order.size();
+    units->resize(order.size());
+    for (size_t k = 0; k < order.size(); ++k) (*units)[k] = order[k].second;
     if (ls.n_units == 0) return EA_OK;
-    std::vector<uint32_t> units(order.size());
-    for (size_t k = 0; k < order.size(); ++k) units[k] = order[k].second;
     if (int rc = device_grid(layout, ls.bt, ls.lds, ls.n_units, &ls.grid)) return rc;
     EA_HIP(sweep_set_lds(layout, ls.lds));   // before any capture: not a stream operation
+    return EA_OK;
+}
+
+// Plan a launch and give it device arrays of its own.
+static int launchset_build(LaunchSet &ls, const std::vector<JobDesc> &descs, const std::vector<size_t> &lds_per_job,
+                           int layout, int bt, hipStream_t st)
+{
+    std::vector<uint32_t> units;
+    if (int rc = launchset_plan(ls, descs, lds_per_job, layout, bt, &units)) return rc;
+    if (ls.n_units == 0) return EA_OK;
     EA_HIP(hipMalloc(&ls.d_descs, descs.size() * sizeof(JobDesc)));
     EA_HIP(hipMalloc(&ls.d_units, units.size() * sizeof(uint32_t)));
     EA_HIP(hipMalloc(&ls.d_queue, sizeof(uint32_t)));
@@ -351,6 +363,58 @@ int ea_sweep_batch(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps, con
     }
     launchset_free(ls);
     if (rc) return rc;
+    for (int j = 0; j < n_sims; ++j) sims[j]->t += n_sweeps[j];
+    return EA_OK;
+}
+
+int ea_sweep_batch_noalloc(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps, const int *swap_every)
+{
+    if (int rc = validate_jobs(sims, n_sims, n_sweeps, swap_every)) return rc;
+    if (n_sims > kNoallocMaxJobs)
+        return fail(EA_EINVAL, "ea_sweep_batch_noalloc: %d jobs exceed the workspace limit of %d", n_sims,
+                    kNoallocMaxJobs);
+    int64_t units = 0;
+    for (int j = 0; j < n_sims; ++j) {
+        if (sims[j]->t + n_sweeps[j] >= ((int64_t)1 << 32))
+            return fail(EA_ESTATE, "sweep counter of sims[%d] would reach 2^32", j);
+        if (n_sweeps[j] > 0) units += 2 * (int64_t)sims[j]->R;
+    }
+    if (units > kNoallocMaxUnits)
+        return fail(EA_EINVAL, "ea_sweep_batch_noalloc: %lld ladders exceed the workspace limit of %d",
+                    (long long)units, kNoallocMaxUnits);
+    // one job: the lone launch uses only the job's own device buffers
+    if (n_sims == 1) return ea_sweep_batch(sims, n_sims, n_sweeps, swap_every);
+    ea_sim *s0 = sims[0];
+    EA_HIP(hipSetDevice(s0->device));
+    hipStream_t st = s0->stream;
+    std::vector<JobDesc> descs(n_sims);
+    std::vector<size_t> lds(n_sims);
+    for (int j = 0; j < n_sims; ++j) {
+        descs[j] = sims[j]->h;
+        descs[j].n_sweeps = (int32_t)n_sweeps[j];
+        descs[j].swap_every = swap_every[j];
+        lds[j] = sims[j]->lds;
+    }
+    LaunchSet ls;   // its device arrays are the workspace: never launchset_free it
+    std::vector<uint32_t> order;
+    if (int rc = launchset_plan(ls, descs, lds, kernel_variant(s0->layout, s0->h.rng), 0, &order)) return rc;
+    if (ls.n_units > 0) {
+        void *ws = nullptr;
+        EA_HIP(noalloc_workspace(&ws));
+        uint8_t *base = (uint8_t *)ws;
+        ls.d_queue = (uint32_t *)(base + kNoallocQueueOff);
+        ls.d_descs = (JobDesc *)(base + kNoallocDescOff);
+        ls.d_units = (uint32_t *)(base + kNoallocUnitOff);
+        // the workspace is rewritten only after the work already queued on every job's stream
+        if (int rc = order_streams(sims, n_sims, st, false)) return rc;
+        EA_HIP(hipMemcpyAsync(ls.d_descs, descs.data(), descs.size() * sizeof(JobDesc), hipMemcpyHostToDevice, st));
+        EA_HIP(hipMemcpyAsync(ls.d_units, order.data(), order.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+        // the queue counter must start at zero whatever an earlier call left there
+        EA_HIP(hipMemsetAsync(ls.d_queue, 0, sizeof(uint32_t), st));
+        if (int rc = launchset_launch(ls, st)) return rc;
+        const hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return fail(EA_EDEVICE, "batched sweep failed: %s", hipGetErrorString(e));
+    }
     for (int j = 0; j < n_sims; ++j) sims[j]->t += n_sweeps[j];
     return EA_OK;
 }
