@@ -96,8 +96,9 @@ typedef struct ea_options {
                             fewer makes the kernel stage word groups through HBM       */
     int split;           /* 0 = auto: a job with fewer ladders than CUs (CAMSC, <= 32
                             temperatures, even L) spreads each ladder's slot groups over 2
-                            or 4 co-resident workgroups when each keeps >= 2048 site-groups
-                            of work per sweep; 1 = never; 2 = whenever possible           */
+                            or 4 workgroups when each keeps >= 2048 site-groups of work
+                            per sweep; 1 = never; 2 = whenever possible.  Batches and
+                            plans apply the same rule to all their jobs together       */
     int rng;             /* flip-draw stream: EA_RNG_WORDS (default) or EA_RNG_PLANES
                             (CAMSC only); both give each flip the acceptance law
                             P(draw < threshold) = threshold / 2^32                      */
@@ -137,11 +138,13 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T,
  * swap_every > 0 and (t+1) % swap_every == 0 (Sec. 4.1); swap_every = 0 turns
  * PT off.  Asynchronous on the handle's stream when one was given, otherwise
  * synchronous.  EA_ESTATE if the total sweep count would reach 2^32.
- * A split job (ea_sim_info: split_parts > 1) launches cooperatively and its
- * workgroups wait for each other at swap points with a bounded wait; should a
- * wait ever time out, this call (or the next ea_observables / ea_state on an
- * asynchronous stream) returns EA_EDEVICE and the state is invalid until
- * ea_set_state. */
+ * A split job (ea_sim_info: split_parts > 1) runs 2 or 4 workgroups per
+ * ladder that wait for each other at swap points with a bounded wait (the
+ * launch needs only that many of its workgroups resident at once to make
+ * progress); should a wait ever time out (for instance when other work holds
+ * the device for about a second), this call (or the next ea_observables /
+ * ea_state on an asynchronous stream) returns EA_EDEVICE and the state is
+ * invalid until ea_set_state. */
 int ea_sweep(ea_sim *sim, int64_t n_sweeps, int swap_every);
 
 /* One launch over the ladders of several jobs of uneven size (Sec. 3.3 maps
@@ -180,14 +183,21 @@ int ea_sweep_batch_noalloc(ea_sim *const *sims, int n_sims, const int64_t *n_swe
  * in device memory, so every replay continues each job's random stream: the
  * results equal those of ea_sweep on each job alone.  The workgroup size is
  * opt->block_threads, or picked by timing candidates on scratch copies of the
- * jobs (results never depend on it).  A job belongs to at most one live plan
+ * jobs (results never depend on it).  When the jobs together have fewer
+ * ladders than the device has compute units and every job can be split (the
+ * conditions of ea_options.split, which each job's own setting can turn
+ * off), the step spreads each ladder over 2 or 4 workgroups; with autotune
+ * the split and unsplit shapes are timed against each other.  A job belongs to at most one live plan
  * (EA_EBUSY otherwise).  Each run is ordered after the work queued on the
  * jobs' own streams, and later work queued there is ordered after the run.
  * Destroying a job while a plan holds it makes ea_plan_run return EA_ESTATE. */
 typedef struct ea_plan ea_plan;
 typedef struct ea_plan_options {
     int block_threads;   /* 0 = autotune (or, with autotune = 0, the largest planned size) */
-    int autotune;        /* 1 = time 256/512/768/1024 threads on scratch copies, cache the best */
+    int autotune;        /* 1 = time 256/512/768/1024 threads, each unsplit and split where
+                            possible, on scratch copies; cache the best per device
+                            architecture and job shapes (also in the file named by
+                            the environment variable EA_TUNE_CACHE, if set)          */
     int use_graph;       /* 1 = replay a captured hipGraph (default); 0 = plain launches */
     int reserved_;
     void *stream;        /* hipStream_t; NULL = a stream owned by the plan, runs synchronous */
@@ -198,18 +208,28 @@ int ea_plan_create(ea_sim *const *sims, int n_sims, int sweeps_per_step, const i
                    const ea_plan_options *opt, ea_plan **out);
 /* Run n_steps >= 0 steps.  EA_ESTATE if a sweep counter would reach 2^32. */
 int ea_plan_run(ea_plan *plan, int64_t n_steps);
+/* Launch shape of a plan's step: workgroup size, workgroups launched, ladders
+ * (units), dynamic LDS bytes, whether a graph is replayed, and workgroups
+ * per ladder (1, or 2/4 for split ladders).  Any pointer may be NULL. */
 int ea_plan_info(const ea_plan *plan, int *block_threads, int *grid, int *n_units, size_t *lds_bytes,
-                 int *uses_graph);
+                 int *uses_graph, int *split_parts);
 void ea_plan_destroy(ea_plan *plan);
 
 /* ---- Serving: continuous batching of jobs on one GPU ----
- * Jobs are submitted with host inputs and wait in arrival order.  Each
- * ea_server_step admits waiting jobs (first fit in arrival order) while their
- * device footprint (ea_job_footprint) fits the budget, runs one launch over
- * every admitted job for min(quantum, sweeps any job has left) sweeps -
- * replaying a graph-captured plan while the job set is unchanged - and retires
- * finished jobs: energies and overlaps are measured, device state is freed.
- * A job's results are the same alone and in any mix. */
+ * Jobs are submitted with host inputs and wait.  Each ea_server_step
+ * (1) admits waiting jobs while their device footprint (ea_job_footprint)
+ * fits the budget: first fit in arrival order (EA_ADMIT_FIFO), or shortest
+ * remaining work first (sweeps x L^3 x n_T x R) until the running jobs hold
+ * fill_ladders ladders (EA_ADMIT_SHORTEST; a long job can wait behind a
+ * stream of shorter ones); the jobs are created while the previous step still
+ * runs on the GPU; (2) waits for that step and retires finished jobs:
+ * energies and overlaps are measured, device state is freed; (3) launches the
+ * next step over every running job, each for min(quantum, sweeps it has left)
+ * sweeps, replaying a graph-captured plan while the job set and sweep counts
+ * are unchanged, and returns without waiting for it.  A job's results are the
+ * same alone and in any mix. */
+#define EA_ADMIT_FIFO     0
+#define EA_ADMIT_SHORTEST 1
 #define EA_JOB_QUEUED    0
 #define EA_JOB_RUNNING   1
 #define EA_JOB_DONE      2
@@ -226,7 +246,10 @@ typedef struct ea_server_options {
     int keep_state;           /* keep each finished job's spins and permutation on the host       */
     int rng;                  /* EA_RNG_* flip-draw stream of every job (planes: CAMSC only); the
                                  jobs run without a field                                        */
-    void *stream;             /* hipStream_t; NULL = a stream owned by the server                 */
+    int policy;               /* EA_ADMIT_SHORTEST (default) or EA_ADMIT_FIFO                     */
+    int fill_ladders;         /* EA_ADMIT_SHORTEST: stop admitting once the running jobs hold this
+                                 many ladders (2 x realizations); 0 = 4 x the compute units      */
+    void *stream;             /* hipStream_t of the steps; NULL = a stream owned by the server    */
 } ea_server_options;
 
 void ea_default_server_options(ea_server_options *opt);
@@ -234,7 +257,8 @@ int ea_server_create(const ea_server_options *opt, ea_server **out);
 /* Queue a job (inputs as ea_create; copied).  EA_ENOMEM if it alone exceeds the budget. */
 int ea_server_submit(ea_server *sv, int L, const int8_t *couplings, const double *betas, int n_T,
                      int n_realizations, uint64_t seed, int64_t n_sweeps, int swap_every, int64_t *job_id);
-/* Admit, run one quantum, retire.  Synchronous.  Counts after the step. */
+/* Admit, finish the step in flight, retire, launch the next step.  Counts
+ * after the call: running jobs include those of the step just launched. */
 int ea_server_step(ea_server *sv, int *n_running, int *n_queued, int *n_finished);
 int ea_server_status(ea_server *sv, int64_t job_id, int *status, int64_t *sweeps_done);
 /* Results of a DONE job: energy int32 [R][2][n_T], overlap int32 [R][n_T] (as ea_observables). */

@@ -46,7 +46,8 @@ class PlanOptions(ctypes.Structure):
 class ServerOptions(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("quantum_sweeps", ctypes.c_int), ("layout", ctypes.c_int),
                 ("max_active", ctypes.c_int), ("autotune", ctypes.c_int), ("keep_state", ctypes.c_int),
-                ("rng", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("rng", ctypes.c_int), ("policy", ctypes.c_int), ("fill_ladders", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
 
 
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_CANCELLED, JOB_FAILED = 0, 1, 2, 3, 4
@@ -92,7 +93,7 @@ def lib():
             "ea_plan_create": (ctypes.c_int, [ctypes.POINTER(P), ctypes.c_int, ctypes.c_int, i32p,
                                               ctypes.POINTER(PlanOptions), ctypes.POINTER(P)]),
             "ea_plan_run": (ctypes.c_int, [P, ctypes.c_int64]),
-            "ea_plan_info": (ctypes.c_int, [P, i32p, i32p, i32p, ctypes.POINTER(ctypes.c_size_t), i32p]),
+            "ea_plan_info": (ctypes.c_int, [P, i32p, i32p, i32p, ctypes.POINTER(ctypes.c_size_t), i32p, i32p]),
             "ea_plan_destroy": (None, [P]),
             "ea_default_server_options": (None, [ctypes.POINTER(ServerOptions)]),
             "ea_server_create": (ctypes.c_int, [ctypes.POINTER(ServerOptions), ctypes.POINTER(P)]),
@@ -360,12 +361,12 @@ class Plan:
         check(lib().ea_plan_run(self._h, int(n_steps)))
 
     def info(self):
-        bt, grid, units, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        bt, grid, units, g, parts = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         lds = ctypes.c_size_t()
         check(lib().ea_plan_info(self._h, ctypes.byref(bt), ctypes.byref(grid), ctypes.byref(units),
-                                 ctypes.byref(lds), ctypes.byref(g)))
+                                 ctypes.byref(lds), ctypes.byref(g), ctypes.byref(parts)))
         return dict(block_threads=bt.value, grid=grid.value, units=units.value, lds_bytes=int(lds.value),
-                    uses_graph=bool(g.value))
+                    uses_graph=bool(g.value), split_parts=parts.value)
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
@@ -379,7 +380,7 @@ class Server:
     """Continuous-batching job server (see ea_server_* in include/ea.h)."""
 
     def __init__(self, hbm_budget_bytes=0, quantum_sweeps=200, layout="camsc", max_active=0, autotune=False,
-                 keep_state=False, rng="words"):
+                 keep_state=False, rng="words", policy="shortest", fill_ladders=0):
         opt = ServerOptions()
         lib().ea_default_server_options(ctypes.byref(opt))
         opt.hbm_budget_bytes = int(hbm_budget_bytes)
@@ -389,6 +390,8 @@ class Server:
         opt.autotune = int(bool(autotune))
         opt.keep_state = int(bool(keep_state))
         opt.rng = RNGS[rng] if isinstance(rng, str) else int(rng)
+        opt.policy = {"fifo": 0, "shortest": 1}[policy] if isinstance(policy, str) else int(policy)
+        opt.fill_ladders = int(fill_ladders)
         self._h = ctypes.c_void_p()
         self.shapes = {}
         check(lib().ea_server_create(ctypes.byref(opt), ctypes.byref(self._h)))

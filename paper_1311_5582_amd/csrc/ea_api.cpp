@@ -232,7 +232,7 @@ int device_grid(int kv, int bt, size_t lds, int n_units, int *grid)
     EA_HIP(hipGetDevice(&dev));
     int cus = 0;
     EA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    int per_cu = sweep_max_blocks_per_cu(kv, bt, lds);
+    int per_cu = sweep_max_blocks_per_cu(kv, 1, bt, lds);
     if (per_cu < 1) return fail(EA_EDEVICE, "sweep kernel cannot be resident with %d threads and %zu B LDS", bt, lds);
     *grid = std::max(1, std::min(n_units, cus * per_cu));
     return EA_OK;
@@ -282,39 +282,51 @@ size_t job_footprint_bytes(int L, int n_T, int R, int layout, int64_t swap_entri
     const size_t N = (size_t)L * L * L, ladders = 2 * (size_t)R;
     const size_t NW = (size_t)(n_T + slots_per_word(layout) - 1) / slots_per_word(layout);
     return a(ladders * NW * N * 4) + a((size_t)R * N) + a(ladders * kMaxTemps * 4) + a((size_t)n_T * kThrCols * 4) +
-           a((size_t)swap_entries * 4) + 3 * a(kMaxTemps * 4) + a(N * 4) + a(2 * 4) + a(ladders * kMaxTemps * 8) +
+           a((size_t)swap_entries * 4) + 3 * a(kMaxTemps * 4) + a(N * 4) + a(kCounterWords * 4) + a(ladders * kMaxTemps * 8) +
            a(ladders * 4) + a(sizeof(JobDesc)) + a(ladders * 2 * kMaxTemps * 8) + a(4) +
            a((size_t)R * n_T * (4 + L) * 8) + a((size_t)R * n_T * 5 * 4);
 }
 
-// Workgroups per ladder for a lone launch: split a ladder's slot groups over
-// 2 or 4 co-resident workgroups when the job alone leaves CUs idle.
-static int choose_split(const ea_sim *s, int split_opt)
+int choose_split_parts(const JobDesc *descs, int n, int bt, size_t lds, int kv, int split_opt)
 {
-    if (split_opt == 1 || s->layout != EA_LAYOUT_CAMSC || s->NW != 1 || (s->L & 1)) return 1;
-    const int ladders = 2 * s->R;
-    const int ngr = (s->n_T + 3) >> 2;
-    const int per_lane = 6 * ((s->N / 2 + s->block_threads - 1) / s->block_threads);
-    if (per_lane > 255) return 1;   // class energy sums must fit 8 bit planes
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess) return 1;
-    int coop = 0;
-    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, s->device) != hipSuccess || !coop) return 1;
+    if (split_opt == 1 || n < 1 || (kv != 0 && kv != 2)) return 1;   // CAMSC word or plane draws only
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
+    int64_t ladders = 0;
+    for (int j = 0; j < n; ++j) {
+        const JobDesc &d = descs[j];
+        if (d.NW != 1 || (d.L & 1)) return 1;
+        const int per_lane = 6 * ((d.N / 2 + bt - 1) / bt);
+        if (per_lane > 255) return 1;   // class energy sums must fit 8 bit planes
+        ladders += d.ladders;
+    }
     for (int parts : {4, 2}) {
-        if (ngr % parts != 0 || ladders * parts > cus) continue;
         // never more workgroups than CUs (measured: 4 parts x 512 threads, two per CU, is
         // slower than 2 parts x 1024); a small lattice is latency-bound: the exchange
         // costs more than the split saves unless each part keeps enough work (measured
         // with PT every sweep: 4 parts pay off from 1024 site-groups per part, 2 parts
         // from 2048)
-        if (split_opt == 0 && (int64_t)s->N * (ngr / parts) < 4096 / parts) continue;
-        const int blocks = (ladders + 7) / 8 * 8 * parts;
-        const int per_cu = sweep_split_max_blocks_per_cu(parts, kernel_variant(s->layout, s->h.rng),
-                                                         s->block_threads, s->lds);
-        if (per_cu < 1 || (int64_t)per_cu * cus < blocks) continue;
+        if (ladders * parts > cus) continue;
+        bool ok = true;
+        for (int j = 0; j < n && ok; ++j) {
+            const int ngr = (descs[j].n_T + 3) >> 2;
+            if (ngr % parts != 0) ok = false;
+            if (split_opt == 0 && (int64_t)descs[j].N * (ngr / parts) < 4096 / parts) ok = false;
+        }
+        if (!ok) continue;
+        // every workgroup resident at once: each queue's parts meet without waiting for a slot
+        const int per_cu = sweep_max_blocks_per_cu(kv, parts, bt, lds);
+        if (per_cu < 1 || (int64_t)per_cu * cus < split_grid((int)ladders, parts)) continue;
         return parts;
     }
     return 1;
+}
+
+// Workgroups per ladder for a lone launch of the job.
+static int choose_split(const ea_sim *s, int split_opt)
+{
+    return choose_split_parts(&s->h, 1, s->block_threads, s->lds, kernel_variant(s->layout, s->h.rng), split_opt);
 }
 
 int order_streams(ea_sim *const *sims, int n_sims, hipStream_t st, bool after)
@@ -335,7 +347,7 @@ int order_streams(ea_sim *const *sims, int n_sims, hipStream_t st, bool after)
 
 int check_split_error(ea_sim *s)
 {
-    if (s->split_parts <= 1) return EA_OK;
+    if (!s->ever_split) return EA_OK;
     uint32_t err = 0;
     EA_HIP(hipMemcpyAsync(&err, s->h.error, sizeof err, hipMemcpyDeviceToHost, s->stream));
     EA_HIP(hipStreamSynchronize(s->stream));
@@ -486,7 +498,7 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
         (rc = upload(s, slen, &dlen)) || (rc = upload(s, ssgn, &dsgn)) || (rc = upload(s, sites, &dsites)))
         return bail(rc);
     h.flip_thr = dft; h.swap_thr = dst; h.swap_off = doff; h.swap_len = dlen; h.swap_sgn = dsgn; h.sites = dsites;
-    std::vector<uint32_t> counters(2, 0u);
+    std::vector<uint32_t> counters(kCounterWords, 0u);   // sweep counter, then the launch's queue words
     if ((rc = upload(s, counters, &s->d_counters))) return bail(rc);
     h.sweep_ctr = s->d_counters;
     std::vector<uint64_t> acc((size_t)ladders * kMaxTemps, 0u);
@@ -521,6 +533,7 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
     s->swap_total = (int64_t)sthr.size();
     plan_optional_lds(N, wr, bt, L % 2 != 0, s->swap_total, &h.swap_lds, &h.sites_lds);
     s->lds = lds_layout(N, wr, h.swap_lds, h.sites_lds).total;
+    s->split_opt = opt.split;
     s->split_parts = choose_split(s, opt.split);
     std::vector<JobDesc> hv(1, h);
     if ((rc = upload(s, hv, &s->d_job))) return bail(rc);

@@ -45,6 +45,12 @@ int build_swap_tables(const double *betas, int n_T, int N, int m, std::vector<ui
                       std::vector<int32_t> *slen, std::vector<int32_t> *ssgn, int64_t *total);
 size_t job_footprint_bytes(int L, int n_T, int R, int layout, int64_t swap_entries);
 int device_grid(int kv, int bt, size_t lds, int n_units, int *grid);   // kv: kernel_variant()
+// Workgroups per ladder (1, 2 or 4) for one launch over the jobs descs[0..n)
+// with workgroups of bt threads and lds bytes: 2 or 4 when every job can be
+// split and the launch alone would leave compute units idle.  split_opt as in
+// ea_options (1 = never, 2 = whenever possible, 0 = when each part keeps
+// enough work).
+int choose_split_parts(const JobDesc *descs, int n, int bt, size_t lds, int kv, int split_opt);
 
 }  // namespace ea
 
@@ -62,11 +68,13 @@ struct ea_sim {
     ea::JobDesc h{};                  // host copy of the descriptor
     ea::JobDesc *d_job = nullptr;
     uint32_t *d_units = nullptr;      // ladders of this job for a lone launch
-    uint32_t *d_counters = nullptr;   // [0] sweep counter, [1] work queue
+    uint32_t *d_counters = nullptr;   // [0] sweep counter, [1..8] queue words of a lone launch
     int64_t swap_total = 0;           // entries in the swap tables
     size_t lds = 0;                   // dynamic LDS bytes of this job's sweep workgroups
     size_t footprint = 0;             // device bytes owned by this job
     int split_parts = 1;              // workgroups per ladder in a lone launch (1, 2 or 4)
+    int split_opt = 0;                // ea_options.split: 0 auto, 1 never, 2 whenever possible
+    bool ever_split = false;          // a split launch has run this job: its exchange may have timed out
     int64_t *d_meas = nullptr;        // measurement sums: count, q^2 [R][n_T], q^4 [R][n_T][2], C [R][n_T][L]
     int32_t *d_obs = nullptr;         // observables outputs: energy, overlap, magnetization
     hipEvent_t ev = nullptr;          // orders launches on other streams (batches, plans) with this job's stream
@@ -80,4 +88,7 @@ int check_split_error(ea_sim *s);
 int order_streams(ea_sim *const *sims, int n_sims, hipStream_t st, bool after);
 // A job held by a live plan is being destroyed: the plan drops it and refuses to run.
 void plan_forget_job(ea_plan *p, ea_sim *s);
+// ea_plan_create with its own sweep count per job and step (sweeps[j] >= 0).
+int plan_create(ea_sim *const *sims, int n_sims, const int *sweeps, const int *swap_every,
+                const ea_plan_options *opt, ea_plan **out);
 }

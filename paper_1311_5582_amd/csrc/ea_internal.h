@@ -24,6 +24,8 @@ constexpr int kMaxTemps = 64;
 constexpr int kThrCols = 16;          // threshold row: column 2E+S, E in 0..6, S in 0..1
 constexpr int kMaxBlock = 1024;
 constexpr int kMaxWaves = kMaxBlock / 64;
+constexpr int kQueueWords = 8;        // work-queue counters of a launch (one per XCD for split ladders)
+constexpr int kCounterWords = 16;     // a job's device counters: [0] sweeps done, [1..8] its lone launch's queues
 
 // Layout parameters: slots per 32-bit word and the bit stride between slots.
 template <int LAYOUT> struct Layout;
@@ -138,22 +140,24 @@ inline int kernel_variant(int layout, int rng)
 {
     return layout == 0 ? (rng ? 2 : 0) : (layout == 1 ? 1 : (layout == 2 ? 3 : 4));
 }
+// One sweep launch over n_units ladders (units[k] = job << 20 | ladder), then
+// the sweep counters advance and the queue words are re-armed.  parts = 1:
+// persistent workgroups pull ladders from queue[0]; parts = 2 or 4 (CAMSC
+// jobs with one word per site and even L): `parts` workgroups per ladder,
+// tickets from queue[blockIdx % 8], grid = split_grid(n_units, parts).
 hipError_t launch_sweep(const JobDesc *d_jobs, int n_jobs, const uint32_t *d_units, int n_units,
-                        uint32_t *d_queue, int kv, int block_threads, size_t lds, int grid,
+                        uint32_t *d_queue, int kv, int parts, int block_threads, size_t lds, int grid,
                         hipStream_t s);
-// Split launch: `parts` co-resident workgroups per ladder (cooperative launch).
-hipError_t launch_sweep_split(const JobDesc *d_job, int ladders, int parts, int kv, int block_threads, size_t lds,
-                              uint32_t *d_queue, hipStream_t s);
-int sweep_split_max_blocks_per_cu(int parts, int kv, int block_threads, size_t lds);
-
+// Workgroups of a split launch: every queue gets as many as its ladders have parts.
+inline int split_grid(int n_units, int parts) { return (n_units + 7) / 8 * 8 * parts; }
 hipError_t launch_observables(const JobDesc *d_job, const JobDesc &h_job, int layout, int32_t *d_energy,
                               int32_t *d_overlap, int32_t *d_magnet, hipStream_t s);
 hipError_t launch_unpack(const JobDesc *d_job, const JobDesc &h_job, int layout, int8_t *d_spins, hipStream_t s);
 hipError_t launch_measure(const JobDesc *d_job, const JobDesc &h_job, int layout, int64_t *count, int64_t *sum_q2,
                           uint64_t *sum_q4, int64_t *sum_c, hipStream_t s);
 hipError_t launch_pack(const JobDesc *d_job, const JobDesc &h_job, int layout, const int8_t *d_spins, hipStream_t s);
-hipError_t sweep_set_lds(int kv, size_t lds);
-int sweep_max_blocks_per_cu(int kv, int block_threads, size_t lds);
+hipError_t sweep_set_lds(int kv, int parts, size_t lds);
+int sweep_max_blocks_per_cu(int kv, int parts, int block_threads, size_t lds);
 
 // Static workspace of the allocation-free batch launch (ea_sweep_batch_noalloc):
 // work-queue counter, job descriptors and unit list of one launch, at fixed

@@ -934,14 +934,18 @@ __device__ __forceinline__ void count_up_word(const uint32_t *words, int N, int 
 // Sweep kernel.
 //
 // PARTS = 1: persistent workgroups pulling ladders from a queue.
-// PARTS > 1 (one job, CAMSC, one word per site, even L; cooperative launch so
-// that all workgroups are resident): PARTS workgroups share a ladder, each
-// holding all of its words in LDS but deciding only its own slot groups.  At a
-// swap point they publish their slots' energies through a double-buffered
-// exchange in HBM (64-bit words tagged with the sweep index, so readers need
-// no fence; the wait is bounded and a timeout is reported through an error
-// flag, so a launch always ends), then all run the identical swap pass.  Partners are placed on one XCD
-// (equal blockIdx mod 8) so that the flags stay in one L2.
+// PARTS > 1 (CAMSC, one word per site, even L): PARTS workgroups share a
+// ladder, each holding all of its words in LDS but deciding only its own slot
+// groups.  At a swap point they publish their slots' energies through a
+// double-buffered exchange in HBM (64-bit words tagged with the sweep index,
+// so readers need no fence; the wait is bounded and a timeout is reported
+// through an error flag, so a launch always ends), then all run the identical
+// swap pass.  Workgroups take tickets from one of eight queues, queue
+// blockIdx mod 8 (the XCD the workgroup runs on), and the PARTS consecutive
+// tickets of a queue are the parts of one ladder, so partners share an L2.
+// Tickets go to workgroups in the order they start: only the most recently
+// opened ladder of a queue can lack a part, so the launch needs no
+// co-residency guarantee to make progress, only PARTS workgroups per queue.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kSpinLimit = 1u << 20;   // polls of a partner's flag before giving up
 
@@ -966,16 +970,19 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
     const int wave = tid >> 6;
     const int nwaves = nthr >> 6;
 
-    for (int iter = 0;; ++iter) {
+    for (;;) {
         uint32_t unit;
         int part = 0;
         if (SPLIT) {
-            if (iter > 0) break;
-            const int b = blockIdx.x;
-            part = (b >> 3) % PARTS;
-            const int ladder_b = (b / (8 * PARTS)) * 8 + (b & 7);
-            if (ladder_b >= n_units) break;   // padding block (its partners pad too)
-            unit = (uint32_t)ladder_b;
+            const uint32_t xq = blockIdx.x & 7u;
+            if (tid == 0) s_next = atomicAdd(queue + xq, 1u);
+            __syncthreads();
+            const uint32_t tk = __builtin_amdgcn_readfirstlane(s_next);
+            __syncthreads();
+            part = (int)(tk % (uint32_t)PARTS);
+            const uint32_t li = (tk / (uint32_t)PARTS) * 8u + xq;   // this queue's (tk / PARTS)-th ladder
+            if (li >= (uint32_t)n_units) break;   // its partners' tickets are past the end too
+            unit = units[li];
         } else {
             if (tid == 0) s_next = atomicAdd(queue, 1u);
             __syncthreads();
@@ -1435,12 +1442,12 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
     }
 }
 
-// Advance each job's sweep counter and re-arm the queue for the next launch.
+// Advance each job's sweep counter and re-arm the queues for the next launch.
 __global__ void advance_kernel(const JobDesc *__restrict__ jobs, int n_jobs, uint32_t *queue)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j < n_jobs) *jobs[j].sweep_ctr += (uint32_t)jobs[j].n_sweeps;
-    if (j == 0) *queue = 0;
+    if (j < kQueueWords) queue[j] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1680,13 +1687,14 @@ static const void *sweep_fn(int kv, int parts)
                       : (parts == 2 ? (const void *)sweep_kernel<0, 2, 0> : (const void *)sweep_kernel<0, 1, 0>);
 }
 
-hipError_t sweep_set_lds(int kv, size_t lds)
+hipError_t sweep_set_lds(int kv, int parts, size_t lds)
 {
     // the attribute is process-wide per kernel; raise it only when a launch needs more
-    static std::atomic<size_t> set_max[5] = {{0}, {0}, {0}, {0}, {0}};
-    std::atomic<size_t> &cur = set_max[kv];
+    static std::atomic<size_t> set_max[5][3] = {};
+    const int pi = parts == 4 ? 2 : (parts == 2 ? 1 : 0);
+    std::atomic<size_t> &cur = set_max[kv][pi];
     if (lds <= cur.load()) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute(sweep_fn(kv, 1), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute(sweep_fn(kv, parts), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e == hipSuccess) {
         size_t prev = cur.load();
         while (prev < lds && !cur.compare_exchange_weak(prev, lds)) {
@@ -1696,35 +1704,19 @@ hipError_t sweep_set_lds(int kv, size_t lds)
 }
 
 hipError_t launch_sweep(const JobDesc *d_jobs, int n_jobs, const uint32_t *d_units, int n_units, uint32_t *d_queue,
-                        int kv, int block_threads, size_t lds, int grid, hipStream_t s)
+                        int kv, int parts, int block_threads, size_t lds, int grid, hipStream_t s)
 {
-    hipError_t e = sweep_set_lds(kv, lds);
+    hipError_t e = sweep_set_lds(kv, parts, lds);
     if (e != hipSuccess) return e;
     void *args[] = {(void *)&d_jobs, (void *)&d_units, (void *)&n_units, (void *)&d_queue};
-    e = hipLaunchKernel(sweep_fn(kv, 1), dim3(grid), dim3(block_threads), args, lds, s);
+    e = hipLaunchKernel(sweep_fn(kv, parts), dim3(grid), dim3(block_threads), args, lds, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(advance_kernel, dim3((n_jobs + 255) / 256), dim3(256), 0, s, d_jobs, n_jobs, d_queue);
+    const int adv = n_jobs > kQueueWords ? n_jobs : kQueueWords;
+    hipLaunchKernelGGL(advance_kernel, dim3((adv + 255) / 256), dim3(256), 0, s, d_jobs, n_jobs, d_queue);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_split(const JobDesc *d_job, int ladders, int parts, int kv, int block_threads, size_t lds,
-                              uint32_t *d_queue, hipStream_t s)
-{
-    const void *fn = sweep_fn(kv, parts);
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    // partners share blockIdx mod 8: ladder l, part p -> block (l / 8) * 8 * parts + p * 8 + l % 8
-    const int grid = (ladders + 7) / 8 * 8 * parts;
-    const uint32_t *no_units = nullptr;
-    int n_units = ladders;
-    void *args[] = {(void *)&d_job, (void *)&no_units, (void *)&n_units, (void *)&d_queue};
-    e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(block_threads), args, (unsigned)lds, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, d_job, 1, d_queue);
-    return hipGetLastError();
-}
-
-int sweep_split_max_blocks_per_cu(int parts, int kv, int block_threads, size_t lds)
+int sweep_max_blocks_per_cu(int kv, int parts, int block_threads, size_t lds)
 {
     int n = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_fn(kv, parts), block_threads, lds);
@@ -1781,11 +1773,5 @@ hipError_t launch_pack(const JobDesc *d_job, const JobDesc &h, int layout, const
     return hipGetLastError();
 }
 
-int sweep_max_blocks_per_cu(int kv, int block_threads, size_t lds)
-{
-    int n = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_fn(kv, 1), block_threads, lds);
-    return e == hipSuccess ? n : 0;
-}
 
 }  // namespace ea

@@ -1,14 +1,17 @@
 // Serving loop: continuous batching of simulation jobs on one GPU.
 //
-// Jobs are submitted with host inputs and wait in arrival order.  Each step
-// (1) admits waiting jobs, first fit in arrival order, while their exact HBM
-// footprint fits the budget, (2) runs one launch over every admitted job for a
-// quantum of sweeps (replaying a graph-captured plan while the job set is
-// unchanged), and (3) retires finished jobs: their energies and overlaps are
-// measured, their device state is released, and the memory admits the next
-// jobs.  Results are a pure function of each job's inputs (counter-based
-// stream, device-resident sweep counters), so a job's result is the same alone
-// and in any mix.
+// Jobs are submitted with host inputs and wait.  Each step (1) admits waiting
+// jobs while their exact HBM footprint fits the budget - first fit in arrival
+// order, or shortest remaining work first until the running jobs hold enough
+// ladders to fill the device - creating them on an admission stream while the
+// previous step still runs on the GPU, (2) waits for that step and retires
+// finished jobs (energies and overlaps measured, device state released, which
+// admits the next jobs), and (3) launches the next step over every running
+// job, each for min(quantum, sweeps it has left) sweeps, replaying a
+// graph-captured plan while the job set and sweep counts are unchanged.
+// Results are a pure function of each job's inputs (counter-based stream,
+// device-resident sweep counters), so a job's result is the same alone and in
+// any mix.
 #include <algorithm>
 #include <cstring>
 #include <deque>
@@ -44,16 +47,23 @@ struct Job {
 struct ea_server {
     ea_server_options opt{};
     int device = 0;
-    hipStream_t stream = nullptr;
+    int fill_ladders = 0;             // shortest-first admission stops once the running jobs hold this many
+    hipStream_t stream = nullptr;     // steps
+    hipStream_t admit = nullptr;      // job creation, measurement and readout
     size_t used = 0;
     int64_t next_id = 1;
     std::map<int64_t, std::unique_ptr<Job>> jobs;
     std::deque<int64_t> queue;        // waiting, arrival order
     std::vector<int64_t> active;      // admitted, running
+    int64_t active_ladders = 0;
     // plan cache: valid while the active set and the per-job sweep counts are unchanged
     ea_plan *plan = nullptr;
     std::vector<int64_t> plan_ids;
-    int plan_sweeps = 0;
+    std::vector<int> plan_sweeps;
+    // the step launched by the last ea_server_step, not yet waited for
+    bool in_flight = false;
+    std::vector<int64_t> flight_ids;
+    std::vector<int> flight_sweeps;
     int64_t steps = 0, launches_replayed = 0, plans_built = 0;
 };
 
@@ -62,7 +72,26 @@ static void drop_plan(ea_server *sv)
     if (sv->plan) ea_plan_destroy(sv->plan);
     sv->plan = nullptr;
     sv->plan_ids.clear();
-    sv->plan_sweeps = 0;
+    sv->plan_sweeps.clear();
+}
+
+// Wait for the step in flight and credit its sweeps.
+static int finish_step(ea_server *sv)
+{
+    if (!sv->in_flight) return EA_OK;
+    sv->in_flight = false;
+    EA_HIP(hipStreamSynchronize(sv->stream));
+    for (size_t k = 0; k < sv->flight_ids.size(); ++k) {
+        auto it = sv->jobs.find(sv->flight_ids[k]);
+        if (it != sv->jobs.end()) it->second->done += sv->flight_sweeps[k];
+    }
+    ++sv->steps;
+    return EA_OK;
+}
+
+static int64_t remaining_work(const Job *j)
+{
+    return (j->n_sweeps - j->done) * (int64_t)j->L * j->L * j->L * j->n_T * j->R;
 }
 
 static void release_job_device(ea_server *sv, Job *j)
@@ -71,6 +100,7 @@ static void release_job_device(ea_server *sv, Job *j)
         ea_destroy(j->sim);
         j->sim = nullptr;
         sv->used -= j->footprint;
+        sv->active_ladders -= 2 * (int64_t)j->R;
     }
 }
 
@@ -83,6 +113,8 @@ void ea_default_server_options(ea_server_options *opt)
     opt->quantum_sweeps = 200;
     opt->layout = EA_LAYOUT_CAMSC;
     opt->autotune = 0;   // the job mix changes at every arrival; tuning each mix would cost more than it saves
+    opt->policy = EA_ADMIT_SHORTEST;
+    opt->fill_ladders = 0;
 }
 
 int ea_server_create(const ea_server_options *opt_in, ea_server **out)
@@ -98,6 +130,8 @@ int ea_server_create(const ea_server_options *opt_in, ea_server **out)
     if (opt.rng == EA_RNG_PLANES && opt.layout != EA_LAYOUT_CAMSC)
         return fail(EA_EINVAL, "plane draws need the CAMSC layout");
     if (opt.max_active < 0 || opt.max_active > 4095) return fail(EA_EINVAL, "max_active outside [0, 4095]");
+    if (opt.policy != EA_ADMIT_FIFO && opt.policy != EA_ADMIT_SHORTEST) return fail(EA_EINVAL, "unknown policy");
+    if (opt.fill_ladders < 0) return fail(EA_EINVAL, "fill_ladders < 0");
     ea_server *sv = new (std::nothrow) ea_server;
     if (!sv) return fail(EA_ENOMEM, "host allocation failed");
     sv->opt = opt;
@@ -108,8 +142,14 @@ int ea_server_create(const ea_server_options *opt_in, ea_server **out)
         e = hipMemGetInfo(&free_b, &total_b);
         sv->opt.hbm_budget_bytes = free_b / 10 * 8;
     }
+    int cus = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, sv->device);
+    sv->fill_ladders = opt.fill_ladders > 0 ? opt.fill_ladders : 4 * cus;
     if (e == hipSuccess && opt.stream == nullptr) e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->admit, hipStreamNonBlocking);
     if (e != hipSuccess) {
+        if (sv->admit) (void)hipStreamDestroy(sv->admit);
+        if (opt.stream == nullptr && sv->stream) (void)hipStreamDestroy(sv->stream);
         delete sv;
         return fail(EA_EDEVICE, "server set-up failed: %s", hipGetErrorString(e));
     }
@@ -151,85 +191,84 @@ int ea_server_step(ea_server *sv, int *n_running, int *n_queued, int *n_finished
     if (!sv) return fail(EA_EINVAL, "ea_server_step: NULL server");
     EA_HIP(hipSetDevice(sv->device));
     int finished = 0;
-    // 1. admission: first fit in arrival order
-    for (auto it = sv->queue.begin(); it != sv->queue.end();) {
-        Job *j = sv->jobs[*it].get();
+    // 1. admission, on the host and the admission stream while the step in flight runs
+    std::vector<int64_t> order(sv->queue.begin(), sv->queue.end());
+    if (sv->opt.policy == EA_ADMIT_SHORTEST)
+        std::stable_sort(order.begin(), order.end(), [sv](int64_t a, int64_t b) {
+            return remaining_work(sv->jobs[a].get()) < remaining_work(sv->jobs[b].get());
+        });
+    for (int64_t id : order) {
+        Job *j = sv->jobs[id].get();
         if ((int)sv->active.size() >= sv->opt.max_active) break;
-        if (sv->used + j->footprint > sv->opt.hbm_budget_bytes) {
-            ++it;
-            continue;
-        }
+        if (sv->opt.policy == EA_ADMIT_SHORTEST && !sv->active.empty() && sv->active_ladders >= sv->fill_ladders)
+            break;
+        if (sv->used + j->footprint > sv->opt.hbm_budget_bytes) continue;
         ea_options o;
         ea_default_options(&o);
         o.layout = sv->opt.layout;
         o.rng = sv->opt.rng;
-        o.stream = sv->stream;
+        o.stream = sv->admit;
+        sv->queue.erase(std::find(sv->queue.begin(), sv->queue.end(), id));
         const int rc = ea_create(j->L, j->J.data(), j->betas.data(), j->n_T, j->R, j->seed, &o, &j->sim);
         if (rc != EA_OK) {
             j->status = EA_JOB_FAILED;
             j->error = ea_last_error();
-            it = sv->queue.erase(it);
             ++finished;
             continue;
         }
         sv->used += j->footprint;
+        sv->active_ladders += 2 * (int64_t)j->R;
         j->status = EA_JOB_RUNNING;
         j->J.clear();
         j->J.shrink_to_fit();
-        sv->active.push_back(j->id);
-        it = sv->queue.erase(it);
+        sv->active.push_back(id);
     }
-    // jobs with nothing left to run finish without a launch
-    auto retire_done = [&](void) -> int {
-        std::vector<int64_t> still;
-        for (int64_t id : sv->active) {
-            Job *j = sv->jobs[id].get();
-            if (j->done < j->n_sweeps) {
-                still.push_back(id);
-                continue;
-            }
-            j->energy.assign((size_t)j->R * 2 * j->n_T, 0);
-            j->overlap.assign((size_t)j->R * j->n_T, 0);
-            int rc = ea_observables(j->sim, j->energy.data(), j->overlap.data());
-            if (rc == EA_OK && sv->opt.keep_state) {
-                j->spins.assign((size_t)j->R * 2 * j->n_T * j->L * j->L * j->L, 0);
-                j->perm.assign((size_t)j->R * 2 * j->n_T, 0);
-                rc = ea_state(j->sim, j->spins.data(), j->perm.data(), nullptr);
-            }
-            if (rc != EA_OK) {
-                j->status = EA_JOB_FAILED;
-                j->error = ea_last_error();
-            } else {
-                j->status = EA_JOB_DONE;
-            }
-            drop_plan(sv);   // the cached plan references this job's buffers
-            release_job_device(sv, j);
-            ++finished;
+    // 2. wait for the step in flight, retire finished jobs
+    if (int rc = finish_step(sv)) return rc;
+    std::vector<int64_t> still;
+    for (int64_t id : sv->active) {
+        Job *j = sv->jobs[id].get();
+        if (j->done < j->n_sweeps) {
+            still.push_back(id);
+            continue;
         }
-        sv->active.swap(still);
-        return EA_OK;
-    };
-    retire_done();
-    // 2. one launch over every running job: the quantum never exceeds what any job has left
+        j->energy.assign((size_t)j->R * 2 * j->n_T, 0);
+        j->overlap.assign((size_t)j->R * j->n_T, 0);
+        int rc = ea_observables(j->sim, j->energy.data(), j->overlap.data());
+        if (rc == EA_OK && sv->opt.keep_state) {
+            j->spins.assign((size_t)j->R * 2 * j->n_T * j->L * j->L * j->L, 0);
+            j->perm.assign((size_t)j->R * 2 * j->n_T, 0);
+            rc = ea_state(j->sim, j->spins.data(), j->perm.data(), nullptr);
+        }
+        if (rc != EA_OK) {
+            j->status = EA_JOB_FAILED;
+            j->error = ea_last_error();
+        } else {
+            j->status = EA_JOB_DONE;
+        }
+        drop_plan(sv);   // the cached plan references this job's buffers
+        release_job_device(sv, j);
+        ++finished;
+    }
+    sv->active.swap(still);
+    // 3. launch the next step over every running job (not waited for here)
     if (!sv->active.empty()) {
-        int q = sv->opt.quantum_sweeps;
+        std::vector<int> q;
+        std::vector<ea_sim *> sims;
+        std::vector<int> se;
         for (int64_t id : sv->active) {
             const Job *j = sv->jobs[id].get();
-            q = (int)std::min<int64_t>(q, j->n_sweeps - j->done);
+            q.push_back((int)std::min<int64_t>(sv->opt.quantum_sweeps, j->n_sweeps - j->done));
+            sims.push_back(j->sim);
+            se.push_back(j->swap_every);
         }
         if (sv->plan == nullptr || sv->plan_ids != sv->active || sv->plan_sweeps != q) {
             drop_plan(sv);
-            std::vector<ea_sim *> sims;
-            std::vector<int> se;
-            for (int64_t id : sv->active) {
-                sims.push_back(sv->jobs[id]->sim);
-                se.push_back(sv->jobs[id]->swap_every);
-            }
             ea_plan_options po;
             ea_default_plan_options(&po);
             po.autotune = sv->opt.autotune;
             po.stream = sv->stream;
-            if (int rc = ea_plan_create(sims.data(), (int)sims.size(), q, se.data(), &po, &sv->plan)) return rc;
+            if (int rc = plan_create(sims.data(), (int)sims.size(), q.data(), se.data(), &po, &sv->plan)) return rc;
             sv->plan_ids = sv->active;
             sv->plan_sweeps = q;
             ++sv->plans_built;
@@ -237,11 +276,9 @@ int ea_server_step(ea_server *sv, int *n_running, int *n_queued, int *n_finished
             ++sv->launches_replayed;
         }
         if (int rc = ea_plan_run(sv->plan, 1)) return rc;
-        EA_HIP(hipStreamSynchronize(sv->stream));
-        for (int64_t id : sv->active) sv->jobs[id]->done += q;
-        ++sv->steps;
-        // 3. retire finished jobs
-        retire_done();
+        sv->in_flight = true;
+        sv->flight_ids = sv->active;
+        sv->flight_sweeps = q;
     }
     if (n_running) *n_running = (int)sv->active.size();
     if (n_queued) *n_queued = (int)sv->queue.size();
@@ -292,8 +329,8 @@ int ea_server_cancel(ea_server *sv, int64_t id)
     if (j->status == EA_JOB_QUEUED) {
         sv->queue.erase(std::find(sv->queue.begin(), sv->queue.end(), id));
     } else if (j->status == EA_JOB_RUNNING) {
+        if (int rc = finish_step(sv)) return rc;
         drop_plan(sv);
-        EA_HIP(hipStreamSynchronize(sv->stream));
         release_job_device(sv, j);
         sv->active.erase(std::find(sv->active.begin(), sv->active.end(), id));
     } else {
@@ -330,10 +367,12 @@ void ea_server_destroy(ea_server *sv)
 {
     if (!sv) return;
     (void)hipSetDevice(sv->device);
+    (void)finish_step(sv);
     drop_plan(sv);
     (void)hipStreamSynchronize(sv->stream);
     for (auto &kv : sv->jobs) release_job_device(sv, kv.second.get());
     if (sv->opt.stream == nullptr) (void)hipStreamDestroy(sv->stream);
+    (void)hipStreamDestroy(sv->admit);
     delete sv;
 }
 

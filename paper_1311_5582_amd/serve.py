@@ -49,5 +49,6 @@ def run_trace(trace, server, realize=None, idle_sleep_s=0.0005, on_done=None):
 def latency_summary(records):
     lat = np.array([r["latency_s"] for r in records.values()])
     flips = sum(r["job"]["sweeps"] * r["job"]["L"] ** 3 * r["job"]["n_T"] * r["job"]["R"] * 2 for r in records.values())
+    done_last = max(r["done_s"] for r in records.values())
     return dict(jobs=len(lat), p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
-                mean_s=float(lat.mean()), max_s=float(lat.max()), flips=float(flips))
+                mean_s=float(lat.mean()), max_s=float(lat.max()), flips=float(flips), done_last_s=float(done_last))

@@ -89,7 +89,52 @@ def _trace(n, seed=9):
     return out
 
 
-def test_server_results_alone_equal_mix(oracle_lib):
+@pytest.mark.parametrize("autotune", [False, True])
+def test_split_plan_and_batch_equal_alone(oracle_lib, autotune):
+    """Jobs that together hold fewer ladders than the device has compute
+    units run with split ladders in a graph-captured plan and in a batch; every
+    replay equals the same jobs run one at a time without splitting, and one
+    realization of each job equals the oracle."""
+    jobs = [(16, 8, 32, 61, 1), (12, 6, 16, 62, 3), (16, 4, 24, 63, 0)]   # L, R, n_T, seed, swap_every
+    sims = [_make(L, R, n_T, seed) for L, R, n_T, seed, _ in jobs]
+    bats = [_make(L, R, n_T, seed) for L, R, n_T, seed, _ in jobs]
+    refs = [B.Sim(L, inputs.couplings(L, R, seed), inputs.geometric_betas(n_T, 0.4, 2.0), seed, split=False)
+            for L, R, n_T, seed, _ in jobs]
+    se = [j[4] for j in jobs]
+    plan = B.Plan(sims, 6, se, autotune=autotune)
+    info = plan.info()
+    print(f"[runtime] split plan info {info}", flush=True)
+    if not autotune:
+        assert info["split_parts"] > 1
+    for rep in range(3):
+        plan.run(1)
+        B.sweep_batch(bats, [6, 6, 6], se)
+        for ref, s in zip(refs, se):
+            ref.sweep(6, s)
+        for k, (a, b, c) in enumerate(zip(sims, bats, refs)):
+            sa, pa, ta = a.state()
+            sb, pb, tb = b.state()
+            sc, pc, tc = c.state()
+            assert ta == tb == tc == 6 * (rep + 1)
+            assert np.array_equal(pa, pc) and np.array_equal(sa, sc), f"plan replay {rep} job {k}"
+            assert np.array_equal(pb, pc) and np.array_equal(sb, sc), f"batch {rep} job {k}"
+    plan.close()
+    for (L, R, n_T, seed, swe), sim in zip(jobs, sims):
+        r = R - 1
+        o = oracle_lib.OracleSim(L, inputs.couplings(L, R, seed)[[r]], inputs.geometric_betas(n_T, 0.4, 2.0), seed,
+                                 rid=np.array([r]))
+        o.sweep(18, swe)
+        s, perm, t = sim.state()
+        assert np.array_equal(s[r], o.spins[0]) and np.array_equal(perm[r], o.temp_of_slot[0])
+        E, q = sim.observables()
+        Eo, qo = o.observables()
+        assert np.array_equal(E[r], Eo[0]) and np.array_equal(q[r], qo[0])
+    for x in sims + bats + refs:
+        x.close()
+
+
+@pytest.mark.parametrize("policy", ["shortest", "fifo"])
+def test_server_results_alone_equal_mix(oracle_lib, policy):
     """Jobs admitted under a budget that holds only a few at a time, with a
     small quantum so they interleave: each final state equals the job run
     alone, and the energies/overlaps equal ea_observables of that run; one
@@ -97,7 +142,7 @@ def test_server_results_alone_equal_mix(oracle_lib):
     trace = _trace(8)
     fps = [B.job_footprint(j["L"], inputs.geometric_betas(j["n_T"], 0.4, 2.0), j["R"]) for j in trace]
     budget = sum(sorted(fps)[-3:])
-    srv = B.Server(hbm_budget_bytes=budget, quantum_sweeps=7, keep_state=True)
+    srv = B.Server(hbm_budget_bytes=budget, quantum_sweeps=7, keep_state=True, policy=policy)
 
     recs, wall = serve.run_trace(trace, srv, on_done=lambda jid, j, st: None)
     assert len(recs) == len(trace)
