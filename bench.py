@@ -8,9 +8,13 @@ overlaps); the default 10 steps x 1000 sweeps is the whole 10^4-sweep job.
 ps/flip follows Eq. tsf of the paper: wall time / (sweeps x spins x
 temperatures x samples), samples = realizations x 2 copies.
 
-Prints one JSON line.  The roofline object prices the sweep kernel against
-the integer issue rate of the chip; the cpu_baseline object times the CPU
-oracle on a bounded sample of the same workload.
+Further legs on the same line: the large job (L=24, 256 realizations, 48
+temperatures, PT every 10 sweeps) with both draw streams, the five uneven
+jobs batched vs plain, and the 64-job serving trace through the server vs
+the plain single-job path.  The roofline objects price the sweep kernel
+against the vector ALU rate of the chip; the cpu_baseline object times the
+CPU oracle on a bounded sample of the same workload, on all host cores and
+on one.
 """
 import argparse
 import json
@@ -26,12 +30,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ps per spin-flip attempt (1 GPU, batched vs plain) + p50/p99 job latency"
 
-# int32 operations per spin-flip attempt that the method itself needs (the
-# count is derived in the design notes): a quarter of a Philox4x32-10 block
-# (10 rounds x (2 v_mad_u64_u32 + 2 three-input xors) / 4 = 10), the table
-# column, address, compare and insert (4), and the share of the bit-parallel
-# bond energies (2).  On gfx950 every one of these issues at full rate
-# (measured: v_mad_u64_u32 33.4 T/s, v_bitop3 36.1 T/s on 256 CUs).
+# int32 operations per spin-flip attempt that the method itself needs: a
+# quarter of a Philox4x32-10 block (10 rounds x (2 v_mad_u64_u32 + 2
+# three-input xors) / 4 = 10), the table column, address, compare and insert
+# (4), and the share of the bit-parallel bond energies (2).
 ALG_OPS_PER_FLIP = 16
 # The same for the bit-plane stream: a flip attempt needs the planes up to the
 # first one where its draw and threshold differ.  Per 16-slot half a Philox
@@ -42,10 +44,22 @@ ALG_OPS_PER_FLIP = 16
 # their bit-sliced sum (6 xor3, a full-adder tree of 8, masks and the update,
 # about 20 ops per 32 slots): 0.63.  About 5 in all.
 ALG_OPS_PER_FLIP_PLANES = 5
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz int32 lane-operations per second
-PEAK_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+# MI355X vector ALU peak: 256 CUs x 4 SIMDs x 32 lane-operations per cycle x
+# 2.4 GHz = 78.6 T lane-operations/s (the rate behind the published 157.3
+# TFLOP/s fp32 vector figure, an FMA being 2 flops).  A wave64 instruction
+# occupies a SIMD for 4 cycles at the basic 16 lanes/cycle, but the probe
+# (--valu-rate) measures v_bitop3_b32 at 49 T/s with the clock at 1.7 GHz,
+# about 28 lanes/cycle, so 16 lanes/cycle is no ceiling; v_xad_u32 and
+# two-operand instructions measure ~16 lanes/cycle, v_mad_u64_u32 ~10.5 and
+# v_mul_hi_u32 ~8.
+PEAK_OPS_PER_S = 256 * 4 * 32 * 2.4e9
 KERNEL_SRC = os.path.join(ROOT, "paper_1311_5582_amd", "csrc", "ea_kernels.hip")
 PROFILES = os.path.join(ROOT, "profiles")
+
+
+def progress(msg):
+    """One line per finished leg on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash():
@@ -67,8 +81,54 @@ def measured_traffic(workload, layout, rng="words"):
     return int(m.group(1))
 
 
-def cpu_baseline(L, n_T, t_min, t_max, seed, sweeps, threads):
-    """Time the oracle: `threads` realizations, one per thread, `sweeps` each."""
+def valu_rates(grid=1024, iters=512):
+    """Issue rates measured by the probe library: lane-operations per second of
+    v_bitop3_b32, v_xor_b32 + v_min_u32, v_xad_u32, v_mad_u64_u32 (each paired
+    with a v_mov_b32, counted separately), v_mul_hi_u32 (each with a v_xor_b32),
+    and Philox4x32-10 blocks per second; with the shader clock each ran at."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_1311_5582_amd", "libea_valu_probe.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    lib.ea_probe_valu_rates.restype = ctypes.c_int
+    rates, ms, ghz = (ctypes.c_double * 6)(), (ctypes.c_double * 6)(), (ctypes.c_double * 6)()
+    rc = lib.ea_probe_valu_rates(grid, iters, rates, ms, ghz)
+    if rc != 0:
+        raise RuntimeError(f"VALU probe failed with HIP error {rc}")
+    names = ["v_bitop3_b32", "v_xor_b32+v_min_u32", "v_xad_u32", "v_mad_u64_u32(+v_mov_b32)",
+             "v_mul_hi_u32(+v_xor_b32)", "philox4x32_10_blocks"]
+    return {"grid": grid, "threads_per_workgroup": 1024, "iters": iters,
+            "rates_T_per_s": {n: round(rates[k] / 1e12, 3) for k, n in enumerate(names)},
+            "kernel_ms": {n: round(ms[k], 4) for k, n in enumerate(names)},
+            "shader_clock_GHz": {n: round(ghz[k], 3) for k, n in enumerate(names)},
+            "peak_T_per_s": round(PEAK_OPS_PER_S / 1e12, 3)}
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo) and its logical CPU count."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, os.cpu_count() or 1
+
+
+def usable_cores():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def time_oracle(L, n_T, t_min, t_max, seed, sweeps, threads):
+    """Wall time of the oracle on `threads` realizations, one per thread."""
     import oracle
     from paper_1311_5582_amd import inputs
     betas = inputs.geometric_betas(n_T, t_min, t_max)
@@ -81,10 +141,22 @@ def cpu_baseline(L, n_T, t_min, t_max, seed, sweeps, threads):
     for th in ths:
         th.join()
     dt = time.perf_counter() - t0
-    flips = sweeps * L ** 3 * n_T * 2 * threads
+    return dt, sweeps * L ** 3 * n_T * 2 * threads
+
+
+def cpu_baseline(L, n_T, t_min, t_max, seed, sweeps, threads, single_sweeps):
+    """Time the oracle on all usable host cores (one realization per thread,
+    `sweeps` each) and on one core (one realization, `single_sweeps`)."""
+    model, logical = cpu_model()
+    dt, flips = time_oracle(L, n_T, t_min, t_max, seed, sweeps, threads)
+    dt1, flips1 = time_oracle(L, n_T, t_min, t_max, seed, single_sweeps, 1)
     return {"value": dt / flips * 1e12, "unit": "ps/flip", "cores": threads, "kind": "oracle",
             "sample": f"{threads} realizations x 2 copies x {n_T} temps, L={L}, {sweeps} sweeps, "
-                      f"PT every sweep ({flips:.3g} flip attempts, {dt:.1f} s wall)"}
+                      f"PT every sweep, one realization per thread ({flips:.3g} flip attempts, {dt:.1f} s wall)",
+            "cpu_model": model, "host_logical_cpus": logical,
+            "single_core": {"value": dt1 / flips1 * 1e12, "unit": "ps/flip", "cores": 1,
+                            "sample": f"1 realization x 2 copies x {n_T} temps, L={L}, {single_sweeps} sweeps, "
+                                      f"PT every sweep ({flips1:.3g} flip attempts, {dt1:.1f} s wall)"}}
 
 
 def bench_other_stream(B, torch, L, J, betas, seed, layout, block_threads, split, rng, sweeps, swap_every, steps):
@@ -142,6 +214,48 @@ def bench_layout_study(B, torch, inputs, sweeps, steps):
     return out
 
 
+def bench_large(B, inputs, torch, sweeps, steps, rng="words"):
+    """The large production job (L=24, 256 realizations x 2 copies, 48
+    temperatures, PT every 10 sweeps): `steps` launches of `sweeps` sweeps,
+    each followed by a measurement of energies and overlaps; kernel time from
+    HIP events on the launch stream."""
+    cfg = inputs.CONFIGS["L24_R256"]
+    L, R, n_T = cfg["L"], cfg["R"], cfg["n_T"]
+    J = inputs.couplings(L, R, cfg["seed"])
+    betas = inputs.geometric_betas(n_T, cfg["t_min"], cfg["t_max"])
+    stream = torch.cuda.Stream()
+    sim = B.Sim(L, J, betas, cfg["seed"], stream=stream, rng=rng)
+    info = sim.info()
+    sim.sweep(sweeps, cfg["swap_every"])
+    sim.observables()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        sim.sweep(sweeps, cfg["swap_every"])
+        b.record(stream)
+        sim.observables()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.close()
+    flips = sweeps * L ** 3 * n_T * R * 2
+    kern = float(np.mean([a.elapsed_time(b) for a, b in evs])) / 1e3
+    ops = ALG_OPS_PER_FLIP if rng == "words" else ALG_OPS_PER_FLIP_PLANES
+    achieved = ops * flips / kern / 1e12
+    peak = PEAK_OPS_PER_S / 1e12
+    return {"workload": "L24_R256", "L": L, "realizations": R, "copies": 2, "temperatures": n_T,
+            "T_range": [cfg["t_min"], cfg["t_max"]], "swap_every": cfg["swap_every"], "rng": rng,
+            "sweeps_per_step": sweeps, "steps": steps, "measurement_per_step": True,
+            "block_threads": info["block_threads"], "workgroups_per_ladder": info["split_parts"],
+            "ps_per_flip": round(wall / (flips * steps) * 1e12, 4), "ms_per_step": round(wall / steps * 1e3, 4),
+            "kernel_ps_per_flip": round(kern / flips * 1e12, 4),
+            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
+                         "frac": round(achieved / peak, 4), "traffic": measured_traffic("L24_R256", "camsc", rng),
+                         "ops_per_flip": ops, "kernel_sha1": kernel_source_hash(),
+                         "kernel": "sweep_kernel<CAMSC, %d>" % info["split_parts"]}}
+
+
 def flips_of(job, sweeps):
     return sweeps * job["L"] ** 3 * job["n_T"] * job["R"] * 2
 
@@ -190,23 +304,55 @@ def bench_batched(B, inputs, torch, sweeps, steps):
             "units": info["units"], "uses_graph": info["uses_graph"]}
 
 
-def bench_serving(B, inputs, n_jobs, rate, quantum, sweep_scale=1.0, max_active=0):
-    """Poisson job trace through the continuous-batching server (max_active=1:
-    the same server as a plain queue, one job on the GPU at a time)."""
+def bench_serving(B, inputs, n_jobs, rate, quantum, sweep_scale=1.0, policy="ratio", fill=0):
+    """Poisson job trace through the continuous-batching server."""
     from paper_1311_5582_amd import serve
     trace = inputs.serving_trace(n_jobs=n_jobs, rate_per_s=rate)
     for j in trace:
         j["sweeps"] = max(1, int(j["sweeps"] * sweep_scale))
-    srv = B.Server(quantum_sweeps=quantum, max_active=max_active)
+    srv = B.Server(quantum_sweeps=quantum, policy=policy, fill_ladders=fill)
     recs, wall = serve.run_trace(trace, srv)
     st = srv.stats()
     srv.close()
     summ = serve.latency_summary(recs)
+    busy = summ["done_last_s"] - trace[0]["arrival_s"]
     return {"jobs": n_jobs, "rate_per_s": round(rate, 3), "quantum_sweeps": quantum, "sweep_scale": sweep_scale,
+            "policy": policy, "fill_ladders": fill, "p50_latency_s": round(summ["p50_s"], 4), "p99_latency_s": round(summ["p99_s"], 4),
+            "mean_latency_s": round(summ["mean_s"], 4), "wall_s": round(wall, 3),
+            "aggregate_ps_per_flip": round(busy / summ["flips"] * 1e12, 4), "steps": st["steps"],
+            "plans_built": st["plans_built"], "launches_replayed": st["launches_replayed"], "worst": summ["worst"]}
+
+
+def bench_queue_plain(B, inputs, torch, n_jobs, rate, sweep_scale=1.0):
+    """The same trace through the plain single-job path: jobs in arrival order,
+    one at a time, each created and run alone with ea_sweep (split ladders
+    where the library picks them), measured and released."""
+    from paper_1311_5582_amd import serve
+    trace = inputs.serving_trace(n_jobs=n_jobs, rate_per_s=rate)
+    for j in trace:
+        j["sweeps"] = max(1, int(j["sweeps"] * sweep_scale))
+    prepared = [(inputs.couplings(j["L"], j["R"], j["seed"]), inputs.geometric_betas(j["n_T"], j["t_min"], j["t_max"]))
+                for j in trace]
+    recs = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, (j, (J, betas)) in enumerate(zip(trace, prepared)):
+        wait = j["arrival_s"] - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        sim = B.Sim(j["L"], J, betas, j["seed"])
+        sim.sweep(j["sweeps"], j["swap_every"])
+        sim.observables()
+        sim.close()
+        now = time.perf_counter() - t0
+        recs[k] = dict(job=j, status=B.JOB_DONE, done_s=now, latency_s=now - j["arrival_s"])
+    wall = time.perf_counter() - t0
+    summ = serve.latency_summary(recs)
+    busy = summ["done_last_s"] - trace[0]["arrival_s"]
+    return {"jobs": n_jobs, "rate_per_s": round(rate, 3), "sweep_scale": sweep_scale, "path": "ea_sweep per job, FIFO",
             "p50_latency_s": round(summ["p50_s"], 4), "p99_latency_s": round(summ["p99_s"], 4),
             "mean_latency_s": round(summ["mean_s"], 4), "wall_s": round(wall, 3),
-            "aggregate_ps_per_flip": round(wall / summ["flips"] * 1e12, 4), "steps": st["steps"],
-            "plans_built": st["plans_built"], "launches_replayed": st["launches_replayed"]}
+            "aggregate_ps_per_flip": round(busy / summ["flips"] * 1e12, 4), "worst": summ["worst"]}
 
 
 def main():
@@ -228,24 +374,55 @@ def main():
                     help="one workgroup per ladder even when the job has fewer ladders than compute units")
     ap.add_argument("--swap-every", type=int, default=-1, help="override the workload's PT interval")
     ap.add_argument("--cpu-sweeps", type=int, default=900)
+    ap.add_argument("--cpu-single-sweeps", type=int, default=700,
+                    help="sweeps of the one-core oracle timing (one realization)")
+    ap.add_argument("--no-large", action="store_true", help="skip the L=24, 256-realization job")
+    ap.add_argument("--large-sweeps", type=int, default=200)
+    ap.add_argument("--large-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-sweeps", type=int, default=250)
     ap.add_argument("--batched-steps", type=int, default=4)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=64)
+    ap.add_argument("--serving-fill-sweep", default="",
+                    help="comma-separated ladder fill targets: only run the served trace at 20 jobs/s and at "
+                         "--serving-rate2 for each, with --serving-policy, and print their lines")
+    ap.add_argument("--serving-policy", default="ratio", choices=["ratio", "shortest", "fifo"])
+    ap.add_argument("--serving-rate2", type=float, default=1.526)
+    ap.add_argument("--serving-policies", action="store_true",
+                    help="also run the trace with every waiting job admitted at once (first fit, arrival order)")
     ap.add_argument("--serving-quantum", type=int, default=200)
     ap.add_argument("--serving-scale", type=float, default=1.0,
                     help="multiply every job's sweep count (1.0 = the lognormal trace as drawn)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before timing, run one elementwise kernel that reads and writes this many MiB "
                          "(reference kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--valu-rate", action="store_true",
+                    help="only measure the integer issue rates behind the roofline and print them")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: each realization is an independent Markov chain and this "
               "build measures one GPU's share; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.valu_rate:
+        print(json.dumps({"valu_rate": valu_rates()}), flush=True)
+        return
+    if args.serving_fill_sweep:
+        from paper_1311_5582_amd import binding as B
+        from paper_1311_5582_amd import inputs
+        res = {}
+        for fill in [int(x) for x in args.serving_fill_sweep.split(",")]:
+            for rate in (20.0, args.serving_rate2):
+                r = bench_serving(B, inputs, args.serving_jobs, rate, args.serving_quantum, args.serving_scale,
+                                  policy=args.serving_policy, fill=fill)
+                res[f"fill{fill}_rate{rate}"] = r
+                progress(f"fill {fill} rate {rate}: p50 {r['p50_latency_s']} p99 {r['p99_latency_s']} "
+                         f"{r['aggregate_ps_per_flip']} ps/flip")
+        print(json.dumps({"serving_fill_sweep": res}), flush=True)
+        return
 
     import torch
     from paper_1311_5582_amd import binding as B
@@ -324,26 +501,52 @@ def main():
                      "kernel": "sweep_kernel<%s, %d>" % (args.layout.upper(), launch["split_parts"])},
     }
     sim.close()
+    progress(f"{args.workload}: {ps_per_flip:.4f} ps/flip")
     if not args.no_other_stream and args.layout == "camsc":
         other = "planes" if args.rng == "words" else "words"
         out["other_stream"] = bench_other_stream(B, torch, L, J, betas, cfg["seed"], args.layout, args.block_threads,
                                                  not args.no_split, other, S, se, 3)
+    if "other_stream" in out:
+        progress(f"other stream: {out['other_stream']['ps_per_flip']} ps/flip")
     if args.layout_study:
         out["layout_study_kernel_ps_per_flip"] = bench_layout_study(B, torch, inputs, 200, 3)
+        progress("layout study done")
+    if not args.no_large:
+        out["large"] = bench_large(B, inputs, torch, args.large_sweeps, args.large_steps)
+        out["large_planes"] = bench_large(B, inputs, torch, args.large_sweeps, args.large_steps, rng="planes")
+        progress(f"L24_R256: {out['large']['ps_per_flip']} / planes {out['large_planes']['ps_per_flip']} ps/flip")
     if not args.no_batched:
         out["batched"] = bench_batched(B, inputs, torch, args.batched_sweeps, args.batched_steps)
+        progress(f"batched: {out['batched']['batched_ps_per_flip']} vs plain {out['batched']['plain_ps_per_flip']}")
     if not args.no_serving:
-        out["serving"] = bench_serving(B, inputs, args.serving_jobs, 20.0, args.serving_quantum, args.serving_scale)
-        # the same trace shape at 0.8 x the measured service capacity (jobs/s)
+        def leg(name, result):
+            out[name] = result
+            progress(f"{name}: p50 {result['p50_latency_s']} s p99 {result['p99_latency_s']} s "
+                     f"{result['aggregate_ps_per_flip']} ps/flip")
+
+        leg("serving", bench_serving(B, inputs, args.serving_jobs, 20.0, args.serving_quantum, args.serving_scale))
+        # the same trace through the plain single-job path, one job at a time
+        leg("serving_queue_only", bench_queue_plain(B, inputs, torch, args.serving_jobs, 20.0, args.serving_scale))
+        if args.serving_policies:
+            # every waiting job admitted at once (processor sharing), and response-ratio admission
+            leg("serving_fifo_all", bench_serving(B, inputs, args.serving_jobs, 20.0, args.serving_quantum,
+                                                  args.serving_scale, policy="fifo"))
+            leg("serving_shortest", bench_serving(B, inputs, args.serving_jobs, 20.0, args.serving_quantum,
+                                                  args.serving_scale, policy="shortest"))
+        # the same trace shape at 0.8 x the measured service capacity (jobs/s), served and plain
         cap = out["serving"]["jobs"] / max(out["serving"]["wall_s"], 1e-9)
-        out["serving_at_0.8_capacity"] = bench_serving(B, inputs, args.serving_jobs, 0.8 * cap,
-                                                      args.serving_quantum, args.serving_scale)
-        # the first trace through a plain queue: one job on the GPU at a time
-        out["serving_queue_only"] = bench_serving(B, inputs, args.serving_jobs, 20.0, args.serving_quantum,
-                                                  args.serving_scale, max_active=1)
+        leg("serving_at_0.8_capacity", bench_serving(B, inputs, args.serving_jobs, 0.8 * cap, args.serving_quantum,
+                                                     args.serving_scale))
+        leg("serving_queue_only_at_0.8_capacity", bench_queue_plain(B, inputs, torch, args.serving_jobs, 0.8 * cap,
+                                                                    args.serving_scale))
+        if args.serving_policies:
+            leg("serving_shortest_at_0.8_capacity", bench_serving(B, inputs, args.serving_jobs, 0.8 * cap,
+                                                                  args.serving_quantum, args.serving_scale,
+                                                                  policy="shortest"))
     if not args.no_cpu_baseline:
-        threads = max(1, min(os.cpu_count() or 1, 16))
-        out["cpu_baseline"] = cpu_baseline(L, n_T, cfg["t_min"], cfg["t_max"], cfg["seed"], args.cpu_sweeps, threads)
+        out["cpu_baseline"] = cpu_baseline(L, n_T, cfg["t_min"], cfg["t_max"], cfg["seed"], args.cpu_sweeps,
+                                           usable_cores(), args.cpu_single_sweeps)
+        progress("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 

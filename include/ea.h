@@ -218,18 +218,26 @@ void ea_plan_destroy(ea_plan *plan);
 /* ---- Serving: continuous batching of jobs on one GPU ----
  * Jobs are submitted with host inputs and wait.  Each ea_server_step
  * (1) admits waiting jobs while their device footprint (ea_job_footprint)
- * fits the budget: first fit in arrival order (EA_ADMIT_FIFO), or shortest
- * remaining work first (sweeps x L^3 x n_T x R) until the running jobs hold
- * fill_ladders ladders (EA_ADMIT_SHORTEST; a long job can wait behind a
- * stream of shorter ones); the jobs are created while the previous step still
+ * fits the budget: first fit in arrival order (EA_ADMIT_FIFO), or, until the
+ * running jobs hold fill_ladders ladders, shortest remaining work first
+ * (sweeps x L^3 x n_T x R; EA_ADMIT_SHORTEST: a long job can wait behind a
+ * stream of shorter ones) or highest response ratio first ((waited +
+ * estimated service) / estimated service, with the service time from the
+ * measured rate of the server's own steps; EA_ADMIT_RESPONSE_RATIO: the
+ * longer a job has waited relative to its size, the sooner it runs); the
+ * jobs are created while the previous step still
  * runs on the GPU; (2) waits for that step and retires finished jobs:
  * energies and overlaps are measured, device state is freed; (3) launches the
- * next step over every running job, each for min(quantum, sweeps it has left)
- * sweeps, replaying a graph-captured plan while the job set and sweep counts
- * are unchanged, and returns without waiting for it.  A job's results are the
+ * next step over every running job and returns without waiting for it.  In a
+ * step the running job with the most work per ladder and sweep (L^3 x n_T)
+ * runs quantum sweeps and every other job round(quantum x that work / its
+ * own) sweeps, so that all ladders of the step take about equally long (at
+ * most the sweeps it has left); a graph-captured plan is replayed while the
+ * job set and sweep counts are unchanged.  A job's results are the
  * same alone and in any mix. */
-#define EA_ADMIT_FIFO     0
-#define EA_ADMIT_SHORTEST 1
+#define EA_ADMIT_FIFO           0
+#define EA_ADMIT_SHORTEST       1
+#define EA_ADMIT_RESPONSE_RATIO 2
 #define EA_JOB_QUEUED    0
 #define EA_JOB_RUNNING   1
 #define EA_JOB_DONE      2
@@ -239,15 +247,15 @@ void ea_plan_destroy(ea_plan *plan);
 typedef struct ea_server ea_server;
 typedef struct ea_server_options {
     size_t hbm_budget_bytes;  /* device bytes for job state; 0 = 80% of free memory at creation */
-    int quantum_sweeps;       /* sweeps per step (default 200)                                   */
+    int quantum_sweeps;       /* sweeps per step of the job with the most work per sweep (200)    */
     int layout;               /* EA_LAYOUT_* of every job                                         */
     int max_active;           /* admitted jobs at once, <= 4095 (0 = 4095)                        */
     int autotune;             /* 1 = tune each job mix's workgroup size (cached by shape); default 0 */
     int keep_state;           /* keep each finished job's spins and permutation on the host       */
     int rng;                  /* EA_RNG_* flip-draw stream of every job (planes: CAMSC only); the
                                  jobs run without a field                                        */
-    int policy;               /* EA_ADMIT_SHORTEST (default) or EA_ADMIT_FIFO                     */
-    int fill_ladders;         /* EA_ADMIT_SHORTEST: stop admitting once the running jobs hold this
+    int policy;               /* EA_ADMIT_RESPONSE_RATIO (default), _SHORTEST or _FIFO            */
+    int fill_ladders;         /* SHORTEST, RESPONSE_RATIO: stop admitting once the running jobs hold this
                                  many ladders (2 x realizations); 0 = 4 x the compute units      */
     void *stream;             /* hipStream_t of the steps; NULL = a stream owned by the server    */
 } ea_server_options;

@@ -6,9 +6,11 @@ available, device memory comes from torch's caching allocator and the work
 runs on a torch stream; otherwise the library's own hipMalloc and the default
 stream are used.  A missing library is an error, never a fallback.
 """
+import atexit
 import ctypes
 import os
 import re
+import weakref
 
 import numpy as np
 
@@ -157,6 +159,20 @@ def swap_threshold(dbeta_abs, n):
     return int(lib().ea_swap_threshold(float(dbeta_abs), int(n)))
 
 
+# Live handles, closed in dependency order (servers, plans, then jobs) when
+# the interpreter exits, while torch and this module are still intact: a
+# handle's device memory may come from torch's caching allocator, whose
+# callbacks must not run during interpreter teardown.
+_LIVE = {"server": weakref.WeakSet(), "plan": weakref.WeakSet(), "sim": weakref.WeakSet()}
+
+
+@atexit.register
+def _close_live_handles():
+    for kind in ("server", "plan", "sim"):
+        for h in list(_LIVE[kind]):
+            h.close()
+
+
 class TorchAllocator:
     """Device memory for the library from torch's caching allocator."""
 
@@ -221,10 +237,11 @@ class Sim:
         self._h = ctypes.c_void_p()
         check(lib().ea_create(L, _p(J, ctypes.c_int8), _p(b, ctypes.c_double), len(b), J.shape[0],
                               ctypes.c_uint64(int(seed) & (2 ** 64 - 1)), ctypes.byref(opt), ctypes.byref(self._h)))
+        _LIVE["sim"].add(self)
 
     def close(self):
-        if getattr(self, "_h", None) and self._h.value:
-            lib().ea_destroy(self._h)
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.ea_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     __del__ = close
@@ -356,6 +373,7 @@ class Plan:
         self._h = ctypes.c_void_p()
         check(lib().ea_plan_create(hs, n, int(sweeps_per_step), _p(se, ctypes.c_int32), ctypes.byref(opt),
                                    ctypes.byref(self._h)))
+        _LIVE["plan"].add(self)
 
     def run(self, n_steps=1):
         check(lib().ea_plan_run(self._h, int(n_steps)))
@@ -369,8 +387,8 @@ class Plan:
                     uses_graph=bool(g.value), split_parts=parts.value)
 
     def close(self):
-        if getattr(self, "_h", None) and self._h.value:
-            lib().ea_plan_destroy(self._h)
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.ea_plan_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     __del__ = close
@@ -380,7 +398,7 @@ class Server:
     """Continuous-batching job server (see ea_server_* in include/ea.h)."""
 
     def __init__(self, hbm_budget_bytes=0, quantum_sweeps=200, layout="camsc", max_active=0, autotune=False,
-                 keep_state=False, rng="words", policy="shortest", fill_ladders=0):
+                 keep_state=False, rng="words", policy="ratio", fill_ladders=0):
         opt = ServerOptions()
         lib().ea_default_server_options(ctypes.byref(opt))
         opt.hbm_budget_bytes = int(hbm_budget_bytes)
@@ -390,11 +408,12 @@ class Server:
         opt.autotune = int(bool(autotune))
         opt.keep_state = int(bool(keep_state))
         opt.rng = RNGS[rng] if isinstance(rng, str) else int(rng)
-        opt.policy = {"fifo": 0, "shortest": 1}[policy] if isinstance(policy, str) else int(policy)
+        opt.policy = {"fifo": 0, "shortest": 1, "ratio": 2}[policy] if isinstance(policy, str) else int(policy)
         opt.fill_ladders = int(fill_ladders)
         self._h = ctypes.c_void_p()
         self.shapes = {}
         check(lib().ea_server_create(ctypes.byref(opt), ctypes.byref(self._h)))
+        _LIVE["server"].add(self)
 
     def submit(self, L, couplings, betas, seed, n_sweeps, swap_every=1):
         J = np.ascontiguousarray(couplings, dtype=np.int8)
@@ -446,8 +465,8 @@ class Server:
                     plans_built=plans.value, launches_replayed=replays.value)
 
     def close(self):
-        if getattr(self, "_h", None) and self._h.value:
-            lib().ea_server_destroy(self._h)
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.ea_server_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     __del__ = close

@@ -10,6 +10,9 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libea_mi355x.so")
+# issue-rate probe behind the roofline pricing (bench.py --valu-rate); not part of the ABI
+PROBE_LIB = os.path.join(PKG, "libea_valu_probe.so")
+PROBE_SRC = os.path.join(PKG, "csrc", "valu_probe.hip")
 SOURCES = [os.path.join(PKG, "csrc", f) for f in ("ea_kernels.hip", "ea_workspace.hip", "ea_api.cpp", "ea_runtime.cpp", "ea_server.cpp")]
 ARCH = os.environ.get("EA_OFFLOAD_ARCH", "gfx950")
 
@@ -36,6 +39,8 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(PKG, "csrc", os.path.basename(src) + ".o")
         cmds.append([hipcc()] + HIPCC_FLAGS + ["-x", "hip", "-c", src, "-o", obj])
         objs.append(obj)
+    probe_tmp = PROBE_LIB + ".tmp"
+    cmds.append([hipcc()] + HIPCC_FLAGS + ["-x", "hip", "-shared", PROBE_SRC, "-o", probe_tmp])
     # the translation units are independent: compile them side by side
     with cf.ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as ex:
         for cmd in cmds:
@@ -49,6 +54,7 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    os.replace(probe_tmp, PROBE_LIB)
     for o in objs:
         os.remove(o)
     return LIB

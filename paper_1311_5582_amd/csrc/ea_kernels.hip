@@ -933,7 +933,9 @@ __device__ __forceinline__ void count_up_word(const uint32_t *words, int N, int 
 // ---------------------------------------------------------------------------
 // Sweep kernel.
 //
-// PARTS = 1: persistent workgroups pulling ladders from a queue.
+// PARTS = 1: persistent workgroups pulling ladders from a queue (units[k] =
+// job << 20 | ladder).  With PARTS > 1, UNITS = false runs one job's ladders
+// in order (job 0, ladder = list index) and UNITS = true reads the list.
 // PARTS > 1 (CAMSC, one word per site, even L): PARTS workgroups share a
 // ladder, each holding all of its words in LDS but deciding only its own slot
 // groups.  At a swap point they publish their slots' energies through a
@@ -949,7 +951,7 @@ __device__ __forceinline__ void count_up_word(const uint32_t *words, int N, int 
 // ---------------------------------------------------------------------------
 constexpr uint32_t kSpinLimit = 1u << 20;   // polls of a partner's flag before giving up
 
-template <int LAYOUT, int PARTS, int RNG>
+template <int LAYOUT, int PARTS, int RNG, bool UNITS = false>
 __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restrict__ jobs,
                                                           const uint32_t *__restrict__ units, int n_units,
                                                           uint32_t *queue)
@@ -970,10 +972,13 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
     const int wave = tid >> 6;
     const int nwaves = nthr >> 6;
 
-    for (;;) {
+    for (int iter = 0;; ++iter) {
         uint32_t unit;
         int part = 0;
         if (SPLIT) {
+            // one ticket per workgroup: the grid gives every queue as many
+            // workgroups as its ladders have parts
+            if (iter > 0) break;
             const uint32_t xq = blockIdx.x & 7u;
             if (tid == 0) s_next = atomicAdd(queue + xq, 1u);
             __syncthreads();
@@ -982,7 +987,9 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
             part = (int)(tk % (uint32_t)PARTS);
             const uint32_t li = (tk / (uint32_t)PARTS) * 8u + xq;   // this queue's (tk / PARTS)-th ladder
             if (li >= (uint32_t)n_units) break;   // its partners' tickets are past the end too
-            unit = units[li];
+            // a lone job's ladders in order need no list (and an index the
+            // compiler can recompute keeps fewer registers live than a loaded one)
+            unit = UNITS ? units[li] : li;
         } else {
             if (tid == 0) s_next = atomicAdd(queue, 1u);
             __syncthreads();
@@ -1674,17 +1681,21 @@ hipError_t launch_init_spins(const JobDesc *d_job, const JobDesc &h, int layout,
     return hipGetLastError();
 }
 
-// Sweep kernel variants: kv = 0 CAMSC, 1 AMSC4, 2 CAMSC with plane draws, 3 AMSC3, 4 AMSC1.
-static const void *sweep_fn(int kv, int parts)
+// Sweep kernel variants: kv = 0 CAMSC, 1 AMSC4, 2 CAMSC with plane draws, 3 AMSC3, 4 AMSC1;
+// split ladders (parts 2 or 4, CAMSC) read the unit list when `listed`.
+static const void *sweep_fn(int kv, int parts, bool listed = false)
 {
     if (kv == 1) return (const void *)sweep_kernel<1, 1, 0>;
     if (kv == 3) return (const void *)sweep_kernel<2, 1, 0>;
     if (kv == 4) return (const void *)sweep_kernel<3, 1, 0>;
-    if (kv == 2)
-        return parts == 4 ? (const void *)sweep_kernel<0, 4, 1>
-                          : (parts == 2 ? (const void *)sweep_kernel<0, 2, 1> : (const void *)sweep_kernel<0, 1, 1>);
-    return parts == 4 ? (const void *)sweep_kernel<0, 4, 0>
-                      : (parts == 2 ? (const void *)sweep_kernel<0, 2, 0> : (const void *)sweep_kernel<0, 1, 0>);
+    if (kv == 2) {
+        if (parts == 4) return listed ? (const void *)sweep_kernel<0, 4, 1, true> : (const void *)sweep_kernel<0, 4, 1>;
+        if (parts == 2) return listed ? (const void *)sweep_kernel<0, 2, 1, true> : (const void *)sweep_kernel<0, 2, 1>;
+        return (const void *)sweep_kernel<0, 1, 1>;
+    }
+    if (parts == 4) return listed ? (const void *)sweep_kernel<0, 4, 0, true> : (const void *)sweep_kernel<0, 4, 0>;
+    if (parts == 2) return listed ? (const void *)sweep_kernel<0, 2, 0, true> : (const void *)sweep_kernel<0, 2, 0>;
+    return (const void *)sweep_kernel<0, 1, 0>;
 }
 
 hipError_t sweep_set_lds(int kv, int parts, size_t lds)
@@ -1695,6 +1706,8 @@ hipError_t sweep_set_lds(int kv, int parts, size_t lds)
     std::atomic<size_t> &cur = set_max[kv][pi];
     if (lds <= cur.load()) return hipSuccess;
     hipError_t e = hipFuncSetAttribute(sweep_fn(kv, parts), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess && parts > 1)
+        e = hipFuncSetAttribute(sweep_fn(kv, parts, true), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e == hipSuccess) {
         size_t prev = cur.load();
         while (prev < lds && !cur.compare_exchange_weak(prev, lds)) {
@@ -1709,7 +1722,8 @@ hipError_t launch_sweep(const JobDesc *d_jobs, int n_jobs, const uint32_t *d_uni
     hipError_t e = sweep_set_lds(kv, parts, lds);
     if (e != hipSuccess) return e;
     void *args[] = {(void *)&d_jobs, (void *)&d_units, (void *)&n_units, (void *)&d_queue};
-    e = hipLaunchKernel(sweep_fn(kv, parts), dim3(grid), dim3(block_threads), args, lds, s);
+    // one job's units are its ladders in order (a launch set of one job keeps them so)
+    e = hipLaunchKernel(sweep_fn(kv, parts, n_jobs > 1), dim3(grid), dim3(block_threads), args, lds, s);
     if (e != hipSuccess) return e;
     const int adv = n_jobs > kQueueWords ? n_jobs : kQueueWords;
     hipLaunchKernelGGL(advance_kernel, dim3((adv + 255) / 256), dim3(256), 0, s, d_jobs, n_jobs, d_queue);
@@ -1718,9 +1732,13 @@ hipError_t launch_sweep(const JobDesc *d_jobs, int n_jobs, const uint32_t *d_uni
 
 int sweep_max_blocks_per_cu(int kv, int parts, int block_threads, size_t lds)
 {
-    int n = 0;
+    int n = 0, m = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, sweep_fn(kv, parts), block_threads, lds);
-    return e == hipSuccess ? n : 0;
+    if (e == hipSuccess && parts > 1)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, sweep_fn(kv, parts, true), block_threads, lds);
+    else
+        m = n;
+    return e == hipSuccess ? (n < m ? n : m) : 0;
 }
 
 hipError_t launch_observables(const JobDesc *d_job, const JobDesc &h, int layout, int32_t *d_energy,

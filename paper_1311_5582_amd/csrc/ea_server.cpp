@@ -7,12 +7,14 @@
 // previous step still runs on the GPU, (2) waits for that step and retires
 // finished jobs (energies and overlaps measured, device state released, which
 // admits the next jobs), and (3) launches the next step over every running
-// job, each for min(quantum, sweeps it has left) sweeps, replaying a
+// job, each for about as much work per ladder as `quantum` sweeps of the job
+// with the most work per sweep (capped by the sweeps it has left), replaying a
 // graph-captured plan while the job set and sweep counts are unchanged.
 // Results are a pure function of each job's inputs (counter-based stream,
 // device-resident sweep counters), so a job's result is the same alone and in
 // any mix.
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -32,6 +34,7 @@ struct Job {
     int L = 0, n_T = 0, R = 0, swap_every = 0;
     uint64_t seed = 0;
     int64_t n_sweeps = 0, done = 0;
+    double arrival = 0.0;                      // host clock at submission, seconds
     size_t footprint = 0;
     std::vector<int8_t> J;
     std::vector<double> betas;
@@ -43,6 +46,8 @@ struct Job {
 };
 
 }  // namespace
+
+constexpr int kMaxStepSweeps = 1 << 20;   // sweeps of one job in one step, at most
 
 struct ea_server {
     ea_server_options opt{};
@@ -64,6 +69,9 @@ struct ea_server {
     bool in_flight = false;
     std::vector<int64_t> flight_ids;
     std::vector<int> flight_sweeps;
+    double flight_flips = 0.0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // around each step, for the measured service rate
+    double s_per_flip = 1e-12;                 // running estimate of the GPU time per flip attempt
     int64_t steps = 0, launches_replayed = 0, plans_built = 0;
 };
 
@@ -76,11 +84,19 @@ static void drop_plan(ea_server *sv)
 }
 
 // Wait for the step in flight and credit its sweeps.
+static double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 static int finish_step(ea_server *sv)
 {
     if (!sv->in_flight) return EA_OK;
     sv->in_flight = false;
     EA_HIP(hipStreamSynchronize(sv->stream));
+    float ms = 0.0f;
+    if (sv->flight_flips > 0.0 && hipEventElapsedTime(&ms, sv->ev0, sv->ev1) == hipSuccess && ms > 0.0f)
+        sv->s_per_flip = 0.8 * sv->s_per_flip + 0.2 * (1e-3 * ms / sv->flight_flips);
     for (size_t k = 0; k < sv->flight_ids.size(); ++k) {
         auto it = sv->jobs.find(sv->flight_ids[k]);
         if (it != sv->jobs.end()) it->second->done += sv->flight_sweeps[k];
@@ -92,6 +108,14 @@ static int finish_step(ea_server *sv)
 static int64_t remaining_work(const Job *j)
 {
     return (j->n_sweeps - j->done) * (int64_t)j->L * j->L * j->L * j->n_T * j->R;
+}
+
+// Response ratio of a waiting job: (time waited + its estimated service time)
+// / its estimated service time, the service time from the measured rate.
+static double response_ratio(const ea_server *sv, const Job *j, double now)
+{
+    const double est = std::max(1e-6, (double)remaining_work(j) * 2.0 * sv->s_per_flip);
+    return (now - j->arrival + est) / est;
 }
 
 static void release_job_device(ea_server *sv, Job *j)
@@ -113,7 +137,7 @@ void ea_default_server_options(ea_server_options *opt)
     opt->quantum_sweeps = 200;
     opt->layout = EA_LAYOUT_CAMSC;
     opt->autotune = 0;   // the job mix changes at every arrival; tuning each mix would cost more than it saves
-    opt->policy = EA_ADMIT_SHORTEST;
+    opt->policy = EA_ADMIT_RESPONSE_RATIO;
     opt->fill_ladders = 0;
 }
 
@@ -130,7 +154,7 @@ int ea_server_create(const ea_server_options *opt_in, ea_server **out)
     if (opt.rng == EA_RNG_PLANES && opt.layout != EA_LAYOUT_CAMSC)
         return fail(EA_EINVAL, "plane draws need the CAMSC layout");
     if (opt.max_active < 0 || opt.max_active > 4095) return fail(EA_EINVAL, "max_active outside [0, 4095]");
-    if (opt.policy != EA_ADMIT_FIFO && opt.policy != EA_ADMIT_SHORTEST) return fail(EA_EINVAL, "unknown policy");
+    if (opt.policy < EA_ADMIT_FIFO || opt.policy > EA_ADMIT_RESPONSE_RATIO) return fail(EA_EINVAL, "unknown policy");
     if (opt.fill_ladders < 0) return fail(EA_EINVAL, "fill_ladders < 0");
     ea_server *sv = new (std::nothrow) ea_server;
     if (!sv) return fail(EA_ENOMEM, "host allocation failed");
@@ -147,7 +171,11 @@ int ea_server_create(const ea_server_options *opt_in, ea_server **out)
     sv->fill_ladders = opt.fill_ladders > 0 ? opt.fill_ladders : 4 * cus;
     if (e == hipSuccess && opt.stream == nullptr) e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->admit, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&sv->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&sv->ev1);
     if (e != hipSuccess) {
+        if (sv->ev0) (void)hipEventDestroy(sv->ev0);
+        if (sv->ev1) (void)hipEventDestroy(sv->ev1);
         if (sv->admit) (void)hipStreamDestroy(sv->admit);
         if (opt.stream == nullptr && sv->stream) (void)hipStreamDestroy(sv->stream);
         delete sv;
@@ -178,6 +206,7 @@ int ea_server_submit(ea_server *sv, int L, const int8_t *couplings, const double
     j->id = sv->next_id++;
     j->L = L; j->n_T = n_T; j->R = R; j->seed = seed; j->n_sweeps = n_sweeps; j->swap_every = swap_every;
     j->footprint = fp;
+    j->arrival = now_s();
     j->J.assign(couplings, couplings + nJ);
     j->betas.assign(betas, betas + n_T);
     *job_id = j->id;
@@ -193,14 +222,24 @@ int ea_server_step(ea_server *sv, int *n_running, int *n_queued, int *n_finished
     int finished = 0;
     // 1. admission, on the host and the admission stream while the step in flight runs
     std::vector<int64_t> order(sv->queue.begin(), sv->queue.end());
-    if (sv->opt.policy == EA_ADMIT_SHORTEST)
+    if (sv->opt.policy == EA_ADMIT_SHORTEST) {
         std::stable_sort(order.begin(), order.end(), [sv](int64_t a, int64_t b) {
             return remaining_work(sv->jobs[a].get()) < remaining_work(sv->jobs[b].get());
         });
+    } else if (sv->opt.policy == EA_ADMIT_RESPONSE_RATIO) {
+        const double now = now_s();
+        std::vector<std::pair<double, int64_t>> keyed;
+        for (int64_t id : order) keyed.push_back({-response_ratio(sv, sv->jobs[id].get(), now), id});
+        std::stable_sort(keyed.begin(), keyed.end(),
+                         [](const std::pair<double, int64_t> &a, const std::pair<double, int64_t> &b) {
+                             return a.first < b.first;
+                         });
+        for (size_t k = 0; k < keyed.size(); ++k) order[k] = keyed[k].second;
+    }
     for (int64_t id : order) {
         Job *j = sv->jobs[id].get();
         if ((int)sv->active.size() >= sv->opt.max_active) break;
-        if (sv->opt.policy == EA_ADMIT_SHORTEST && !sv->active.empty() && sv->active_ladders >= sv->fill_ladders)
+        if (sv->opt.policy != EA_ADMIT_FIFO && !sv->active.empty() && sv->active_ladders >= sv->fill_ladders)
             break;
         if (sv->used + j->footprint > sv->opt.hbm_budget_bytes) continue;
         ea_options o;
@@ -253,12 +292,24 @@ int ea_server_step(ea_server *sv, int *n_running, int *n_queued, int *n_finished
     sv->active.swap(still);
     // 3. launch the next step over every running job (not waited for here)
     if (!sv->active.empty()) {
+        // Sweeps per step in inverse proportion to a ladder's work per sweep
+        // (sites x temperatures): the job with the most work per sweep runs
+        // `quantum` sweeps, and every ladder of the step takes about as long,
+        // so a job with cheap sweeps is not held to the pace of an expensive
+        // one and the launch's units are of one size.
+        double w_max = 0.0;
+        for (int64_t id : sv->active) {
+            const Job *j = sv->jobs[id].get();
+            w_max = std::max(w_max, (double)j->L * j->L * j->L * j->n_T);
+        }
         std::vector<int> q;
         std::vector<ea_sim *> sims;
         std::vector<int> se;
         for (int64_t id : sv->active) {
             const Job *j = sv->jobs[id].get();
-            q.push_back((int)std::min<int64_t>(sv->opt.quantum_sweeps, j->n_sweeps - j->done));
+            const double w = (double)j->L * j->L * j->L * j->n_T;
+            const double want = std::min((double)kMaxStepSweeps, std::round(sv->opt.quantum_sweeps * w_max / w));
+            q.push_back((int)std::min<int64_t>((int64_t)std::max(1.0, want), j->n_sweeps - j->done));
             sims.push_back(j->sim);
             se.push_back(j->swap_every);
         }
@@ -275,10 +326,17 @@ int ea_server_step(ea_server *sv, int *n_running, int *n_queued, int *n_finished
         } else {
             ++sv->launches_replayed;
         }
+        EA_HIP(hipEventRecord(sv->ev0, sv->stream));
         if (int rc = ea_plan_run(sv->plan, 1)) return rc;
+        EA_HIP(hipEventRecord(sv->ev1, sv->stream));
         sv->in_flight = true;
         sv->flight_ids = sv->active;
         sv->flight_sweeps = q;
+        sv->flight_flips = 0.0;
+        for (size_t k = 0; k < sv->active.size(); ++k) {
+            const Job *j = sv->jobs[sv->active[k]].get();
+            sv->flight_flips += (double)q[k] * j->L * j->L * j->L * j->n_T * 2.0 * j->R;
+        }
     }
     if (n_running) *n_running = (int)sv->active.size();
     if (n_queued) *n_queued = (int)sv->queue.size();
@@ -373,6 +431,8 @@ void ea_server_destroy(ea_server *sv)
     for (auto &kv : sv->jobs) release_job_device(sv, kv.second.get());
     if (sv->opt.stream == nullptr) (void)hipStreamDestroy(sv->stream);
     (void)hipStreamDestroy(sv->admit);
+    (void)hipEventDestroy(sv->ev0);
+    (void)hipEventDestroy(sv->ev1);
     delete sv;
 }
 

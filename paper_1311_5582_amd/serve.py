@@ -50,5 +50,10 @@ def latency_summary(records):
     lat = np.array([r["latency_s"] for r in records.values()])
     flips = sum(r["job"]["sweeps"] * r["job"]["L"] ** 3 * r["job"]["n_T"] * r["job"]["R"] * 2 for r in records.values())
     done_last = max(r["done_s"] for r in records.values())
+    worst = sorted(records.values(), key=lambda r: -r["latency_s"])[:3]
+    worst = [dict(job_id=r["job"].get("job_id"), L=r["job"]["L"], R=r["job"]["R"], n_T=r["job"]["n_T"],
+                  sweeps=r["job"]["sweeps"], arrival_s=round(r["job"]["arrival_s"], 3),
+                  latency_s=round(r["latency_s"], 3)) for r in worst]
     return dict(jobs=len(lat), p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
-                mean_s=float(lat.mean()), max_s=float(lat.max()), flips=float(flips), done_last_s=float(done_last))
+                mean_s=float(lat.mean()), max_s=float(lat.max()), flips=float(flips), done_last_s=float(done_last),
+                worst=worst)

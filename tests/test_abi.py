@@ -166,3 +166,24 @@ def test_swap_acceptance_is_64_bit_in_the_header():
     assert "the device counts in 64 bits" in text
     internal = open(os.path.join(B.PKG, "csrc", "ea_internal.h")).read()
     assert "uint64_t *swap_acc;" in internal
+
+
+def test_close_after_library_teardown_is_inert():
+    """At interpreter teardown the binding's globals may already be gone:
+    closing a handle then does nothing instead of raising."""
+    import ctypes
+    from paper_1311_5582_amd import binding as B
+    saved = B._lib
+    objs = []
+    try:
+        B._lib = None
+        for cls in (B.Sim, B.Plan, B.Server):
+            obj = cls.__new__(cls)
+            obj._h = ctypes.c_void_p(0x1000)   # never dereferenced: the library is gone
+            objs.append(obj)
+            obj.close()
+            assert obj._h.value == 0x1000
+    finally:
+        for obj in objs:
+            obj._h = ctypes.c_void_p()   # before the library comes back: the finalisers must not see the fake handle
+        B._lib = saved

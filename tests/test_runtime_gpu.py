@@ -133,7 +133,7 @@ def test_split_plan_and_batch_equal_alone(oracle_lib, autotune):
         x.close()
 
 
-@pytest.mark.parametrize("policy", ["shortest", "fifo"])
+@pytest.mark.parametrize("policy", ["shortest", "fifo", "ratio"])
 def test_server_results_alone_equal_mix(oracle_lib, policy):
     """Jobs admitted under a budget that holds only a few at a time, with a
     small quantum so they interleave: each final state equals the job run
@@ -256,3 +256,20 @@ def test_server_serving_trace_shapes(oracle_lib, rng, n_jobs):
     print(f"[runtime] serving shapes stats {st} wall {wall:.3f}s", flush=True)
     assert st["hbm_used"] == 0
     srv.close()
+
+
+def test_exit_hook_closes_live_handles():
+    """The binding's exit hook closes every live server, plan and job in that
+    order (it runs before interpreter teardown, while torch is intact), and a
+    handle closed there is left inert for its own finaliser."""
+    sims = [_make(8, 2, 16, s) for s in (1, 2)]
+    plan = B.Plan(sims, 5, [1, 1], autotune=False)
+    plan.run(1)
+    srv = B.Server(quantum_sweeps=3)
+    srv.submit(6, inputs.couplings(6, 1, 3), inputs.geometric_betas(8, 0.5, 2.0), 3, 7, 1)
+    srv.step()
+    assert plan in B._LIVE["plan"] and srv in B._LIVE["server"] and all(x in B._LIVE["sim"] for x in sims)
+    B._close_live_handles()
+    assert not srv._h.value and not plan._h.value and not any(x._h.value for x in sims)
+    for x in (srv, plan, *sims):
+        x.close()   # a second close is a no-op
