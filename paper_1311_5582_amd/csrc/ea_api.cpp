@@ -181,11 +181,12 @@ int wgs_per_cu(size_t lds, int bt)
 
 // Optional LDS copies (swap tables, odd-L site list) are taken only when they
 // fit and do not lower the number of workgroups a CU can hold.
-void plan_optional_lds(int N, int wr, int bt, bool odd, int64_t swap_entries, int *swap_lds, int *sites_lds)
+void plan_optional_lds(int N, int wr, int bt, bool odd, int64_t swap_entries, uint32_t item_bytes, int *swap_lds,
+                       int *sites_lds)
 {
     *swap_lds = 0;
     *sites_lds = 0;
-    auto total = [&](int sw, int si) { return (size_t)lds_layout(N, wr, sw, si).total; };
+    auto total = [&](int sw, int si) { return (size_t)lds_layout(N, wr, sw, si, item_bytes).total; };
     const int base = wgs_per_cu(total(0, 0), bt);
     if (odd && total(0, N) <= kLdsBudget && wgs_per_cu(total(0, N), bt) >= base) *sites_lds = N;
     if (swap_entries > 0 && swap_entries < (1 << 20) && total((int)swap_entries, *sites_lds) <= kLdsBudget &&
@@ -196,10 +197,12 @@ void plan_optional_lds(int N, int wr, int bt, bool odd, int64_t swap_entries, in
 int plan_launch(int N, int NW, const ea_options &opt, int *block_threads, int *words_resident)
 {
     // words resident in LDS
-    const LdsLayout lay = lds_layout(N, 1, 1, 1);
-    if (lay.mask % 8 != 0 || lay.ptab % 16 != 0 || lay.spin % 16 != 0 || lay.thr % 16 != 0 || lay.stab % 4 != 0 || lay.sites % 4 != 0)
+    const uint32_t items = opt.rng == EA_RNG_PLANES ? kPlaneItemBytes : 0u;
+    const LdsLayout lay = lds_layout(N, 1, 1, 1, items);
+    if (lay.mask % 8 != 0 || lay.ptab % 16 != 0 || lay.spin % 16 != 0 || lay.thr % 16 != 0 || lay.stab % 4 != 0 ||
+        lay.sites % 4 != 0 || lay.items % 16 != 0)
         return fail(EA_EINVAL, "internal LDS layout misaligned for %d sites", N);
-    const size_t fixed = lds_layout(N, 0, 0, 0).total;
+    const size_t fixed = lds_layout(N, 0, 0, 0, items).total;
     if (fixed + (size_t)N * 4 > kLdsBudget)
         return fail(EA_EINVAL, "lattice of %d sites does not fit one spin word in LDS", N);
     int wr_max = (int)((kLdsBudget - fixed) / ((size_t)N * 4));
@@ -531,8 +534,9 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
     h.invL = 1.0f / (float)L;
     h.invH = 1.0f / (float)(L / 2 > 0 ? L / 2 : 1);
     s->swap_total = (int64_t)sthr.size();
-    plan_optional_lds(N, wr, bt, L % 2 != 0, s->swap_total, &h.swap_lds, &h.sites_lds);
-    s->lds = lds_layout(N, wr, h.swap_lds, h.sites_lds).total;
+    const uint32_t item_bytes = opt.rng == EA_RNG_PLANES ? kPlaneItemBytes : 0u;
+    plan_optional_lds(N, wr, bt, L % 2 != 0, s->swap_total, item_bytes, &h.swap_lds, &h.sites_lds);
+    s->lds = lds_layout(N, wr, h.swap_lds, h.sites_lds, item_bytes).total;
     s->split_opt = opt.split;
     s->split_parts = choose_split(s, opt.split);
     std::vector<JobDesc> hv(1, h);

@@ -102,6 +102,7 @@ struct LdsLayout {
     uint32_t mask;    // [kMaxTemps] u64 speculative accept bits
     uint32_t ptab;    // [2 words][3 E][32 planes] u32 bit-sliced thresholds by slot (EA_RNG_PLANES)
     uint32_t up;      // [kMaxTemps] i32 spins up per slot (with a field)
+    uint32_t items;   // [kMaxWaves][3][kItemCap] u32 halves still undecided after 8 planes (plane draws)
     uint32_t spin;    // [words][N] u32 spin words
     uint32_t stab;    // [swap_entries] u32 swap tables (optional)
     uint32_t sites;   // [site_entries] u32 packed coordinates (optional)
@@ -109,7 +110,15 @@ struct LdsLayout {
     uint32_t total;
 };
 
-__host__ __device__ inline LdsLayout lds_layout(int N, int words, int swap_entries, int site_entries)
+// Plane draws: every wave keeps up to kItemCap 16-slot halves that 8 planes
+// left undecided, as three u32 fields each, and finishes them 64 at a time
+// once more than kItemFlush wait (kItemFlush + 64 <= kItemCap).
+constexpr int kItemCap = 96;
+constexpr int kItemFlush = 32;
+constexpr uint32_t kPlaneItemBytes = (uint32_t)kMaxWaves * 3u * (uint32_t)kItemCap * 4u;
+
+__host__ __device__ inline LdsLayout lds_layout(int N, int words, int swap_entries, int site_entries,
+                                                uint32_t item_bytes = 0)
 {
     LdsLayout l;
     l.thr = 0;
@@ -125,7 +134,8 @@ __host__ __device__ inline LdsLayout lds_layout(int N, int words, int swap_entri
     l.mask = l.acc + kMaxTemps * 4;
     l.ptab = l.mask + kMaxTemps * 8;
     l.up = l.ptab + 2 * 3 * 32 * 4;
-    l.spin = l.up + kMaxTemps * 4;
+    l.items = l.up + kMaxTemps * 4;
+    l.spin = l.items + item_bytes;
     l.stab = l.spin + (uint32_t)words * (uint32_t)N * 4u;
     l.sites = l.stab + (uint32_t)swap_entries * 4u;
     l.j6 = l.sites + (uint32_t)site_entries * 4u;

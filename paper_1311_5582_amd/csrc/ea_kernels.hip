@@ -136,15 +136,17 @@ struct Smem {
     uint64_t *mask;   // speculative accept bits per pair
     uint32_t *ptab;   // [2][3][32] bit-sliced thresholds by slot (plane draws)
     int32_t *up;      // spins up per slot (with a field)
+    uint32_t *items;  // plane draws: per wave, the halves waiting for more planes
     uint32_t *spin;   // [words_resident][N]
     uint32_t *stab;   // swap tables (when cached)
     uint32_t *sites;  // odd-L site list (when cached)
     uint8_t *j6;      // [N]
 };
 
-__device__ __forceinline__ Smem carve(uint8_t *base, int N, int words, int swap_entries, int site_entries)
+__device__ __forceinline__ Smem carve(uint8_t *base, int N, int words, int swap_entries, int site_entries,
+                                      uint32_t item_bytes)
 {
-    const LdsLayout l = lds_layout(N, words, swap_entries, site_entries);
+    const LdsLayout l = lds_layout(N, words, swap_entries, site_entries, item_bytes);
     Smem s;
     s.thr = (uint32_t *)(base + l.thr);
     s.fthr = (uint32_t *)(base + l.fthr);
@@ -154,6 +156,7 @@ __device__ __forceinline__ Smem carve(uint8_t *base, int N, int words, int swap_
     s.draw = (uint32_t *)(base + l.draw);
     s.ptab = (uint32_t *)(base + l.ptab);
     s.up = (int32_t *)(base + l.up);
+    s.items = (uint32_t *)(base + l.items);
     s.soff = (int32_t *)(base + l.soff);
     s.slen = (int32_t *)(base + l.slen);
     s.ssgn = (int32_t *)(base + l.ssgn);
@@ -222,54 +225,10 @@ __device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c)
 // planes (plane p holds bit 31 - p); plane p of the 16-slot half h is the
 // 16-bit field p & 1 of word (p & 7) >> 1 of block (site, t, r,
 // domain | copy | h << 8 | p >> 3).  `draw < threshold` is decided at the
-// first plane where the two differ, so the slots still undecided (`und`) are
-// compared plane by plane against their thresholds, which pt holds bit-sliced
-// by slot (pt[e * 32 + p] = bit 31 - p of the threshold at E = e, e = 0..2;
-// m1 / m2 select the slots with E = 1 / 2), and the wave stops drawing once
-// every lane is decided.  NH halves starting at global half index h0 (c3
-// already holds it); with NH == 1 the half sits at bit `lo` (0 or 16) of the
-// word.  Returns the slots whose draw is below their threshold.
-template <int NH>
-__device__ __forceinline__ uint32_t camsc_decide_planes(uint32_t und, uint32_t m1, uint32_t m2, const uint32_t *pt,
-                                                        uint32_t site, uint32_t t, uint32_t r, uint32_t c3,
-                                                        uint32_t k0, uint32_t k1, int lo)
-{
-    uint32_t lt = 0;
-    // byte selectors of v_perm_b32: one 16-bit field moved to bit `lo`, other bits 0
-    const uint32_t sel_even = lo ? 0x01000C0Cu : 0x0C0C0100u;
-    const uint32_t sel_odd = lo ? 0x03020C0Cu : 0x0C0C0302u;
-    // two blocks (16 planes) per round: a wave of 64 lanes almost never
-    // decides all its slots within 8 planes, and two independent Philox chains
-    // per half keep the SIMD busy
-#pragma unroll 1
-    for (int g = 0; g < 4; g += 2) {
-        if (__builtin_amdgcn_ballot_w64(und != 0u) == 0ull) break;   // every lane decided
-        const U4 a0 = philox10(site, t, r, c3 + (uint32_t)g, k0, k1);
-        const U4 a1 = philox10(site, t, r, c3 + (uint32_t)g + 1u, k0, k1);
-        U4 b0 = a0, b1 = a1;
-        if (NH == 2) {
-            b0 = philox10(site, t, r, c3 + (1u << 8) + (uint32_t)g, k0, k1);
-            b1 = philox10(site, t, r, c3 + (1u << 8) + (uint32_t)g + 1u, k0, k1);
-        }
-        const uint32_t wa[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-        const uint32_t wb[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
-        const uint32_t *p0 = pt + 8 * g;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            uint32_t R;
-            if (NH == 2)   // low halves of both blocks' word, or high halves: slots 0..15 | 16..31
-                R = __builtin_amdgcn_perm(wb[q >> 1], wa[q >> 1], (q & 1) ? 0x07060302u : 0x05040100u);
-            else
-                R = __builtin_amdgcn_perm(wa[q >> 1], wa[q >> 1], (q & 1) ? sel_odd : sel_even);
-            const uint32_t t01 = (m1 & p0[32 + q]) | (~m1 & p0[q]);
-            const uint32_t T = (m2 & p0[64 + q]) | (~m2 & t01);
-            const uint32_t x = und & (R ^ T);   // decided at this plane
-            lt |= x & T;                        // draw bit 0, threshold bit 1: below
-            und ^= x;
-        }
-    }
-    return lt;
-}
+// first plane where the two differ, so the slots still undecided are compared
+// plane by plane against their thresholds, which ptab holds bit-sliced by slot
+// (pt[e * 32 + p] = bit 31 - p of the threshold at E = e, e = 0..2; m1 / m2
+// select the slots with E = 1 / 2).
 
 // Bit-sliced thresholds by slot for the plane draws, from the rows by slot:
 // ptab[w][e][p] bit b = bit 31 - p of the threshold of slot 32 w + b at E = e
@@ -288,6 +247,174 @@ __device__ __forceinline__ void build_ptab(const Smem &sm, int NW, int wave, int
             sm.ptab[item] = (uint32_t)b;
             if (NW > 1) sm.ptab[96 + item] = (uint32_t)(b >> 32);
         }
+    }
+}
+
+// Plane draws, first round: planes 0..7 of NH halves from one block each
+// (block index 0 of the stream above), for the slots in `und`.  Returns the
+// slots found below their threshold; `und` keeps the slots these planes left
+// undecided (their draw and threshold agree in the top 8 bits; probability
+// 2^-8 each), which finish later from the half's next blocks.
+template <int NH>
+__device__ __forceinline__ uint32_t camsc_planes8(uint32_t &und, uint32_t m1, uint32_t m2, const uint32_t *pt,
+                                                  uint32_t site, uint32_t t, uint32_t r, uint32_t c3, uint32_t k0,
+                                                  uint32_t k1, int lo)
+{
+    uint32_t lt = 0;
+    const uint32_t sel_even = lo ? 0x01000C0Cu : 0x0C0C0100u;
+    const uint32_t sel_odd = lo ? 0x03020C0Cu : 0x0C0C0302u;
+    const U4 a = philox10(site, t, r, c3, k0, k1);
+    U4 b = a;
+    if (NH == 2) b = philox10(site, t, r, c3 + (1u << 8), k0, k1);
+    const uint32_t wa[4] = {a.x, a.y, a.z, a.w};
+    const uint32_t wb[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        uint32_t R;
+        if (NH == 2)
+            R = __builtin_amdgcn_perm(wb[q >> 1], wa[q >> 1], (q & 1) ? 0x07060302u : 0x05040100u);
+        else
+            R = __builtin_amdgcn_perm(wa[q >> 1], wa[q >> 1], (q & 1) ? sel_odd : sel_even);
+        const uint32_t t01 = (m1 & pt[32 + q]) | (~m1 & pt[q]);
+        const uint32_t T = (m2 & pt[64 + q]) | (~m2 & t01);
+        const uint32_t x = und & (R ^ T);
+        lt |= x & T;
+        und ^= x;
+    }
+    return lt;
+}
+
+// A wave's list of halves that the first 8 planes left undecided, in LDS:
+// field 0 = site | local word << 15 | half << 17 | next block << 18, field 1 =
+// undecided slots | E==1 slots << 16, field 2 = E==2 slots (16-bit masks of the
+// half).  Working through them a whole wave at a time keeps the lanes busy:
+// the wave-wide alternative, drawing the next planes for every lane while any
+// lane still needs them, spends most of its Philox blocks on decided slots.
+struct PlaneQueue {
+    uint32_t *f;   // this wave's fields: f[k], f[kItemCap + k], f[2 kItemCap + k]
+    int count;     // halves waiting (uniform across the wave)
+};
+
+__device__ __forceinline__ PlaneQueue plane_queue(const Smem &sm, int wave)
+{
+    PlaneQueue q;
+    q.f = sm.items + wave * 3 * kItemCap;
+    q.count = 0;
+    return q;
+}
+
+// Append this lane's half if it has undecided slots; every lane of the wave calls it.
+__device__ __forceinline__ void plane_push(PlaneQueue &q, uint32_t und16, uint32_t m1_16, uint32_t m2_16, uint32_t key)
+{
+    const uint64_t b = __ballot(und16 != 0u);
+    if (b == 0ull) return;
+    const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+    if (und16 != 0u) {
+        const int pos = q.count + below;
+        q.f[pos] = key;
+        q.f[kItemCap + pos] = und16 | (m1_16 << 16);
+        q.f[2 * kItemCap + pos] = m2_16;
+    }
+    q.count = __builtin_amdgcn_readfirstlane(q.count + (int)__builtin_popcountll(b));
+}
+
+// Take up to 64 waiting halves, one per lane, and compare them against their
+// next 8 planes (block `next block` of the half); xor the flips found into the
+// spin words (other bits than the first round's, so the order is free) and put
+// back the halves still undecided.  A half whose 32 planes all agree has a draw
+// equal to its threshold: not below it, so no flip.  Every lane calls it.
+__device__ __forceinline__ void plane_drain(const Smem &sm, PlaneQueue &q, int lane, int N, int g0, uint32_t t,
+                                            uint32_t r, uint32_t c3base, uint32_t k0, uint32_t k1)
+{
+    const int n = min(q.count, 64);
+    const int base = q.count - n;
+    q.count = base;
+    uint32_t key = 0, und = 0, m1 = 0, m2 = 0;
+    if (lane < n) {
+        key = q.f[base + lane];
+        const uint32_t y = q.f[kItemCap + base + lane];
+        und = y & 0xFFFFu;
+        m1 = y >> 16;
+        m2 = q.f[2 * kItemCap + base + lane];
+    }
+    const uint32_t blk = key >> 18;
+    if (lane < n) {
+        const uint32_t site = key & 0x7FFFu, wl = (key >> 15) & 3u, hb = (key >> 17) & 1u;
+        const uint32_t wg = (uint32_t)g0 + wl;
+        const U4 a = philox10(site, t, r, c3base | ((2u * wg + hb) << 8) | blk, k0, k1);
+        const uint32_t w4[4] = {a.x, a.y, a.z, a.w};
+        const uint32_t *pt = sm.ptab + wg * 96u + 8u * blk;
+        const uint32_t sh = 16u * hb;
+        const uint32_t m0 = ~(m1 | m2);
+        uint32_t lt = 0;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const uint32_t R = (w4[p >> 1] >> (16 * (p & 1))) & 0xFFFFu;
+            const uint32_t T = ((m0 & (pt[p] >> sh)) | (m1 & (pt[32 + p] >> sh)) | (m2 & (pt[64 + p] >> sh))) & 0xFFFFu;
+            const uint32_t x = und & (R ^ T);
+            lt |= x & T;
+            und ^= x;
+        }
+        if (lt) atomicXor(sm.spin + wl * (uint32_t)N + site, lt << sh);
+    }
+    plane_push(q, blk < 3u ? und : 0u, m1, m2, (key & 0x3FFFFu) | ((blk + 1u) << 18));
+}
+
+// One site (all resident words) with plane draws, outside the summing class:
+// the first 8 planes of each half decide here, the rest go to the wave's list.
+// Every lane of the wave calls it; `live` lanes hold a site.
+template <bool SPLIT>
+__device__ __forceinline__ void update_site_planes(const Smem &sm, PlaneQueue &q, bool live, const Nbrs &nb, int N,
+                                                   int gw, int g0, int n_T, uint32_t t, uint32_t r, uint32_t c3base,
+                                                   uint32_t k0, uint32_t k1, int gb, int ngr_own, int lane)
+{
+    const uint32_t j6 = live ? sm.j6[nb.i] : 0u;
+    for (int w = 0; w < gw; ++w) {
+        const int wg = g0 + w;
+        const int left = n_T - wg * 32;
+        uint32_t valid = left >= 32 ? 0xFFFFFFFFu : ((1u << left) - 1u);
+        int h0 = 2 * wg, nh = left > 16 ? 2 : 1, lo = 0;
+        if (SPLIT) {
+            const int a = 4 * gb, b = 4 * (gb + ngr_own) - 1;
+            valid &= (ngr_own >= 8 ? 0xFFFFFFFFu : ((1u << (4 * ngr_own)) - 1u)) << (4 * gb);
+            h0 = 2 * wg + (a >> 4);
+            nh = (b >> 4) - (a >> 4) + 1;
+            lo = nh == 1 ? (a & 16) : 0;
+        }
+        uint32_t und = 0, m1 = 0, m2 = 0;
+        if (live) {
+            uint32_t *sw = sm.spin + (size_t)w * N;
+            const uint32_t S = sw[nb.i];
+            const uint32_t e0 = S ^ sw[nb.xp] ^ (0u - (j6 & 1u));
+            const uint32_t e1 = S ^ sw[nb.xm] ^ (0u - ((j6 >> 1) & 1u));
+            const uint32_t e2 = S ^ sw[nb.yp] ^ (0u - ((j6 >> 2) & 1u));
+            const uint32_t e3 = S ^ sw[nb.ym] ^ (0u - ((j6 >> 3) & 1u));
+            const uint32_t e4 = S ^ sw[nb.zp] ^ (0u - ((j6 >> 4) & 1u));
+            const uint32_t e5 = S ^ sw[nb.zm] ^ (0u - ((j6 >> 5) & 1u));
+            const uint32_t s1 = xor3(e0, e1, e2), c1 = maj3(e0, e1, e2);
+            const uint32_t s2 = xor3(e3, e4, e5), c2 = maj3(e3, e4, e5);
+            const uint32_t E0 = s1 ^ s2, kk = s1 & s2;
+            const uint32_t E1 = xor3(c1, c2, kk), E2 = maj3(c1, c2, kk);
+            const uint32_t always = E2 | (E1 & E0);   // E >= 3
+            m1 = E0 & ~E1;
+            m2 = E1 & ~E0;
+            und = valid & ~always;
+            const uint32_t *pt = sm.ptab + wg * 96;
+            const uint32_t c3 = c3base | ((uint32_t)h0 << 8);
+            const uint32_t lt = nh == 2 ? camsc_planes8<2>(und, m1, m2, pt, nb.i, t, r, c3, k0, k1, 0)
+                                        : camsc_planes8<1>(und, m1, m2, pt, nb.i, t, r, c3, k0, k1, lo);
+            sw[nb.i] = S ^ ((lt | always) & valid);
+        }
+        const uint32_t key = (uint32_t)nb.i | ((uint32_t)w << 15) | (1u << 18);
+        if (nh == 2) {
+            plane_push(q, und & 0xFFFFu, m1 & 0xFFFFu, m2 & 0xFFFFu, key);
+            while (q.count > kItemFlush) plane_drain(sm, q, lane, N, g0, t, r, c3base, k0, k1);
+            plane_push(q, und >> 16, m1 >> 16, m2 >> 16, key | (1u << 17));
+        } else {
+            plane_push(q, (und >> lo) & 0xFFFFu, (m1 >> lo) & 0xFFFFu, (m2 >> lo) & 0xFFFFu,
+                       key | ((uint32_t)(lo >> 4) << 17));
+        }
+        while (q.count > kItemFlush) plane_drain(sm, q, lane, N, g0, t, r, c3base, k0, k1);
     }
 }
 
@@ -514,40 +641,8 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
         const uint32_t e4 = S ^ sw[nb.zp] ^ m[4];
         const uint32_t e5 = S ^ sw[nb.zm] ^ m[5];
         const int wg = __builtin_amdgcn_readfirstlane(g0 + w);
-        if (LAYOUT == 0 && RNG == 1) {
-            // CAMSC with bit-plane draws: E as three bit planes (full adders)
-            const uint32_t s1 = xor3(e0, e1, e2), c1 = maj3(e0, e1, e2);
-            const uint32_t s2 = xor3(e3, e4, e5), c2 = maj3(e3, e4, e5);
-            const uint32_t E0 = s1 ^ s2, kk = s1 & s2;
-            const uint32_t E1 = xor3(c1, c2, kk), E2 = maj3(c1, c2, kk);
-            const uint32_t always = E2 | (E1 & E0);   // E >= 3
-            const int slot0 = wg * 32;
-            const int left = n_T - slot0;
-            uint32_t valid = left >= 32 ? 0xFFFFFFFFu : ((1u << left) - 1u);
-            int h0 = 2 * wg, nh = left > 16 ? 2 : 1, lo = 0;
-            if (SPLIT) {
-                const int a = 4 * gb, b = 4 * (gb + ngr_own) - 1;
-                valid &= (ngr_own >= 8 ? 0xFFFFFFFFu : ((1u << (4 * ngr_own)) - 1u)) << (4 * gb);
-                h0 = 2 * wg + (a >> 4);
-                nh = (b >> 4) - (a >> 4) + 1;
-                lo = nh == 1 ? (a & 16) : 0;
-            }
-            const uint32_t und = valid & ~always;
-            const uint32_t *pt = sm.ptab + wg * 96;
-            const uint32_t c3 = c3base | ((uint32_t)h0 << 8);
-            const uint32_t F = nh == 2 ? camsc_decide_planes<2>(und, E0 & ~E1, E1 & ~E0, pt, nb.i, t, r, c3, k0, k1, 0)
-                                       : camsc_decide_planes<1>(und, E0 & ~E1, E1 & ~E0, pt, nb.i, t, r, c3, k0, k1,
-                                                                lo);
-            const uint32_t flip = (F | always) & valid;
-            sw[nb.i] = S ^ flip;
-            if (ACC) {
-                // unsatisfied bonds after the update: E if kept, 6 - E if flipped;
-                // bit planes of 6 - E: (E0, ~(E1 ^ E0), ~(E2 ^ (E1 & E0)))
-                const uint32_t C1 = (flip & ~(E1 ^ E0)) | (~flip & E1);
-                const uint32_t C2 = (flip & ~(E2 ^ (E1 & E0))) | (~flip & E2);
-                planes_add3<NPC>(*P, E0, C1, C2, np);
-            }
-        } else if (LAYOUT == 0) {
+        if (LAYOUT == 0) {
+            static_assert(RNG == 0, "plane draws update sites through class_pass_planes");
             // CAMSC: sum the six 1-bit bond words as three bit planes (full
             // adders, one bitop3 each), then widen into four 4-bit-segment words
             // (segment j of word k holds slot 4j + k) that carry 2E+S:
@@ -856,13 +951,63 @@ __device__ __forceinline__ void class_pass_ng(const Smem &sm, int c, int tid, in
                                                         c3base, k0, k1, segw, fd, P, np, gb, ngr_own);
 }
 
+// One colour class with plane draws: sites in wave-uniform rounds so that
+// every lane takes part in the list's ballots, then the wave finishes its
+// list before the class barrier.  `slist` = the odd-L site list (NULL:
+// checkerboard class c of an even lattice, `count` sites); otherwise entries
+// first..first+count-1 of it.  ACC (the summing class of an even lattice, one
+// word per site): once the wave's list is empty its sites are final, and each
+// lane adds the unsatisfied incidences of its sites, recounted from the
+// updated spins, into its bit-plane counters.
+template <bool SPLIT, bool ACC = false, int NPC = 0>
+__device__ void class_pass_planes(const Smem &sm, int c, int tid, int nthr, int count, const uint32_t *slist,
+                                  int first, int L, float invH, float invL, int N, int gw, int g0, int n_T, uint32_t t,
+                                  uint32_t r, uint32_t c3base, uint32_t k0, uint32_t k1, int gb, int ngr_own,
+                                  uint32_t (*P)[8] = nullptr, int np = 0)
+{
+    const int lane = tid & 63;
+    PlaneQueue q = plane_queue(sm, tid >> 6);
+    for (int jb = tid - lane; jb < count; jb += nthr) {   // the same trip count for the whole wave
+        const int j = jb + lane;
+        const bool live = j < count;
+        const int jj = live ? j : 0;
+        const Nbrs nb = slist ? neighbours_packed(slist[first + jj], L) : checker_site(jj, c, L, invH, invL);
+        update_site_planes<SPLIT>(sm, q, live, nb, N, gw, g0, n_T, t, r, c3base, k0, k1, gb, ngr_own, lane);
+    }
+    while (q.count > 0) plane_drain(sm, q, lane, N, g0, t, r, c3base, k0, k1);
+    if (ACC) {
+        // a wave's list holds only its own sites: once it is empty they are final
+        for (int j = tid; j < count; j += nthr) {
+            const Nbrs nb = checker_site(j, c, L, invH, invL);
+            const uint32_t j6 = sm.j6[nb.i];
+            const uint32_t *sw = sm.spin;
+            const uint32_t S = sw[nb.i];
+            const uint32_t e0 = S ^ sw[nb.xp] ^ (0u - (j6 & 1u));
+            const uint32_t e1 = S ^ sw[nb.xm] ^ (0u - ((j6 >> 1) & 1u));
+            const uint32_t e2 = S ^ sw[nb.yp] ^ (0u - ((j6 >> 2) & 1u));
+            const uint32_t e3 = S ^ sw[nb.ym] ^ (0u - ((j6 >> 3) & 1u));
+            const uint32_t e4 = S ^ sw[nb.zp] ^ (0u - ((j6 >> 4) & 1u));
+            const uint32_t e5 = S ^ sw[nb.zm] ^ (0u - ((j6 >> 5) & 1u));
+            const uint32_t s1 = xor3(e0, e1, e2), c1 = maj3(e0, e1, e2);
+            const uint32_t s2 = xor3(e3, e4, e5), c2 = maj3(e3, e4, e5);
+            const uint32_t kk = s1 & s2;
+            planes_add3<NPC>(*P, s1 ^ s2, xor3(c1, c2, kk), maj3(c1, c2, kk), np);
+        }
+    }
+}
+
 template <int LAYOUT, bool ACC, bool SPLIT, int RNG, int NPC = 0>
 __device__ __forceinline__ void class_pass(const Smem &sm, int c, int tid, int nthr, int half, int L, float invH,
                                            float invL, int N, int NW, int gw, int g0, int n_T, uint32_t t, uint32_t r,
                                            uint32_t c3base, uint32_t k0, uint32_t k1, uint32_t segw, const Field &fd,
                                            uint32_t (*P)[8], int np, int gb, int ngr_own)
 {
-    if (SPLIT && LAYOUT == 0 && RNG == 0 && NW == 1 && !fd.on) {
+    if constexpr (LAYOUT == 0 && RNG == 1) {
+        class_pass_planes<SPLIT, ACC, NPC>(sm, c, tid, nthr, half, nullptr, 0, L, invH, invL, N, gw, g0, n_T, t, r,
+                                           c3base, k0, k1, gb, ngr_own, P, np);
+        return;
+    } else {
+    if (SPLIT && LAYOUT == 0 && NW == 1 && !fd.on) {
         const int ng = ngr_own;
 #define EA_PASS(G) class_pass_ng<LAYOUT, ACC, SPLIT, RNG, NPC, G>(sm, c, tid, nthr, half, L, invH, invL, N, gw, g0, \
                        n_T, t, r, c3base, k0, k1, segw, fd, P, np, gb, ngr_own)
@@ -877,6 +1022,7 @@ __device__ __forceinline__ void class_pass(const Smem &sm, int c, int tid, int n
     for (int j = tid; j < half; j += nthr)
         update_site<LAYOUT, ACC, SPLIT, RNG, false, NPC>(sm, checker_site(j, c, L, invH, invL), N, gw, g0, n_T, t, r,
                                                         c3base, k0, k1, segw, fd, P, np, gb, ngr_own);
+    }
 }
 
 template <int LAYOUT>
@@ -1010,7 +1156,7 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
         const uint32_t k0 = jd.key0, k1 = jd.key1;
         const uint32_t segw = jd.seg_bits;
         const int n_swap_lds = jd.swap_lds, n_sites_lds = jd.sites_lds;
-        const Smem sm = carve(smem_raw, N, WR, n_swap_lds, n_sites_lds);
+        const Smem sm = carve(smem_raw, N, WR, n_swap_lds, n_sites_lds, RNG == 1 ? kPlaneItemBytes : 0u);
         uint32_t *g_spin = jd.spins + (size_t)ladder * NW * N;
         const int n_groups = (NW + WR - 1) / WR;
 
@@ -1110,10 +1256,14 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                         if (!(fused_energy && swap_now && s == chunk - 1)) __syncthreads();
                     } else {
                         for (int c = 0; c < jd.n_classes; ++c) {
-                            const int end = jd.class_off[c + 1];
-                            for (int it = jd.class_off[c] + tid; it < end; it += nthr)
-                                update_site<LAYOUT, false, false, RNG>(sm, neighbours_packed(slist[it], L), N, gw, g0, n_T, ts, r,
-                                                    c3flip, k0, k1, segw, fd);
+                            const int beg = jd.class_off[c], end = jd.class_off[c + 1];
+                            if constexpr (RNG == 1)
+                                class_pass_planes<false>(sm, c, tid, nthr, end - beg, slist, beg, L, invH, invL, N, gw,
+                                                         g0, n_T, ts, r, c3flip, k0, k1, 0, 0);
+                            else
+                                for (int it = beg + tid; it < end; it += nthr)
+                                    update_site<LAYOUT, false, false, RNG>(sm, neighbours_packed(slist[it], L), N, gw,
+                                                                          g0, n_T, ts, r, c3flip, k0, k1, segw, fd);
                             __syncthreads();
                         }
                     }
@@ -1142,7 +1292,7 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                 // ---- replica-exchange pass after sweep t + chunk - 1 ----
                 const uint32_t tswap = t + (uint32_t)chunk - 1u;
                 const int pairs = n_T - 1;
-                if (PREDRAW) {
+                if constexpr (PREDRAW) {
                     // Wave 0 publishes this workgroup's slot values and draws the
                     // next sweep's first colour class (as every wave does) before
                     // it collects the partners' values; then all waves compute the

@@ -312,3 +312,34 @@ def test_split_choice(L, R, n_T, parts):
     sim = B.Sim(L, inputs.couplings(L, R, 3), inputs.geometric_betas(n_T, 0.5, 2.0), 3)
     assert sim.info()["split_parts"] == parts
     sim.close()
+
+
+@pytest.mark.parametrize("n_T,split", [(64, False), (32, "always")])
+def test_plane_draws_deep_planes(oracle_lib, n_T, split):
+    """Plane draws over enough flip attempts that halves needing planes 16..31
+    occur (a slot's draw and threshold agree in their top 16 bits with
+    probability 2^-16): L=2 with 16 realizations for 3 x 10^4 sweeps is up to
+    5 x 10^8 flip attempts, a few thousand such halves and about ten past
+    plane 24, all finished from the wave's list; every realization bit for bit
+    the oracle's (one oracle thread per realization)."""
+    import threading
+    L, R, seed, sweeps = 2, 16, 8100 + n_T, 30_000
+    J = inputs.couplings(L, R, seed)
+    betas = inputs.geometric_betas(n_T, 0.3, 3.0)
+    sim = B.Sim(L, J, betas, seed, rng="planes", split=split)
+    print(f"[parity] deep planes {sim.info()}", flush=True)
+    sim.sweep(sweeps, 1)
+    s, perm, t = sim.state()
+    E, q = sim.observables()
+    orcs = [oracle_lib.OracleSim(L, J[[r]], betas, seed, rid=np.array([r]), rng="planes") for r in range(R)]
+    ths = [threading.Thread(target=o.sweep, args=(sweeps, 1)) for o in orcs]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    for r, o in enumerate(orcs):
+        assert o.t == t == sweeps
+        assert np.array_equal(perm[r], o.temp_of_slot[0]), f"realization {r}: permutation differs"
+        assert np.array_equal(s[r], o.spins[0]), f"realization {r}: spins differ"
+        Eo, qo = o.observables()
+        assert np.array_equal(E[r], Eo[0]) and np.array_equal(q[r], qo[0])
