@@ -159,11 +159,13 @@ def cpu_baseline(L, n_T, t_min, t_max, seed, sweeps, threads, single_sweeps):
                                       f"PT every sweep ({flips1:.3g} flip attempts, {dt1:.1f} s wall)"}}
 
 
-def bench_other_stream(B, torch, L, J, betas, seed, layout, block_threads, split, rng, sweeps, swap_every, steps):
+def bench_other_stream(B, torch, L, J, betas, seed, layout, block_threads, split, rng, sweeps, swap_every, steps,
+                       site_order="natural"):
     """The same workload and launch with the other flip-draw stream (kernel time
     from HIP events on the launch stream, wall time around the steps)."""
     stream = torch.cuda.Stream()
-    sim = B.Sim(L, J, betas, seed, layout=layout, block_threads=block_threads, stream=stream, split=split, rng=rng)
+    sim = B.Sim(L, J, betas, seed, layout=layout, block_threads=block_threads, stream=stream, split=split, rng=rng,
+                site_order=site_order)
     sim.sweep(sweeps, swap_every)
     sim.observables()
     torch.cuda.synchronize()
@@ -214,7 +216,7 @@ def bench_layout_study(B, torch, inputs, sweeps, steps):
     return out
 
 
-def bench_large(B, inputs, torch, sweeps, steps, rng="words"):
+def bench_large(B, inputs, torch, sweeps, steps, rng="words", site_order="natural"):
     """The large production job (L=24, 256 realizations x 2 copies, 48
     temperatures, PT every 10 sweeps): `steps` launches of `sweeps` sweeps,
     each followed by a measurement of energies and overlaps; kernel time from
@@ -224,7 +226,7 @@ def bench_large(B, inputs, torch, sweeps, steps, rng="words"):
     J = inputs.couplings(L, R, cfg["seed"])
     betas = inputs.geometric_betas(n_T, cfg["t_min"], cfg["t_max"])
     stream = torch.cuda.Stream()
-    sim = B.Sim(L, J, betas, cfg["seed"], stream=stream, rng=rng)
+    sim = B.Sim(L, J, betas, cfg["seed"], stream=stream, rng=rng, site_order=site_order)
     info = sim.info()
     sim.sweep(sweeps, cfg["swap_every"])
     sim.observables()
@@ -245,7 +247,7 @@ def bench_large(B, inputs, torch, sweeps, steps, rng="words"):
     achieved = ops * flips / kern / 1e12
     peak = PEAK_OPS_PER_S / 1e12
     return {"workload": "L24_R256", "L": L, "realizations": R, "copies": 2, "temperatures": n_T,
-            "T_range": [cfg["t_min"], cfg["t_max"]], "swap_every": cfg["swap_every"], "rng": rng,
+            "T_range": [cfg["t_min"], cfg["t_max"]], "swap_every": cfg["swap_every"], "rng": rng, "site_order": site_order,
             "sweeps_per_step": sweeps, "steps": steps, "measurement_per_step": True,
             "block_threads": info["block_threads"], "workgroups_per_ladder": info["split_parts"],
             "ps_per_flip": round(wall / (flips * steps) * 1e12, 4), "ms_per_step": round(wall / steps * 1e3, 4),
@@ -370,6 +372,8 @@ def main():
                     help="also time every spin layout on the L=16 job with PT every 10 sweeps")
     ap.add_argument("--no-other-stream", action="store_true",
                     help="skip timing the same workload with the other flip-draw stream")
+    ap.add_argument("--site-order", default="natural", choices=["natural", "by_class"],
+                    help="order of the spin words in LDS: natural (unified) or by checkerboard class (separated)")
     ap.add_argument("--no-split", action="store_true",
                     help="one workgroup per ladder even when the job has fewer ladders than compute units")
     ap.add_argument("--swap-every", type=int, default=-1, help="override the workload's PT interval")
@@ -435,7 +439,7 @@ def main():
     J = inputs.couplings(L, R, cfg["seed"])
     betas = inputs.geometric_betas(n_T, cfg["t_min"], cfg["t_max"])
     sim = B.Sim(L, J, betas, cfg["seed"], layout=args.layout, block_threads=args.block_threads, stream=stream,
-                split=not args.no_split, rng=args.rng)
+                split=not args.no_split, rng=args.rng, site_order=args.site_order)
     launch = sim.info()
     S, se = args.sweeps_per_step, (cfg["swap_every"] if args.swap_every < 0 else args.swap_every)
 
@@ -491,7 +495,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "L": L, "spins": L ** 3, "realizations": R, "copies": 2,
                    "temperatures": n_T, "T_range": [cfg["t_min"], cfg["t_max"]], "sweeps_per_step": S,
-                   "swap_every": se, "layout": args.layout, "rng": args.rng, "measurement_per_step": True,
+                   "swap_every": se, "layout": args.layout, "rng": args.rng, "site_order": args.site_order,
+                   "measurement_per_step": True,
                    "block_threads": launch["block_threads"], "workgroups_per_ladder": launch["split_parts"],
                    "kernel_ps_per_flip": round(avg_launch_s / flips_per_step * 1e12, 4),
                    "paper_ps_per_flip_gtx580": 33.5},
@@ -505,15 +510,16 @@ def main():
     if not args.no_other_stream and args.layout == "camsc":
         other = "planes" if args.rng == "words" else "words"
         out["other_stream"] = bench_other_stream(B, torch, L, J, betas, cfg["seed"], args.layout, args.block_threads,
-                                                 not args.no_split, other, S, se, 3)
+                                                 not args.no_split, other, S, se, 3, args.site_order)
     if "other_stream" in out:
         progress(f"other stream: {out['other_stream']['ps_per_flip']} ps/flip")
     if args.layout_study:
         out["layout_study_kernel_ps_per_flip"] = bench_layout_study(B, torch, inputs, 200, 3)
         progress("layout study done")
     if not args.no_large:
-        out["large"] = bench_large(B, inputs, torch, args.large_sweeps, args.large_steps)
-        out["large_planes"] = bench_large(B, inputs, torch, args.large_sweeps, args.large_steps, rng="planes")
+        out["large"] = bench_large(B, inputs, torch, args.large_sweeps, args.large_steps, site_order=args.site_order)
+        out["large_planes"] = bench_large(B, inputs, torch, args.large_sweeps, args.large_steps, rng="planes",
+                                          site_order=args.site_order)
         progress(f"L24_R256: {out['large']['ps_per_flip']} / planes {out['large_planes']['ps_per_flip']} ps/flip")
     if not args.no_batched:
         out["batched"] = bench_batched(B, inputs, torch, args.batched_sweeps, args.batched_steps)

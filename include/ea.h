@@ -113,7 +113,17 @@ typedef struct ea_options {
     void *(*dev_alloc)(size_t bytes, void *ctx);
     void (*dev_free)(void *ptr, void *ctx);
     void *alloc_ctx;
+    int site_order;      /* order of the spin words and coupling bytes in the workgroup's
+                            scratchpad, after the allocation schemes of Sec. 4.2.1:
+                            EA_ORDER_NATURAL (default; the "unified" lattice) or
+                            EA_ORDER_BY_CLASS (the "separated" one: each checkerboard
+                            class contiguous, CAMSC and even L only; such a job runs
+                            only in launches of its own: ea_sweep, a one-job batch
+                            or plan, EA_EINVAL in a mix).  Results never depend on it  */
 } ea_options;
+
+#define EA_ORDER_NATURAL  0
+#define EA_ORDER_BY_CLASS 1
 
 /* Fill *opt with the defaults (CAMSC, library-chosen launch, default stream,
  * hipMalloc). */

@@ -37,6 +37,7 @@ class Options(ctypes.Structure):
         ("words_resident", ctypes.c_int), ("split", ctypes.c_int), ("rng", ctypes.c_int),
         ("field", ctypes.c_double), ("stream", ctypes.c_void_p),
         ("dev_alloc", _ALLOC_FN), ("dev_free", _FREE_FN), ("alloc_ctx", ctypes.c_void_p),
+        ("site_order", ctypes.c_int),
     ]
 
 
@@ -208,7 +209,7 @@ class Sim:
     """One job: R realizations x 2 copies x n_T temperature slots on the GPU."""
 
     def __init__(self, L, couplings, betas, seed, layout="camsc", block_threads=0, words_resident=0,
-                 stream=None, torch_memory=True, split=True, rng="words", h=0.0):
+                 stream=None, torch_memory=True, split=True, rng="words", h=0.0, site_order="natural"):
         L = int(L)
         J = np.ascontiguousarray(couplings, dtype=np.int8)
         if J.ndim != 3 or J.shape[1:] != (L ** 3, 3):
@@ -223,6 +224,7 @@ class Sim:
         opt.split = {True: 0, "auto": 0, False: 1, "never": 1, "always": 2}[split]
         opt.rng = RNGS[rng] if isinstance(rng, str) else int(rng)
         opt.field = float(h)
+        opt.site_order = {"natural": 0, "by_class": 1}[site_order] if isinstance(site_order, str) else int(site_order)
         self._alloc = None
         torch = _torch_gpu() if (torch_memory or stream is not None) else None
         if stream is not None:

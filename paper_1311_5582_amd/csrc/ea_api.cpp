@@ -409,6 +409,10 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
     if (opt.rng == EA_RNG_PLANES && opt.field != 0.0) return fail(EA_EINVAL, "plane draws need field 0");
     if ((opt.dev_alloc == nullptr) != (opt.dev_free == nullptr))
         return fail(EA_EINVAL, "dev_alloc and dev_free must be given together");
+    if (opt.site_order != EA_ORDER_NATURAL && opt.site_order != EA_ORDER_BY_CLASS)
+        return fail(EA_EINVAL, "unknown site_order %d", opt.site_order);
+    if (opt.site_order == EA_ORDER_BY_CLASS && (opt.layout != EA_LAYOUT_CAMSC || (L & 1)))
+        return fail(EA_EINVAL, "site_order by class needs the CAMSC layout and even L");
     for (int k = 0; k < n_T; ++k)
         if (!std::isfinite(betas[k]) || !(betas[k] > 0.0))
             return fail(EA_EINVAL, "betas[%d]=%g must be finite and > 0", k, betas[k]);
@@ -531,6 +535,7 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
     h.always_add1 = (uint32_t)(8 - a_first[1]) * 0x11111111u;
     h.always_col0 = 2 * a_first[0];
     h.always_col1 = 2 * a_first[1] + 1;
+    h.site_order = opt.site_order;
     h.invL = 1.0f / (float)L;
     h.invH = 1.0f / (float)(L / 2 > 0 ? L / 2 : 1);
     s->swap_total = (int64_t)sthr.size();

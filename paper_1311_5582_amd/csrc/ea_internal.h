@@ -82,7 +82,7 @@ struct JobDesc {
     uint32_t always_add1;     //   a_S = smallest E whose flip is certain for spin bit S
     int32_t always_col0;      // the same as a column 2E+S: certain iff 2E+S >= always_col[S]
     int32_t always_col1;
-    int32_t pad_;
+    int32_t site_order;       // LDS order of spin words and coupling bytes: 0 natural, 1 by colour class (even L)
 };
 
 // Dynamic LDS carve-up of the sweep kernel, one definition for host and
@@ -155,8 +155,9 @@ inline int kernel_variant(int layout, int rng)
 // persistent workgroups pull ladders from queue[0]; parts = 2 or 4 (CAMSC
 // jobs with one word per site and even L): `parts` workgroups per ladder,
 // tickets from queue[blockIdx % 8], grid = split_grid(n_units, parts).
+// sep = 1: spin words in LDS by colour class (one CAMSC job only).
 hipError_t launch_sweep(const JobDesc *d_jobs, int n_jobs, const uint32_t *d_units, int n_units,
-                        uint32_t *d_queue, int kv, int parts, int block_threads, size_t lds, int grid,
+                        uint32_t *d_queue, int kv, int parts, int sep, int block_threads, size_t lds, int grid,
                         hipStream_t s);
 // Workgroups of a split launch: every queue gets as many as its ladders have parts.
 inline int split_grid(int n_units, int parts) { return (n_units + 7) / 8 * 8 * parts; }

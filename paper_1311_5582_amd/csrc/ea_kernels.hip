@@ -74,9 +74,12 @@ __device__ __forceinline__ uint32_t field4(uint32_t x, int shift, uint32_t width
     return __builtin_amdgcn_ubfe(x, (uint32_t)shift, width);
 }
 
-// Site index and the six neighbour indices (periodic).
+// A site's LDS word index, its six neighbours' LDS word indices (periodic),
+// and its natural index g = x + L(y + Lz), which keys the random stream.  In
+// the natural order the LDS index is g.
 struct Nbrs {
     int i, xp, xm, yp, ym, zp, zm;
+    int g;
 };
 
 __device__ __forceinline__ Nbrs neighbours(int x, int y, int z, int L)
@@ -84,6 +87,7 @@ __device__ __forceinline__ Nbrs neighbours(int x, int y, int z, int L)
     const int LL = L * L;
     Nbrs n;
     n.i = x + L * y + LL * z;
+    n.g = n.i;
     n.xp = (x == L - 1) ? n.i - (L - 1) : n.i + 1;
     n.xm = (x == 0) ? n.i + (L - 1) : n.i - 1;
     n.yp = (y == L - 1) ? n.i - (L - 1) * L : n.i + L;
@@ -123,6 +127,61 @@ __device__ __forceinline__ Nbrs natural_site(int i, int L, float invL)
     return neighbours(i - w * L, w - z * L, z, L);
 }
 
+// Natural index of item j of checkerboard class c (even L).
+__device__ __forceinline__ int checker_index(int j, int c, int L, float invH, float invL)
+{
+    const int w = qdiv(j, invH);
+    const int xh = j - w * (L >> 1);
+    const int z = qdiv(w, invL);
+    const int y = w - z * L;
+    return 2 * xh + ((c + y + z) & 1) + L * w;
+}
+
+// LDS order of the spin words and coupling bytes of an even lattice:
+// natural (sep = 0: word g at g), or by colour class (sep = 1: class c in words
+// c N/2 .. c N/2 + N/2 - 1, the class-c site g at c N/2 + g / 2, which is its
+// position j in checker_site's enumeration).  By class, the sites that
+// consecutive threads update are consecutive words, and so are their
+// neighbours along x.
+struct Order {
+    int sep, nh;   // nh = N / 2
+};
+
+// Item j of class c with LDS indices in order SEP.
+template <int SEP>
+__device__ __forceinline__ Nbrs class_site(const Order &o, int j, int c, int L, float invH, float invL)
+{
+    Nbrs n = checker_site(j, c, L, invH, invL);
+    if (SEP) {
+        const int other = (1 - c) * o.nh;
+        n.i = c * o.nh + j;
+        n.xp = other + (n.xp >> 1);
+        n.xm = other + (n.xm >> 1);
+        n.yp = other + (n.yp >> 1);
+        n.ym = other + (n.ym >> 1);
+        n.zp = other + (n.zp >> 1);
+        n.zm = other + (n.zm >> 1);
+    }
+    return n;
+}
+
+
+// Natural index of LDS word k.
+__device__ __forceinline__ int natural_of(const Order &o, int k, int L, float invH, float invL)
+{
+    if (!o.sep) return k;
+    const int c = k >= o.nh ? 1 : 0;
+    return checker_index(k - c * o.nh, c, L, invH, invL);
+}
+
+// Site of LDS word k with LDS indices (any order; for whole-lattice passes).
+__device__ __forceinline__ Nbrs lds_site(const Order &o, int k, int L, float invH, float invL)
+{
+    if (!o.sep) return natural_site(k, L, invL);
+    const int c = k >= o.nh ? 1 : 0;
+    return class_site<1>(o, k - c * o.nh, c, L, invH, invL);
+}
+
 // LDS regions of the sweep kernel (offsets from lds_layout()).
 struct Smem {
     uint32_t *thr;    // [kMaxTemps][kThrCols] rows by slot
@@ -141,10 +200,11 @@ struct Smem {
     uint32_t *stab;   // swap tables (when cached)
     uint32_t *sites;  // odd-L site list (when cached)
     uint8_t *j6;      // [N]
+    Order ord;        // LDS order of spin words and coupling bytes
 };
 
 __device__ __forceinline__ Smem carve(uint8_t *base, int N, int words, int swap_entries, int site_entries,
-                                      uint32_t item_bytes)
+                                      uint32_t item_bytes, int sep)
 {
     const LdsLayout l = lds_layout(N, words, swap_entries, site_entries, item_bytes);
     Smem s;
@@ -166,6 +226,8 @@ __device__ __forceinline__ Smem carve(uint8_t *base, int N, int words, int swap_
     s.stab = (uint32_t *)(base + l.stab);
     s.sites = (uint32_t *)(base + l.sites);
     s.j6 = base + l.j6;
+    s.ord.sep = sep;
+    s.ord.nh = N >> 1;
     return s;
 }
 
@@ -323,8 +385,8 @@ __device__ __forceinline__ void plane_push(PlaneQueue &q, uint32_t und16, uint32
 // spin words (other bits than the first round's, so the order is free) and put
 // back the halves still undecided.  A half whose 32 planes all agree has a draw
 // equal to its threshold: not below it, so no flip.  Every lane calls it.
-__device__ __forceinline__ void plane_drain(const Smem &sm, PlaneQueue &q, int lane, int N, int g0, uint32_t t,
-                                            uint32_t r, uint32_t c3base, uint32_t k0, uint32_t k1)
+__device__ __forceinline__ void plane_drain(const Smem &sm, PlaneQueue &q, int lane, int N, int g0, int cls,
+                                            uint32_t t, uint32_t r, uint32_t c3base, uint32_t k0, uint32_t k1)
 {
     const int n = min(q.count, 64);
     const int base = q.count - n;
@@ -355,7 +417,8 @@ __device__ __forceinline__ void plane_drain(const Smem &sm, PlaneQueue &q, int l
             lt |= x & T;
             und ^= x;
         }
-        if (lt) atomicXor(sm.spin + wl * (uint32_t)N + site, lt << sh);
+        const uint32_t at = sm.ord.sep ? (uint32_t)(cls * sm.ord.nh) + (site >> 1) : site;   // LDS word of the site
+        if (lt) atomicXor(sm.spin + wl * (uint32_t)N + at, lt << sh);
     }
     plane_push(q, blk < 3u ? und : 0u, m1, m2, (key & 0x3FFFFu) | ((blk + 1u) << 18));
 }
@@ -365,8 +428,9 @@ __device__ __forceinline__ void plane_drain(const Smem &sm, PlaneQueue &q, int l
 // Every lane of the wave calls it; `live` lanes hold a site.
 template <bool SPLIT>
 __device__ __forceinline__ void update_site_planes(const Smem &sm, PlaneQueue &q, bool live, const Nbrs &nb, int N,
-                                                   int gw, int g0, int n_T, uint32_t t, uint32_t r, uint32_t c3base,
-                                                   uint32_t k0, uint32_t k1, int gb, int ngr_own, int lane)
+                                                   int gw, int g0, int cls, int n_T, uint32_t t, uint32_t r,
+                                                   uint32_t c3base, uint32_t k0, uint32_t k1, int gb, int ngr_own,
+                                                   int lane)
 {
     const uint32_t j6 = live ? sm.j6[nb.i] : 0u;
     for (int w = 0; w < gw; ++w) {
@@ -401,20 +465,20 @@ __device__ __forceinline__ void update_site_planes(const Smem &sm, PlaneQueue &q
             und = valid & ~always;
             const uint32_t *pt = sm.ptab + wg * 96;
             const uint32_t c3 = c3base | ((uint32_t)h0 << 8);
-            const uint32_t lt = nh == 2 ? camsc_planes8<2>(und, m1, m2, pt, nb.i, t, r, c3, k0, k1, 0)
-                                        : camsc_planes8<1>(und, m1, m2, pt, nb.i, t, r, c3, k0, k1, lo);
+            const uint32_t lt = nh == 2 ? camsc_planes8<2>(und, m1, m2, pt, nb.g, t, r, c3, k0, k1, 0)
+                                        : camsc_planes8<1>(und, m1, m2, pt, nb.g, t, r, c3, k0, k1, lo);
             sw[nb.i] = S ^ ((lt | always) & valid);
         }
-        const uint32_t key = (uint32_t)nb.i | ((uint32_t)w << 15) | (1u << 18);
+        const uint32_t key = (uint32_t)nb.g | ((uint32_t)w << 15) | (1u << 18);
         if (nh == 2) {
             plane_push(q, und & 0xFFFFu, m1 & 0xFFFFu, m2 & 0xFFFFu, key);
-            while (q.count > kItemFlush) plane_drain(sm, q, lane, N, g0, t, r, c3base, k0, k1);
+            while (q.count > kItemFlush) plane_drain(sm, q, lane, N, g0, cls, t, r, c3base, k0, k1);
             plane_push(q, und >> 16, m1 >> 16, m2 >> 16, key | (1u << 17));
         } else {
             plane_push(q, (und >> lo) & 0xFFFFu, (m1 >> lo) & 0xFFFFu, (m2 >> lo) & 0xFFFFu,
                        key | ((uint32_t)(lo >> 4) << 17));
         }
-        while (q.count > kItemFlush) plane_drain(sm, q, lane, N, g0, t, r, c3base, k0, k1);
+        while (q.count > kItemFlush) plane_drain(sm, q, lane, N, g0, cls, t, r, c3base, k0, k1);
     }
 }
 
@@ -683,21 +747,21 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
             uint32_t F;
             if (SPLIT) {   // a split ladder owns at most four groups
                 switch (ngr) {
-                    case 4: F = camsc_decide<4, PRE>(X, rows, nb.i, c, pre); break;
-                    case 3: F = camsc_decide<3, PRE>(X, rows, nb.i, c, pre); break;
-                    case 2: F = camsc_decide<2, PRE>(X, rows, nb.i, c, pre); break;
-                    default: F = camsc_decide<1, PRE>(X, rows, nb.i, c, pre); break;
+                    case 4: F = camsc_decide<4, PRE>(X, rows, nb.g, c, pre); break;
+                    case 3: F = camsc_decide<3, PRE>(X, rows, nb.g, c, pre); break;
+                    case 2: F = camsc_decide<2, PRE>(X, rows, nb.g, c, pre); break;
+                    default: F = camsc_decide<1, PRE>(X, rows, nb.g, c, pre); break;
                 }
             } else {
                 switch (ngr) {
-                    case 8: F = camsc_decide<8>(X, rows, nb.i, c); break;
-                    case 7: F = camsc_decide<7>(X, rows, nb.i, c); break;
-                    case 6: F = camsc_decide<6>(X, rows, nb.i, c); break;
-                    case 5: F = camsc_decide<5>(X, rows, nb.i, c); break;
-                    case 4: F = camsc_decide<4>(X, rows, nb.i, c); break;
-                    case 3: F = camsc_decide<3>(X, rows, nb.i, c); break;
-                    case 2: F = camsc_decide<2>(X, rows, nb.i, c); break;
-                    default: F = camsc_decide<1>(X, rows, nb.i, c); break;
+                    case 8: F = camsc_decide<8>(X, rows, nb.g, c); break;
+                    case 7: F = camsc_decide<7>(X, rows, nb.g, c); break;
+                    case 6: F = camsc_decide<6>(X, rows, nb.g, c); break;
+                    case 5: F = camsc_decide<5>(X, rows, nb.g, c); break;
+                    case 4: F = camsc_decide<4>(X, rows, nb.g, c); break;
+                    case 3: F = camsc_decide<3>(X, rows, nb.g, c); break;
+                    case 2: F = camsc_decide<2>(X, rows, nb.g, c); break;
+                    default: F = camsc_decide<1>(X, rows, nb.g, c); break;
                 }
             }
             if (SPLIT) F <<= 4 * gb;
@@ -720,7 +784,7 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
             const uint32_t valid = left >= 8 ? M : (M & ((1u << (4 * left)) - 1u));
             const uint32_t *rows = sm.thr + slot0 * kThrCols;
             const Ctr c{t, r, c3base + (uint32_t)(wg * 2), k0, k1, segw};
-            const uint32_t F = left > 4 ? amsc4_decide<2>(X, rows, nb.i, c) : amsc4_decide<1>(X, rows, nb.i, c);
+            const uint32_t F = left > 4 ? amsc4_decide<2>(X, rows, nb.g, c) : amsc4_decide<1>(X, rows, nb.g, c);
             sw[nb.i] = S ^ ((F | always) & valid);
         } else {
             // AMSC3 / AMSC1 (Sec. 4.3.3): 2E+S is joined slot by slot.  AMSC3
@@ -740,7 +804,7 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
                 const int slot = slot0 + j;
                 if ((slot >> 2) != cur) {   // uniform across the wave
                     cur = slot >> 2;
-                    blk = philox10(nb.i, t, r, c3base + (uint32_t)cur, k0, k1);
+                    blk = philox10(nb.g, t, r, c3base + (uint32_t)cur, k0, k1);
                 }
                 uint32_t E;
                 if (LAYOUT == 2)
@@ -773,8 +837,8 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
 // vector work plus one LDS atomic per wave.
 // ---------------------------------------------------------------------------
 template <int LAYOUT, int NP>
-__device__ void count_unsat_word_np(const uint32_t *words, const uint8_t *j6, int N, int L, float invL, int slot0,
-                                    int n_T, int *U)
+__device__ void count_unsat_word_np(const Order &o, const uint32_t *words, const uint8_t *j6, int N, int L, float invH,
+                                    float invL, int slot0, int n_T, int *U)
 {
     constexpr int SPW = Layout<LAYOUT>::kSlotsPerWord;
     constexpr int STR = Layout<LAYOUT>::kStride;
@@ -783,7 +847,7 @@ __device__ void count_unsat_word_np(const uint32_t *words, const uint8_t *j6, in
 #pragma unroll
     for (int p = 0; p < 14; ++p) P[p] = 0;
     for (int idx = threadIdx.x; idx < N; idx += blockDim.x) {
-        const Nbrs nb = natural_site(idx, L, invL);
+        const Nbrs nb = lds_site(o, idx, L, invH, invL);
         const uint32_t S = words[nb.i];
         const uint32_t jb = j6[nb.i];
         const uint32_t ex = S ^ words[nb.xp] ^ ((0u - (jb & 1u)) & keep);
@@ -918,7 +982,7 @@ __device__ __forceinline__ void update_pair_camsc(const Smem &sm, const Nbrs &na
 #pragma unroll
             for (int k = 0; k < 4; ++k) X[k] >>= 4 * gb;
         }
-        uint32_t F = camsc_decide<NG, PRE>(X, rows, (uint32_t)nn[q].i, c, q == 0 ? prea : preb);
+        uint32_t F = camsc_decide<NG, PRE>(X, rows, (uint32_t)nn[q].g, c, q == 0 ? prea : preb);
         if (SPLIT) F <<= 4 * gb;
         const uint32_t flip = (F | always) & valid;
         out[q] = S[q] ^ flip;
@@ -935,7 +999,7 @@ __device__ __forceinline__ void update_pair_camsc(const Smem &sm, const Nbrs &na
 // One colour class of an even lattice: a split ladder with word draws and no
 // field takes the sites of a thread two at a time, everything else one at a
 // time (pairing measured slower where a workgroup holds the whole ladder).
-template <int LAYOUT, bool ACC, bool SPLIT, int RNG, int NPC, int NG>
+template <int LAYOUT, bool ACC, bool SPLIT, int RNG, int NPC, int NG, int SEP>
 __device__ __forceinline__ void class_pass_ng(const Smem &sm, int c, int tid, int nthr, int half, int L, float invH,
                                               float invL, int N, int gw, int g0, int n_T, uint32_t t, uint32_t r,
                                               uint32_t c3base, uint32_t k0, uint32_t k1, uint32_t segw,
@@ -943,11 +1007,12 @@ __device__ __forceinline__ void class_pass_ng(const Smem &sm, int c, int tid, in
 {
     int j = tid;
     for (; j + nthr < half; j += 2 * nthr)
-        update_pair_camsc<ACC, SPLIT, NG, NPC>(sm, checker_site(j, c, L, invH, invL),
-                                               checker_site(j + nthr, c, L, invH, invL), n_T, t, r, c3base, k0, k1,
+        update_pair_camsc<ACC, SPLIT, NG, NPC>(sm, class_site<SEP>(sm.ord, j, c, L, invH, invL),
+                                               class_site<SEP>(sm.ord, j + nthr, c, L, invH, invL), n_T, t, r, c3base,
+                                               k0, k1,
                                                segw, P, np, gb, ngr_own);
     if (j < half)
-        update_site<LAYOUT, ACC, SPLIT, RNG, false, NPC>(sm, checker_site(j, c, L, invH, invL), N, gw, g0, n_T, t, r,
+        update_site<LAYOUT, ACC, SPLIT, RNG, false, NPC>(sm, class_site<SEP>(sm.ord, j, c, L, invH, invL), N, gw, g0, n_T, t, r,
                                                         c3base, k0, k1, segw, fd, P, np, gb, ngr_own);
 }
 
@@ -959,7 +1024,7 @@ __device__ __forceinline__ void class_pass_ng(const Smem &sm, int c, int tid, in
 // word per site): once the wave's list is empty its sites are final, and each
 // lane adds the unsatisfied incidences of its sites, recounted from the
 // updated spins, into its bit-plane counters.
-template <bool SPLIT, bool ACC = false, int NPC = 0>
+template <bool SPLIT, bool ACC = false, int NPC = 0, int SEP = 0>
 __device__ void class_pass_planes(const Smem &sm, int c, int tid, int nthr, int count, const uint32_t *slist,
                                   int first, int L, float invH, float invL, int N, int gw, int g0, int n_T, uint32_t t,
                                   uint32_t r, uint32_t c3base, uint32_t k0, uint32_t k1, int gb, int ngr_own,
@@ -971,14 +1036,14 @@ __device__ void class_pass_planes(const Smem &sm, int c, int tid, int nthr, int 
         const int j = jb + lane;
         const bool live = j < count;
         const int jj = live ? j : 0;
-        const Nbrs nb = slist ? neighbours_packed(slist[first + jj], L) : checker_site(jj, c, L, invH, invL);
-        update_site_planes<SPLIT>(sm, q, live, nb, N, gw, g0, n_T, t, r, c3base, k0, k1, gb, ngr_own, lane);
+        const Nbrs nb = slist ? neighbours_packed(slist[first + jj], L) : class_site<SEP>(sm.ord, jj, c, L, invH, invL);
+        update_site_planes<SPLIT>(sm, q, live, nb, N, gw, g0, c, n_T, t, r, c3base, k0, k1, gb, ngr_own, lane);
     }
-    while (q.count > 0) plane_drain(sm, q, lane, N, g0, t, r, c3base, k0, k1);
+    while (q.count > 0) plane_drain(sm, q, lane, N, g0, c, t, r, c3base, k0, k1);
     if (ACC) {
         // a wave's list holds only its own sites: once it is empty they are final
         for (int j = tid; j < count; j += nthr) {
-            const Nbrs nb = checker_site(j, c, L, invH, invL);
+            const Nbrs nb = class_site<SEP>(sm.ord, j, c, L, invH, invL);
             const uint32_t j6 = sm.j6[nb.i];
             const uint32_t *sw = sm.spin;
             const uint32_t S = sw[nb.i];
@@ -996,20 +1061,20 @@ __device__ void class_pass_planes(const Smem &sm, int c, int tid, int nthr, int 
     }
 }
 
-template <int LAYOUT, bool ACC, bool SPLIT, int RNG, int NPC = 0>
+template <int LAYOUT, bool ACC, bool SPLIT, int RNG, int NPC = 0, int SEP = 0>
 __device__ __forceinline__ void class_pass(const Smem &sm, int c, int tid, int nthr, int half, int L, float invH,
                                            float invL, int N, int NW, int gw, int g0, int n_T, uint32_t t, uint32_t r,
                                            uint32_t c3base, uint32_t k0, uint32_t k1, uint32_t segw, const Field &fd,
                                            uint32_t (*P)[8], int np, int gb, int ngr_own)
 {
     if constexpr (LAYOUT == 0 && RNG == 1) {
-        class_pass_planes<SPLIT, ACC, NPC>(sm, c, tid, nthr, half, nullptr, 0, L, invH, invL, N, gw, g0, n_T, t, r,
-                                           c3base, k0, k1, gb, ngr_own, P, np);
+        class_pass_planes<SPLIT, ACC, NPC, SEP>(sm, c, tid, nthr, half, nullptr, 0, L, invH, invL, N, gw, g0, n_T, t,
+                                                r, c3base, k0, k1, gb, ngr_own, P, np);
         return;
     } else {
     if (SPLIT && LAYOUT == 0 && NW == 1 && !fd.on) {
         const int ng = ngr_own;
-#define EA_PASS(G) class_pass_ng<LAYOUT, ACC, SPLIT, RNG, NPC, G>(sm, c, tid, nthr, half, L, invH, invL, N, gw, g0, \
+#define EA_PASS(G) class_pass_ng<LAYOUT, ACC, SPLIT, RNG, NPC, G, SEP>(sm, c, tid, nthr, half, L, invH, invL, N, gw, g0, \
                        n_T, t, r, c3base, k0, k1, segw, fd, P, np, gb, ngr_own)
         switch (ng) {
             case 1: EA_PASS(1); return;
@@ -1020,25 +1085,27 @@ __device__ __forceinline__ void class_pass(const Smem &sm, int c, int tid, int n
 #undef EA_PASS
     }
     for (int j = tid; j < half; j += nthr)
-        update_site<LAYOUT, ACC, SPLIT, RNG, false, NPC>(sm, checker_site(j, c, L, invH, invL), N, gw, g0, n_T, t, r,
+        update_site<LAYOUT, ACC, SPLIT, RNG, false, NPC>(sm, class_site<SEP>(sm.ord, j, c, L, invH, invL), N, gw, g0, n_T, t, r,
                                                         c3base, k0, k1, segw, fd, P, np, gb, ngr_own);
     }
 }
 
 template <int LAYOUT>
-__device__ __forceinline__ void count_unsat_word(const uint32_t *words, const uint8_t *j6, int N, int L, float invL,
+__device__ __forceinline__ void count_unsat_word(const Order &o, const uint32_t *words, const uint8_t *j6, int N, int L,
+                                                 float invH, float invL,
                                                  int slot0, int n_T, int np, int *U)
 {
     switch (np) {
-        case 2: count_unsat_word_np<LAYOUT, 2>(words, j6, N, L, invL, slot0, n_T, U); break;
-        case 3: count_unsat_word_np<LAYOUT, 3>(words, j6, N, L, invL, slot0, n_T, U); break;
-        case 4: count_unsat_word_np<LAYOUT, 4>(words, j6, N, L, invL, slot0, n_T, U); break;
-        case 5: count_unsat_word_np<LAYOUT, 5>(words, j6, N, L, invL, slot0, n_T, U); break;
-        case 6: count_unsat_word_np<LAYOUT, 6>(words, j6, N, L, invL, slot0, n_T, U); break;
-        case 7: count_unsat_word_np<LAYOUT, 7>(words, j6, N, L, invL, slot0, n_T, U); break;
-        default: count_unsat_word_np<LAYOUT, 8>(words, j6, N, L, invL, slot0, n_T, U); break;
+        case 2: count_unsat_word_np<LAYOUT, 2>(o, words, j6, N, L, invH, invL, slot0, n_T, U); break;
+        case 3: count_unsat_word_np<LAYOUT, 3>(o, words, j6, N, L, invH, invL, slot0, n_T, U); break;
+        case 4: count_unsat_word_np<LAYOUT, 4>(o, words, j6, N, L, invH, invL, slot0, n_T, U); break;
+        case 5: count_unsat_word_np<LAYOUT, 5>(o, words, j6, N, L, invH, invL, slot0, n_T, U); break;
+        case 6: count_unsat_word_np<LAYOUT, 6>(o, words, j6, N, L, invH, invL, slot0, n_T, U); break;
+        case 7: count_unsat_word_np<LAYOUT, 7>(o, words, j6, N, L, invH, invL, slot0, n_T, U); break;
+        default: count_unsat_word_np<LAYOUT, 8>(o, words, j6, N, L, invH, invL, slot0, n_T, U); break;
     }
 }
+
 
 // Spins up per slot for one word, added into U[slot0 + b] (the same plane
 // counters and wave reduction as the bond counts, one bit per site).
@@ -1097,7 +1164,7 @@ __device__ __forceinline__ void count_up_word(const uint32_t *words, int N, int 
 // ---------------------------------------------------------------------------
 constexpr uint32_t kSpinLimit = 1u << 20;   // polls of a partner's flag before giving up
 
-template <int LAYOUT, int PARTS, int RNG, bool UNITS = false>
+template <int LAYOUT, int PARTS, int RNG, bool UNITS = false, int SEP = 0>
 __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restrict__ jobs,
                                                           const uint32_t *__restrict__ units, int n_units,
                                                           uint32_t *queue)
@@ -1109,6 +1176,7 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
     constexpr bool PREDRAW = SPLIT && RNG == 0;
     static_assert(!SPLIT || LAYOUT == 0, "split ladders are CAMSC only");
     static_assert(RNG == 0 || LAYOUT == 0, "plane draws are CAMSC only");
+    static_assert(SEP == 0 || (LAYOUT == 0 && !UNITS), "the class order runs lone CAMSC launches only");
     extern __shared__ __align__(16) uint8_t smem_raw[];
     __shared__ uint32_t s_next;
 
@@ -1156,13 +1224,13 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
         const uint32_t k0 = jd.key0, k1 = jd.key1;
         const uint32_t segw = jd.seg_bits;
         const int n_swap_lds = jd.swap_lds, n_sites_lds = jd.sites_lds;
-        const Smem sm = carve(smem_raw, N, WR, n_swap_lds, n_sites_lds, RNG == 1 ? kPlaneItemBytes : 0u);
+        const Smem sm = carve(smem_raw, N, WR, n_swap_lds, n_sites_lds, RNG == 1 ? kPlaneItemBytes : 0u, SEP);
         uint32_t *g_spin = jd.spins + (size_t)ladder * NW * N;
         const int n_groups = (NW + WR - 1) / WR;
 
         // couplings, tables and permutation of this ladder
         const uint8_t *g_j6 = jd.j6 + (size_t)r * N;
-        for (int idx = tid; idx < N; idx += nthr) sm.j6[idx] = g_j6[idx];
+        for (int idx = tid; idx < N; idx += nthr) sm.j6[idx] = g_j6[natural_of(sm.ord, idx, L, invH, invL)];
         for (int idx = tid; idx < n_T * kThrCols; idx += nthr) sm.fthr[idx] = jd.flip_thr[idx];
         for (int idx = tid; idx < n_swap_lds; idx += nthr) sm.stab[idx] = jd.swap_thr[idx];
         for (int idx = tid; idx < n_sites_lds; idx += nthr) sm.sites[idx] = jd.sites[idx];
@@ -1177,7 +1245,10 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
             sm.ssgn[tid] = jd.swap_sgn[tid];
         }
         if (n_groups == 1)
-            for (int idx = tid; idx < NW * N; idx += nthr) sm.spin[idx] = g_spin[idx];
+            for (int idx = tid; idx < N; idx += nthr) {
+                const int nat = natural_of(sm.ord, idx, L, invH, invL);
+                for (int w = 0; w < NW; ++w) sm.spin[(size_t)w * N + idx] = g_spin[(size_t)w * N + nat];
+            }
         __syncthreads();
         if (tid < n_T) sm.sot[sm.perm[tid]] = tid;
         for (int idx = tid; idx < kMaxTemps * kThrCols; idx += nthr) {
@@ -1224,29 +1295,32 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
             for (int g0 = 0; g0 < NW; g0 += WR) {
                 const int gw = min(WR, NW - g0);
                 if (n_groups > 1) {
-                    for (int idx = tid; idx < gw * N; idx += nthr) sm.spin[idx] = g_spin[(size_t)g0 * N + idx];
+                    for (int idx = tid; idx < N; idx += nthr) {
+                        const int nat = natural_of(sm.ord, idx, L, invH, invL);
+                        for (int w = 0; w < gw; ++w) sm.spin[(size_t)w * N + idx] = g_spin[(size_t)(g0 + w) * N + nat];
+                    }
                     __syncthreads();
                 }
                 for (int s = 0; s < chunk; ++s) {
                     const uint32_t ts = t + (uint32_t)s;
                     if (even) {
                         if (!(PREDRAW && s == 0 && c0_done)) {
-                            class_pass<LAYOUT, false, SPLIT, RNG>(sm, 0, tid, nthr, half, L, invH, invL, N, NW, gw, g0,
+                            class_pass<LAYOUT, false, SPLIT, RNG, 0, SEP>(sm, 0, tid, nthr, half, L, invH, invL, N, NW, gw, g0,
                                                                   n_T, ts, r, c3flip, k0, k1, segw, fd, nullptr, 0, gb,
                                                                   ngr_own);
                             __syncthreads();
                         }
                         if (fused_energy && swap_now && s == chunk - 1) {
                             if (RNG == 0 && np_b == 4)   // at most two sites per lane
-                                class_pass<LAYOUT, true, SPLIT, RNG, 4>(sm, 1, tid, nthr, half, L, invH, invL, N, NW,
+                                class_pass<LAYOUT, true, SPLIT, RNG, 4, SEP>(sm, 1, tid, nthr, half, L, invH, invL, N, NW,
                                                                         gw, g0, n_T, ts, r, c3flip, k0, k1, segw, fd, P,
                                                                         np_b, gb, ngr_own);
                             else
-                                class_pass<LAYOUT, true, SPLIT, RNG>(sm, 1, tid, nthr, half, L, invH, invL, N, NW, gw,
+                                class_pass<LAYOUT, true, SPLIT, RNG, 0, SEP>(sm, 1, tid, nthr, half, L, invH, invL, N, NW, gw,
                                                                      g0, n_T, ts, r, c3flip, k0, k1, segw, fd, P, np_b,
                                                                      gb, ngr_own);
                         } else {
-                            class_pass<LAYOUT, false, SPLIT, RNG>(sm, 1, tid, nthr, half, L, invH, invL, N, NW, gw, g0,
+                            class_pass<LAYOUT, false, SPLIT, RNG, 0, SEP>(sm, 1, tid, nthr, half, L, invH, invL, N, NW, gw, g0,
                                                                   n_T, ts, r, c3flip, k0, k1, segw, fd, nullptr, 0, gb,
                                                                   ngr_own);
                         }
@@ -1276,15 +1350,18 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                             reduce_planes8_add<1>(P[0], np_b, s_hi - s_lo, sm.U, s_lo);
                     } else {
                         for (int w = 0; w < gw; ++w) {
-                            count_unsat_word<LAYOUT>(sm.spin + (size_t)w * N, sm.j6, N, L, invL, (g0 + w) * SPW, n_T,
-                                                     np, sm.U);
+                            count_unsat_word<LAYOUT>(sm.ord, sm.spin + (size_t)w * N, sm.j6, N, L, invH, invL,
+                                                     (g0 + w) * SPW, n_T, np, sm.U);
                             if (fd.on) count_up_word<LAYOUT>(sm.spin + (size_t)w * N, N, (g0 + w) * SPW, n_T, np, sm.up);
                         }
                     }
                 }
                 if (n_groups > 1) {
                     __syncthreads();
-                    for (int idx = tid; idx < gw * N; idx += nthr) g_spin[(size_t)g0 * N + idx] = sm.spin[idx];
+                    for (int idx = tid; idx < N; idx += nthr) {
+                        const int nat = natural_of(sm.ord, idx, L, invH, invL);
+                        for (int w = 0; w < gw; ++w) g_spin[(size_t)(g0 + w) * N + nat] = sm.spin[(size_t)w * N + idx];
+                    }
                 }
             }
             c0_done = false;
@@ -1418,8 +1495,8 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                         int j0 = tid;
                         asm volatile("" : "+v"(j0));   // as in predraw_site
                         if (j0 + nthr < half && !fd.on) {   // both sites in one block, as in class_pass
-                            const Nbrs na = checker_site(j0, 0, L, invH, invL);
-                            const Nbrs nb = checker_site(j0 + nthr, 0, L, invH, invL);
+                            const Nbrs na = class_site<SEP>(sm.ord, j0, 0, L, invH, invL);
+                            const Nbrs nb = class_site<SEP>(sm.ord, j0 + nthr, 0, L, invH, invL);
 #define EA_PAIR(G) update_pair_camsc<false, SPLIT, G, 0, PREDRAW>(sm, na, nb, n_T, tn, r, c3flip, k0, k1, segw, \
                                                                  nullptr, 0, gb, ngr_own, st[0], st[1])
                             switch (ngr_own) {
@@ -1431,19 +1508,19 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
 #undef EA_PAIR
                         } else {
                             if (j0 < half)
-                                update_site<LAYOUT, false, SPLIT, RNG, PREDRAW>(sm, checker_site(j0, 0, L, invH, invL),
+                                update_site<LAYOUT, false, SPLIT, RNG, PREDRAW>(sm, class_site<SEP>(sm.ord, j0, 0, L, invH, invL),
                                                                                 N, 1, 0, n_T, tn, r, c3flip, k0, k1,
                                                                                 segw, fd, nullptr, 0, gb, ngr_own,
                                                                                 st[0]);
                             if (j0 + nthr < half)
-                                update_site<LAYOUT, false, SPLIT, RNG, PREDRAW>(sm, checker_site(j0 + nthr, 0, L,
-                                                                                                 invH, invL),
+                                update_site<LAYOUT, false, SPLIT, RNG, PREDRAW>(sm, class_site<SEP>(sm.ord, j0 + nthr, 0, L,
+                                                                                               invH, invL),
                                                                                 N, 1, 0, n_T, tn, r, c3flip, k0, k1,
                                                                                 segw, fd, nullptr, 0, gb, ngr_own,
                                                                                 st[1]);
                         }
                         for (int j = tid + 2 * nthr; j < half; j += nthr)
-                            update_site<LAYOUT, false, SPLIT, RNG>(sm, checker_site(j, 0, L, invH, invL), N, 1, 0, n_T,
+                            update_site<LAYOUT, false, SPLIT, RNG>(sm, class_site<SEP>(sm.ord, j, 0, L, invH, invL), N, 1, 0, n_T,
                                                                   tn, r, c3flip, k0, k1, segw, fd, nullptr, 0, gb,
                                                                   ngr_own);
                         __syncthreads();
@@ -1585,11 +1662,15 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
             // merge own slots' bits: the partners change disjoint bits, so the xors commute
             const uint32_t own = (ngr_own >= 8 ? 0xFFFFFFFFu : ((1u << (4 * ngr_own)) - 1u)) << s_lo;
             for (int idx = tid; idx < N; idx += nthr) {
-                const uint32_t delta = (sm.spin[idx] ^ g_spin[idx]) & own;
-                if (delta) atomicXor(&g_spin[idx], delta);
+                const int nat = natural_of(sm.ord, idx, L, invH, invL);
+                const uint32_t delta = (sm.spin[idx] ^ g_spin[nat]) & own;
+                if (delta) atomicXor(&g_spin[nat], delta);
             }
         } else if (n_groups == 1) {
-            for (int idx = tid; idx < NW * N; idx += nthr) g_spin[idx] = sm.spin[idx];
+            for (int idx = tid; idx < N; idx += nthr) {
+                const int nat = natural_of(sm.ord, idx, L, invH, invL);
+                for (int w = 0; w < NW; ++w) g_spin[(size_t)w * N + nat] = sm.spin[(size_t)w * N + idx];
+            }
         }
         if (tid < n_T && part == 0) {
             jd.temp_of_slot[ladder * kMaxTemps + tid] = sm.perm[tid];
@@ -1737,8 +1818,8 @@ __global__ void __launch_bounds__(512) observables_kernel(const JobDesc *__restr
     for (int c = 0; c < 2; ++c)
         for (int w = 0; w < NW; ++w)
         {
-            count_unsat_word<LAYOUT>(jd.spins + ((size_t)(2 * r + c) * NW + w) * N, j6, N, jd.L, jd.invL, w * SPW,
-                                     n_T, np, s_U[c]);
+            count_unsat_word<LAYOUT>(Order{0, N >> 1}, jd.spins + ((size_t)(2 * r + c) * NW + w) * N, j6, N, jd.L,
+                                     jd.invH, jd.invL, w * SPW, n_T, np, s_U[c]);   // HBM holds the natural order
             if (magnet) count_up_word<LAYOUT>(jd.spins + ((size_t)(2 * r + c) * NW + w) * N, N, w * SPW, n_T, np, s_up[c]);
         }
     // overlap between the copies at equal temperature index
@@ -1832,12 +1913,22 @@ hipError_t launch_init_spins(const JobDesc *d_job, const JobDesc &h, int layout,
 }
 
 // Sweep kernel variants: kv = 0 CAMSC, 1 AMSC4, 2 CAMSC with plane draws, 3 AMSC3, 4 AMSC1;
-// split ladders (parts 2 or 4, CAMSC) read the unit list when `listed`.
-static const void *sweep_fn(int kv, int parts, bool listed = false)
+// split ladders (parts 2 or 4, CAMSC) read the unit list when `listed`; sep =
+// spin words in LDS by colour class (lone CAMSC launches).
+static const void *sweep_fn(int kv, int parts, bool listed = false, int sep = 0)
 {
     if (kv == 1) return (const void *)sweep_kernel<1, 1, 0>;
     if (kv == 3) return (const void *)sweep_kernel<2, 1, 0>;
     if (kv == 4) return (const void *)sweep_kernel<3, 1, 0>;
+    if (sep) {
+        if (kv == 2)
+            return parts == 4 ? (const void *)sweep_kernel<0, 4, 1, false, 1>
+                              : (parts == 2 ? (const void *)sweep_kernel<0, 2, 1, false, 1>
+                                            : (const void *)sweep_kernel<0, 1, 1, false, 1>);
+        return parts == 4 ? (const void *)sweep_kernel<0, 4, 0, false, 1>
+                          : (parts == 2 ? (const void *)sweep_kernel<0, 2, 0, false, 1>
+                                        : (const void *)sweep_kernel<0, 1, 0, false, 1>);
+    }
     if (kv == 2) {
         if (parts == 4) return listed ? (const void *)sweep_kernel<0, 4, 1, true> : (const void *)sweep_kernel<0, 4, 1>;
         if (parts == 2) return listed ? (const void *)sweep_kernel<0, 2, 1, true> : (const void *)sweep_kernel<0, 2, 1>;
@@ -1858,6 +1949,8 @@ hipError_t sweep_set_lds(int kv, int parts, size_t lds)
     hipError_t e = hipFuncSetAttribute(sweep_fn(kv, parts), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e == hipSuccess && parts > 1)
         e = hipFuncSetAttribute(sweep_fn(kv, parts, true), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess && (kv == 0 || kv == 2))
+        e = hipFuncSetAttribute(sweep_fn(kv, parts, false, 1), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e == hipSuccess) {
         size_t prev = cur.load();
         while (prev < lds && !cur.compare_exchange_weak(prev, lds)) {
@@ -1867,13 +1960,14 @@ hipError_t sweep_set_lds(int kv, int parts, size_t lds)
 }
 
 hipError_t launch_sweep(const JobDesc *d_jobs, int n_jobs, const uint32_t *d_units, int n_units, uint32_t *d_queue,
-                        int kv, int parts, int block_threads, size_t lds, int grid, hipStream_t s)
+                        int kv, int parts, int sep, int block_threads, size_t lds, int grid, hipStream_t s)
 {
     hipError_t e = sweep_set_lds(kv, parts, lds);
     if (e != hipSuccess) return e;
     void *args[] = {(void *)&d_jobs, (void *)&d_units, (void *)&n_units, (void *)&d_queue};
     // one job's units are its ladders in order (a launch set of one job keeps them so)
-    e = hipLaunchKernel(sweep_fn(kv, parts, n_jobs > 1), dim3(grid), dim3(block_threads), args, lds, s);
+    if (sep && (n_jobs > 1 || (kv != 0 && kv != 2))) return hipErrorInvalidValue;   // lone CAMSC launches only
+    e = hipLaunchKernel(sweep_fn(kv, parts, n_jobs > 1, sep), dim3(grid), dim3(block_threads), args, lds, s);
     if (e != hipSuccess) return e;
     const int adv = n_jobs > kQueueWords ? n_jobs : kQueueWords;
     hipLaunchKernelGGL(advance_kernel, dim3((adv + 255) / 256), dim3(256), 0, s, d_jobs, n_jobs, d_queue);

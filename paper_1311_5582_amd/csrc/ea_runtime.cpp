@@ -21,6 +21,7 @@ namespace ea {
 struct LaunchSet {
     int layout = 0;   // kernel variant (kernel_variant of the jobs' layout and draw stream)
     int parts = 1;    // workgroups per ladder (split ladders when > 1)
+    int sep = 0;      // spin words in LDS by colour class (a launch over one job only)
     int n_jobs = 0;
     int n_units = 0;
     int bt = 0;
@@ -57,6 +58,13 @@ static int launchset_plan(LaunchSet &ls, const std::vector<JobDesc> &descs, cons
     ls.layout = layout;
     ls.n_jobs = (int)descs.size();
     ls.descs = descs;
+    ls.sep = 0;
+    for (const JobDesc &d : descs)
+        if (d.site_order != 0) {
+            if (descs.size() > 1)
+                return fail(EA_EINVAL, "a job with its spin words in LDS by colour class runs only alone");
+            ls.sep = d.site_order;
+        }
     std::vector<std::pair<double, uint32_t>> order;
     int want_bt = 0, need_bt = 64;
     size_t lds = 0;
@@ -125,8 +133,8 @@ static int launchset_build(LaunchSet &ls, const std::vector<JobDesc> &descs, con
 static int launchset_launch(const LaunchSet &ls, hipStream_t st)
 {
     if (ls.n_units == 0) return EA_OK;
-    EA_HIP(launch_sweep(ls.d_descs, ls.n_jobs, ls.d_units, ls.n_units, ls.d_queue, ls.layout, ls.parts, ls.bt, ls.lds,
-                        ls.grid, st));
+    EA_HIP(launch_sweep(ls.d_descs, ls.n_jobs, ls.d_units, ls.n_units, ls.d_queue, ls.layout, ls.parts, ls.sep, ls.bt,
+                        ls.lds, ls.grid, st));
     return EA_OK;
 }
 
@@ -386,7 +394,8 @@ int ea_sweep_batch(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps, con
             grid = split_grid(s->h.ladders, parts);
         else if (int rc = device_grid(kv, s->block_threads, s->lds, s->h.ladders, &grid))
             return rc;
-        EA_HIP(launch_sweep(s->d_job, 1, s->d_units, s->h.ladders, s->d_counters + 1, kv, parts, s->block_threads,
+        EA_HIP(launch_sweep(s->d_job, 1, s->d_units, s->h.ladders, s->d_counters + 1, kv, parts, s->h.site_order,
+                            s->block_threads,
                             s->lds, grid, st));
         if (parts > 1) s->ever_split = true;
         s->t += n_sweeps[0];

@@ -46,7 +46,7 @@ def test_swap_thresholds_match_oracle(lib, oracle_lib):
 
 
 def _create(lib, L=4, n_T=4, R=1, J=None, betas=None, layout=0, block_threads=0, words_resident=0, split=0, rng=0,
-            field=0.0):
+            field=0.0, site_order=0):
     if J is None:
         J = inputs.couplings(L, R, seed=1) if L >= 2 else np.ones((R, max(L, 1) ** 3, 3), np.int8)
     if betas is None:
@@ -58,6 +58,7 @@ def _create(lib, L=4, n_T=4, R=1, J=None, betas=None, layout=0, block_threads=0,
     opt.layout, opt.block_threads, opt.words_resident, opt.split = layout, block_threads, words_resident, split
     opt.rng = rng
     opt.field = field
+    opt.site_order = site_order
     h = ctypes.c_void_p()
     rc = lib.ea_create(L, J.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
                        b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n_T, R, 7, ctypes.byref(opt),
@@ -73,6 +74,7 @@ def _create(lib, L=4, n_T=4, R=1, J=None, betas=None, layout=0, block_threads=0,
     dict(rng=2), dict(rng=-1), dict(rng=1, layout=1),
     dict(field=0.3), dict(field=8.25), dict(field=float("nan")), dict(field=float("inf")), dict(field=0.5, rng=1),
     dict(L=32, n_T=64, words_resident=2, J=np.ones((1, 32 ** 3, 3), np.int8)),
+    dict(site_order=2), dict(site_order=-1), dict(site_order=1, L=5), dict(site_order=1, layout=1),
 ])
 def test_create_rejects_invalid_arguments(lib, case):
     if "J" not in case and case.get("L", 4) in (1, 33):

@@ -30,7 +30,7 @@ def _report(tag, **kw):
 
 def run_pair(oracle_lib, L, R, n_T, seed, sweeps, swap_every, layout="camsc", t_min=0.4, t_max=2.0,
              rids=None, block_threads=0, words_resident=0, couplings=None, splits=None, rng="words", split=True,
-             h=0.0):
+             h=0.0, site_order="natural"):
     """Run the GPU on all R realizations and the oracle on `rids`; compare."""
     _report("run", L=L, R=R, n_T=n_T, seed=seed, sweeps=sweeps, swap_every=swap_every, layout=layout,
             bt=block_threads, wr=words_resident, rng=rng, split=split, h=h)
@@ -38,7 +38,7 @@ def run_pair(oracle_lib, L, R, n_T, seed, sweeps, swap_every, layout="camsc", t_
     betas = inputs.geometric_betas(n_T, t_min, t_max)
     rids = list(range(R)) if rids is None else list(rids)
     sim = B.Sim(L, J, betas, seed, layout=layout, block_threads=block_threads, words_resident=words_resident,
-                rng=rng, split=split, h=h)
+                rng=rng, split=split, h=h, site_order=site_order)
     orc = oracle_lib.OracleSim(L, J[rids], betas, seed, rid=np.array(rids), rng=rng, h=h)
     s0, p0, t0 = sim.state()
     assert t0 == 0
@@ -343,3 +343,26 @@ def test_plane_draws_deep_planes(oracle_lib, n_T, split):
         assert np.array_equal(s[r], o.spins[0]), f"realization {r}: spins differ"
         Eo, qo = o.observables()
         assert np.array_equal(E[r], Eo[0]) and np.array_equal(q[r], qo[0])
+
+
+@pytest.mark.parametrize("L,R,n_T,swap_every,rng,split,bt,wr", [
+    (8, 2, 16, 1, "words", False, 0, 0),       # unsplit, fused energy in the summing class
+    (6, 3, 24, 3, "words", False, 0, 0),       # L/2 odd: rows of three class sites
+    (16, 2, 32, 1, "words", "always", 0, 0),   # split ladders, paired sites, next-sweep draws
+    (4, 2, 40, 2, "words", False, 0, 0),       # two words per site, energies from the separate count
+    (8, 1, 64, 3, "words", False, 64, 1),      # second word staged through HBM, 64 threads
+    (10, 1, 32, 0, "planes", "always", 0, 0),  # plane draws, split in 4
+    (6, 2, 22, 1, "planes", False, 0, 0),      # plane draws, ragged halves
+])
+def test_class_order_equals_oracle(oracle_lib, L, R, n_T, swap_every, rng, split, bt, wr):
+    """Spin words and couplings held by colour class in LDS (the separated
+    allocation): the oracle's chain bit for bit in every launch shape."""
+    sim, *_ = run_pair(oracle_lib, L, R, n_T, 9100 + 7 * L + n_T, 21, swap_every, rng=rng, split=split,
+                       block_threads=bt, words_resident=wr, splits=[1, 9, 11], site_order="by_class")
+    print(f"[parity] class order {sim.info()}", flush=True)
+
+
+def test_class_order_field(oracle_lib):
+    """The class order with a field (certain flips both ways, spins-up counts)."""
+    sim, orc, *_ = run_pair(oracle_lib, 6, 3, 16, 9300, 19, 1, h=0.75, splits=[4, 15], site_order="by_class")
+    assert np.array_equal(sim.magnetization(), orc.magnetization())
