@@ -9,9 +9,10 @@ ps/flip follows Eq. tsf of the paper: wall time / (sweeps x spins x
 temperatures x samples), samples = realizations x 2 copies.
 
 Further legs on the same line: the large job (L=24, 256 realizations, 48
-temperatures, PT every 10 sweeps) with both draw streams, the five uneven
-jobs batched vs plain, and the 64-job serving trace through the server vs
-the plain single-job path.  The roofline objects price the sweep kernel
+temperatures, PT every 10 sweeps) with both draw streams, MC and PT fused in
+one launch vs one launch per swap interval, the five uneven jobs batched vs
+plain, and the 64-job serving trace through the server vs the plain
+single-job path.  The roofline objects price the sweep kernel
 against the vector ALU rate of the chip; the cpu_baseline object times the
 CPU oracle on a bounded sample of the same workload, on all host cores and
 on one.
@@ -258,6 +259,48 @@ def bench_large(B, inputs, torch, sweeps, steps, rng="words", site_order="natura
                          "kernel": "sweep_kernel<CAMSC, %d>" % info["split_parts"]}}
 
 
+def bench_fused_vs_separated(B, inputs, torch, sweeps):
+    """MC and PT fused in one persistent launch (this library) against one
+    launch per swap interval, the lower bound of the paper's "separated"
+    scheme (Sec. 4.1, Fig. korg), which adds a second launch for the swap
+    step: the per-interval launches are graph-captured plan steps of
+    swap_every sweeps, each loading its ladders into LDS, running the sweeps
+    and the fused swap step, and writing them back.  Both runs make the same
+    chain, and their energies and overlaps are compared."""
+    cfg = inputs.CONFIGS["L16_R64"]
+    L, R, n_T = cfg["L"], cfg["R"], cfg["n_T"]
+    J = inputs.couplings(L, R, cfg["seed"])
+    betas = inputs.geometric_betas(n_T, cfg["t_min"], cfg["t_max"])
+    flips = sweeps * L ** 3 * n_T * R * 2
+    out = {"workload": "L16_R64", "sweeps": sweeps}
+    for se in (1, 10):
+        fused = B.Sim(L, J, betas, cfg["seed"])
+        fused.sweep(se, se)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fused.sweep(sweeps, se)
+        torch.cuda.synchronize()
+        t_fused = time.perf_counter() - t0
+        sep = B.Sim(L, J, betas, cfg["seed"])
+        plan = B.Plan([sep], se, se, autotune=False)
+        plan.run(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.run(sweeps // se)
+        torch.cuda.synchronize()
+        t_sep = time.perf_counter() - t0
+        parts = plan.info()["split_parts"]
+        plan.close()
+        same = all(np.array_equal(a, b) for a, b in zip(fused.observables(), sep.observables()))
+        fused.close()
+        sep.close()
+        out[f"swap_every_{se}"] = {"fused_ps_per_flip": round(t_fused / flips * 1e12, 4),
+                                   "launch_per_interval_ps_per_flip": round(t_sep / flips * 1e12, 4),
+                                   "ratio": round(t_sep / t_fused, 3), "workgroups_per_ladder": parts,
+                                   "same_chain": bool(same)}
+    return out
+
+
 def flips_of(job, sweeps):
     return sweeps * job["L"] ** 3 * job["n_T"] * job["R"] * 2
 
@@ -384,6 +427,8 @@ def main():
     ap.add_argument("--large-sweeps", type=int, default=200)
     ap.add_argument("--large-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fused-vs-separated", action="store_true",
+                    help="skip the MC/PT fused vs one-launch-per-swap-interval comparison")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-sweeps", type=int, default=250)
     ap.add_argument("--batched-steps", type=int, default=4)
@@ -521,6 +566,10 @@ def main():
         out["large_planes"] = bench_large(B, inputs, torch, args.large_sweeps, args.large_steps, rng="planes",
                                           site_order=args.site_order)
         progress(f"L24_R256: {out['large']['ps_per_flip']} / planes {out['large_planes']['ps_per_flip']} ps/flip")
+    if not args.no_fused_vs_separated:
+        out["mc_pt_fused_vs_separated"] = r = bench_fused_vs_separated(B, inputs, torch, 2000)
+        progress(f"fused vs one launch per swap interval: every sweep {r['swap_every_1']['ratio']}x, "
+                 f"every 10 {r['swap_every_10']['ratio']}x")
     if not args.no_batched:
         out["batched"] = bench_batched(B, inputs, torch, args.batched_sweeps, args.batched_steps)
         progress(f"batched: {out['batched']['batched_ps_per_flip']} vs plain {out['batched']['plain_ps_per_flip']}")

@@ -209,7 +209,8 @@ class Sim:
     """One job: R realizations x 2 copies x n_T temperature slots on the GPU."""
 
     def __init__(self, L, couplings, betas, seed, layout="camsc", block_threads=0, words_resident=0,
-                 stream=None, torch_memory=True, split=True, rng="words", h=0.0, site_order="natural"):
+                 stream=None, torch_memory=True, split=True, rng="words", h=0.0, site_order="natural",
+                 allocator=None):
         L = int(L)
         J = np.ascontiguousarray(couplings, dtype=np.int8)
         if J.ndim != 3 or J.shape[1:] != (L ** 3, 3):
@@ -225,12 +226,15 @@ class Sim:
         opt.rng = RNGS[rng] if isinstance(rng, str) else int(rng)
         opt.field = float(h)
         opt.site_order = {"natural": 0, "by_class": 1}[site_order] if isinstance(site_order, str) else int(site_order)
-        self._alloc = None
+        # allocator: an object with ctypes callbacks alloc_cb / free_cb (TorchAllocator's
+        # interface); default torch's caching allocator when torch sees a GPU, else hipMalloc
+        self._alloc = allocator
         torch = _torch_gpu() if (torch_memory or stream is not None) else None
         if stream is not None:
             opt.stream = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
-        if torch is not None and torch_memory:
+        if self._alloc is None and torch is not None and torch_memory:
             self._alloc = TorchAllocator(torch.cuda.current_device())
+        if self._alloc is not None:
             opt.dev_alloc = self._alloc.alloc_cb
             opt.dev_free = self._alloc.free_cb
         self.stream = stream
