@@ -63,17 +63,25 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def kernel_name(layout, info):
+    """The sweep kernel a launch runs: ladders split by lattice halves run
+    slab_kernel, every other launch sweep_kernel<layout, workgroups per ladder>."""
+    if info.get("split_by_halves"):
+        return "slab_kernel"
+    return "sweep_kernel<%s, %d>" % (layout.upper(), info["split_parts"])
+
+
 def kernel_source_hash():
     import hashlib
     return hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()[:12]
 
 
-def measured_traffic(workload, layout, rng="words"):
+def measured_traffic(workload, layout, rng="words", kernel="sweep_kernel"):
     """HBM bytes per sweep launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, only if it was taken on the current kernel source."""
     import re
     suffix = "" if rng == "words" else "_" + rng
-    path = os.path.join(PROFILES, f"sweep_kernel_{workload}_{layout}{suffix}.md")
+    path = os.path.join(PROFILES, f"{kernel}_{workload}_{layout}{suffix}.md")
     if not os.path.exists(path):
         return None
     m = re.search(r"traffic_bytes_per_launch:\s*(\d+)\s+kernel_sha1:\s*([0-9a-f]+)", open(path).read())
@@ -189,7 +197,8 @@ def bench_other_stream(B, torch, L, J, betas, seed, layout, block_threads, split
 def bench_layout_study(B, torch, inputs, sweeps, steps):
     """The paper's layout comparison (16^3 lattice, PT every 10 sweeps) on the
     benchmark's L=16 job: every layout, one workgroup per ladder, plus CAMSC
-    with split ladders and with bit-plane draws."""
+    with split ladders (by lattice halves, and by slot groups) and with
+    bit-plane draws."""
     cfg = inputs.CONFIGS["L16_R64"]
     L, R, n_T = cfg["L"], cfg["R"], cfg["n_T"]
     J = inputs.couplings(L, R, cfg["seed"])
@@ -200,6 +209,7 @@ def bench_layout_study(B, torch, inputs, sweeps, steps):
     for name, layout, split, rng in (("amsc1", "amsc1", False, "words"), ("amsc3", "amsc3", False, "words"),
                                      ("amsc4", "amsc4", False, "words"), ("camsc", "camsc", False, "words"),
                                      ("camsc_split", "camsc", True, "words"),
+                                     ("camsc_split_slot_groups", "camsc", "slots", "words"),
                                      ("camsc_split_planes", "camsc", True, "planes")):
         stream = torch.cuda.Stream()
         sim = B.Sim(L, J, betas, cfg["seed"], layout=layout, stream=stream, split=split, rng=rng)
@@ -254,9 +264,10 @@ def bench_large(B, inputs, torch, sweeps, steps, rng="words", site_order="natura
             "ps_per_flip": round(wall / (flips * steps) * 1e12, 4), "ms_per_step": round(wall / steps * 1e3, 4),
             "kernel_ps_per_flip": round(kern / flips * 1e12, 4),
             "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
-                         "frac": round(achieved / peak, 4), "traffic": measured_traffic("L24_R256", "camsc", rng),
+                         "frac": round(achieved / peak, 4),
+                         "traffic": measured_traffic("L24_R256", "camsc", rng, kernel_name("camsc", info).split("<")[0]),
                          "ops_per_flip": ops, "kernel_sha1": kernel_source_hash(),
-                         "kernel": "sweep_kernel<CAMSC, %d>" % info["split_parts"]}}
+                         "kernel": kernel_name("camsc", info)}}
 
 
 def bench_fused_vs_separated(B, inputs, torch, sweeps):
@@ -417,6 +428,8 @@ def main():
                     help="skip timing the same workload with the other flip-draw stream")
     ap.add_argument("--site-order", default="natural", choices=["natural", "by_class"],
                     help="order of the spin words in LDS: natural (unified) or by checkerboard class (separated)")
+    ap.add_argument("--split-slots", action="store_true",
+                    help="split ladders by slot groups only (not by lattice halves)")
     ap.add_argument("--no-split", action="store_true",
                     help="one workgroup per ladder even when the job has fewer ladders than compute units")
     ap.add_argument("--swap-every", type=int, default=-1, help="override the workload's PT interval")
@@ -483,8 +496,9 @@ def main():
     stream = torch.cuda.Stream()
     J = inputs.couplings(L, R, cfg["seed"])
     betas = inputs.geometric_betas(n_T, cfg["t_min"], cfg["t_max"])
+    split = False if args.no_split else ("slots" if args.split_slots else True)
     sim = B.Sim(L, J, betas, cfg["seed"], layout=args.layout, block_threads=args.block_threads, stream=stream,
-                split=not args.no_split, rng=args.rng, site_order=args.site_order)
+                split=split, rng=args.rng, site_order=args.site_order)
     launch = sim.info()
     S, se = args.sweeps_per_step, (cfg["swap_every"] if args.swap_every < 0 else args.swap_every)
 
@@ -543,19 +557,22 @@ def main():
                    "swap_every": se, "layout": args.layout, "rng": args.rng, "site_order": args.site_order,
                    "measurement_per_step": True,
                    "block_threads": launch["block_threads"], "workgroups_per_ladder": launch["split_parts"],
+                   "split_by_halves": launch["split_by_halves"],
                    "kernel_ps_per_flip": round(avg_launch_s / flips_per_step * 1e12, 4),
                    "paper_ps_per_flip_gtx580": 33.5},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": measured_traffic(args.workload, args.layout, args.rng),
+                     "frac": round(achieved / peak, 4),
+                     "traffic": measured_traffic(args.workload, args.layout, args.rng,
+                                                 kernel_name(args.layout, launch).split("<")[0]),
                      "ops_per_flip": ops_per_flip, "kernel_sha1": kernel_source_hash(),
-                     "kernel": "sweep_kernel<%s, %d>" % (args.layout.upper(), launch["split_parts"])},
+                     "kernel": kernel_name(args.layout, launch)},
     }
     sim.close()
     progress(f"{args.workload}: {ps_per_flip:.4f} ps/flip")
     if not args.no_other_stream and args.layout == "camsc":
         other = "planes" if args.rng == "words" else "words"
         out["other_stream"] = bench_other_stream(B, torch, L, J, betas, cfg["seed"], args.layout, args.block_threads,
-                                                 not args.no_split, other, S, se, 3, args.site_order)
+                                                 split, other, S, se, 3, args.site_order)
     if "other_stream" in out:
         progress(f"other stream: {out['other_stream']['ps_per_flip']} ps/flip")
     if args.layout_study:

@@ -95,9 +95,15 @@ typedef struct ea_options {
     int words_resident;  /* spin words per site held in LDS at once: 0 = as many as fit;
                             fewer makes the kernel stage word groups through HBM       */
     int split;           /* 0 = auto: a job with fewer ladders than CUs (CAMSC, <= 32
-                            temperatures, even L) spreads each ladder's slot groups over 2
-                            or 4 workgroups when each keeps >= 2048 site-groups of work
-                            per sweep; 1 = never; 2 = whenever possible.  Batches and
+                            temperatures, even L) spreads each ladder over 2 or 4
+                            workgroups when each keeps >= 2048 site-groups of work per
+                            sweep; 1 = never; 2 = whenever possible; 3 = whenever
+                            possible, by slot groups only.  Two workgroups of a ladder
+                            split it by lattice halves along z, each with every slot
+                            (word draws, L >= 4, no field, natural site order; the
+                            halves trade their boundary planes after every colour
+                            class), otherwise by slot groups, each with the whole
+                            lattice (they meet only at swap points).  Batches and
                             plans apply the same rule to all their jobs together       */
     int rng;             /* flip-draw stream: EA_RNG_WORDS (default) or EA_RNG_PLANES
                             (CAMSC only); both give each flip the acceptance law
@@ -361,6 +367,9 @@ int ea_get_dims(const ea_sim *sim, int *L, int *n_T, int *n_realizations, int *l
 /* Launch plan of a lone ea_sweep: workgroup size, spin words resident in LDS,
  * workgroups per ladder (1, or 2/4 when split), dynamic LDS bytes. */
 int ea_sim_info(const ea_sim *sim, int *block_threads, int *words_resident, int *split_parts, size_t *lds_bytes);
+/* How a lone ea_sweep splits the job's ladders: workgroups per ladder (1: not
+ * split) and whether they split it by lattice halves (1) or by slot groups (0). */
+int ea_sim_split(const ea_sim *sim, int *split_parts, int *by_halves);
 
 /* Release the handle and its device memory (NULL is a no-op). */
 void ea_destroy(ea_sim *sim);

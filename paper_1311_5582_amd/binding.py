@@ -115,6 +115,7 @@ def lib():
                                                 ctypes.POINTER(ctypes.c_size_t)]),
             "ea_sim_footprint": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_size_t)]),
             "ea_sim_info": (ctypes.c_int, [P, i32p, i32p, i32p, ctypes.POINTER(ctypes.c_size_t)]),
+            "ea_sim_split": (ctypes.c_int, [P, i32p, i32p]),
             "ea_measure": (ctypes.c_int, [P]),
             "ea_magnetization": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int32)]),
             "ea_measure_read": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
@@ -222,7 +223,8 @@ class Sim:
         opt.block_threads = int(block_threads)
         opt.words_resident = int(words_resident)
         # True/"auto": library choice; False: one workgroup per ladder; "always": split when possible
-        opt.split = {True: 0, "auto": 0, False: 1, "never": 1, "always": 2}[split]
+        # "slots": whenever possible, by slot groups only (not by lattice halves)
+        opt.split = {True: 0, "auto": 0, False: 1, "never": 1, "always": 2, "slots": 3}[split]
         opt.rng = RNGS[rng] if isinstance(rng, str) else int(rng)
         opt.field = float(h)
         opt.site_order = {"natural": 0, "by_class": 1}[site_order] if isinstance(site_order, str) else int(site_order)
@@ -321,7 +323,10 @@ class Sim:
         bt, wr, parts = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         lds = ctypes.c_size_t()
         check(lib().ea_sim_info(self._h, ctypes.byref(bt), ctypes.byref(wr), ctypes.byref(parts), ctypes.byref(lds)))
-        return dict(block_threads=bt.value, words_resident=wr.value, split_parts=parts.value, lds_bytes=int(lds.value))
+        halves = ctypes.c_int()
+        check(lib().ea_sim_split(self._h, None, ctypes.byref(halves)))
+        return dict(block_threads=bt.value, words_resident=wr.value, split_parts=parts.value, lds_bytes=int(lds.value),
+                    split_by_halves=bool(halves.value))
 
     def footprint(self):
         b = ctypes.c_size_t()

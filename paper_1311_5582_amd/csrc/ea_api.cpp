@@ -208,7 +208,7 @@ int plan_launch(int N, int NW, const ea_options &opt, int *block_threads, int *w
     int wr_max = (int)((kLdsBudget - fixed) / ((size_t)N * 4));
     int wr = std::min(NW, wr_max);
     if (opt.words_resident < 0) return fail(EA_EINVAL, "words_resident=%d < 0", opt.words_resident);
-    if (opt.split < 0 || opt.split > 2) return fail(EA_EINVAL, "split=%d is not 0, 1 or 2", opt.split);
+    if (opt.split < 0 || opt.split > 3) return fail(EA_EINVAL, "split=%d is not 0, 1, 2 or 3", opt.split);
     if (opt.words_resident > 0) {
         if (opt.words_resident > wr_max)
             return fail(EA_EINVAL, "words_resident=%d exceeds the %d words that fit in LDS", opt.words_resident, wr_max);
@@ -278,15 +278,38 @@ int build_swap_tables(const double *betas, int n_T, int N, int m, std::vector<ui
     return EA_OK;
 }
 
+// Compute units of the current device (256 when no device can be queried).
+static int device_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        return 256;
+    return cus;
+}
+
+// Bytes of the boundary-plane exchange of ladders split by lattice halves:
+// [ladders][2 parts][2 classes][2 sides][L^2 / 2] tagged words, for jobs of a
+// shape that can run so (CAMSC, one word per site, even L >= 4) with few
+// enough ladders to be split at all (two workgroups per ladder fit in the
+// device's compute units); 0 otherwise.
+size_t halo_bytes(int L, int n_T, int R, int layout)
+{
+    const int64_t ladders = 2 * (int64_t)R;
+    if (layout != EA_LAYOUT_CAMSC || n_T > 32 || (L & 1) || L < 4 || 2 * ladders > device_cus()) return 0;
+    return (size_t)ladders * 8 * ((size_t)L * L / 2) * sizeof(uint64_t);
+}
+
 // Device bytes ea_create allocates for a job (one term per allocation).
 size_t job_footprint_bytes(int L, int n_T, int R, int layout, int64_t swap_entries)
 {
     auto a = [](size_t b) { return std::max<size_t>(b, 16); };
     const size_t N = (size_t)L * L * L, ladders = 2 * (size_t)R;
     const size_t NW = (size_t)(n_T + slots_per_word(layout) - 1) / slots_per_word(layout);
+    const size_t halo = halo_bytes(L, n_T, R, layout);
     return a(ladders * NW * N * 4) + a((size_t)R * N) + a(ladders * kMaxTemps * 4) + a((size_t)n_T * kThrCols * 4) +
            a((size_t)swap_entries * 4) + 3 * a(kMaxTemps * 4) + a(N * 4) + a(kCounterWords * 4) + a(ladders * kMaxTemps * 8) +
-           a(ladders * 4) + a(sizeof(JobDesc)) + a(ladders * 2 * kMaxTemps * 8) + a(4) +
+           a(ladders * 4) + a(sizeof(JobDesc)) + a(ladders * 2 * kMaxTemps * 8) + a(4) + (halo ? a(halo) : 0) +
            a((size_t)R * n_T * (4 + L) * 8) + a((size_t)R * n_T * 5 * 4);
 }
 
@@ -311,11 +334,13 @@ int choose_split_parts(const JobDesc *descs, int n, int bt, size_t lds, int kv, 
         // with PT every sweep: 4 parts pay off from 1024 site-groups per part, 2 parts
         // from 2048)
         if (ladders * parts > cus) continue;
+        // two parts may split by lattice halves, which needs no even count of slot groups
+        const bool halves = parts == 2 && split_variant(descs, n, kv, parts, split_opt) == kSlabVariant;
         bool ok = true;
         for (int j = 0; j < n && ok; ++j) {
             const int ngr = (descs[j].n_T + 3) >> 2;
-            if (ngr % parts != 0) ok = false;
-            if (split_opt == 0 && (int64_t)descs[j].N * (ngr / parts) < 4096 / parts) ok = false;
+            if (ngr % parts != 0 && !halves) ok = false;
+            if (split_opt == 0 && (int64_t)descs[j].N * ngr / parts < 4096 / parts) ok = false;
         }
         if (!ok) continue;
         // every workgroup resident at once: each queue's parts meet without waiting for a slot
@@ -324,6 +349,20 @@ int choose_split_parts(const JobDesc *descs, int n, int bt, size_t lds, int kv, 
         return parts;
     }
     return 1;
+}
+
+// Kernel variant of a split launch: ladders split by lattice halves
+// (kSlabVariant) when every job allows it (CAMSC word draws, one word per site,
+// even L >= 4, no field, natural order, an exchange area) and the split is
+// two ways, unless split_opt asks for slot groups (3); otherwise kv.
+int split_variant(const JobDesc *descs, int n, int kv, int parts, int split_opt)
+{
+    if (parts != 2 || kv != 0 || split_opt == 3 || n < 1) return kv;
+    for (int j = 0; j < n; ++j) {
+        const JobDesc &d = descs[j];
+        if (!d.halo || d.NW != 1 || (d.L & 1) || d.L < 4 || d.field_m != 0 || d.site_order != 0) return kv;
+    }
+    return kSlabVariant;
 }
 
 // Workgroups per ladder for a lone launch of the job.
@@ -514,6 +553,11 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T, int 
     std::vector<uint32_t> err(1, 0u);
     if ((rc = upload(s, xchg, &h.xchg)) || (rc = upload(s, err, &h.error)))
         return bail(rc);
+    if (const size_t hb = halo_bytes(L, n_T, n_realizations, opt.layout)) {
+        std::vector<uint64_t> halo(hb / sizeof(uint64_t), 0);   // tag 0: no sweep has written yet
+        if ((rc = upload(s, halo, &h.halo))) return bail(rc);
+        s->halo_size = hb;
+    }
     std::vector<int64_t> meas((size_t)n_realizations * n_T * (4 + L), 0);
     if ((rc = upload(s, meas, &s->d_meas))) return bail(rc);
     // outputs of the observables kernel: energy and magnetization [R][2][n_T], overlap [R][n_T]
@@ -572,6 +616,16 @@ int ea_sim_info(const ea_sim *s, int *block_threads, int *words_resident, int *s
     if (words_resident) *words_resident = s->words_resident;
     if (split_parts) *split_parts = s->split_parts;
     if (lds_bytes) *lds_bytes = s->lds;
+    return EA_OK;
+}
+
+int ea_sim_split(const ea_sim *s, int *split_parts, int *by_halves)
+{
+    if (!s) return fail(EA_EINVAL, "ea_sim_split: NULL handle");
+    if (split_parts) *split_parts = s->split_parts;
+    if (by_halves)
+        *by_halves = s->split_parts > 1 && split_variant(&s->h, 1, kernel_variant(s->layout, s->h.rng), s->split_parts,
+                                                         s->split_opt) == kSlabVariant;
     return EA_OK;
 }
 
@@ -781,6 +835,8 @@ int ea_set_state(ea_sim *s, const int8_t *spins, const int32_t *temp_of_slot, in
     if (e == hipSuccess) e = hipMemcpyAsync(s->d_counters, &t, sizeof t, hipMemcpyHostToDevice, s->stream);
     // exchange words carry sweep tags: a rewound counter must not meet stale ones
     if (e == hipSuccess) e = hipMemsetAsync(s->h.xchg, 0, (size_t)ladders * 2 * kMaxTemps * sizeof(uint64_t), s->stream);
+    if (e == hipSuccess && s->h.halo)
+        e = hipMemsetAsync(s->h.halo, 0, s->halo_size, s->stream);
     // a valid state clears an earlier exchange timeout
     if (e == hipSuccess) e = hipMemsetAsync(s->h.error, 0, sizeof(uint32_t), s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);

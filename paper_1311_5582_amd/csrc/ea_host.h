@@ -44,6 +44,7 @@ int wgs_per_cu(size_t lds, int bt);
 int build_swap_tables(const double *betas, int n_T, int N, int m, std::vector<uint32_t> *sthr, std::vector<int32_t> *soff,
                       std::vector<int32_t> *slen, std::vector<int32_t> *ssgn, int64_t *total);
 size_t job_footprint_bytes(int L, int n_T, int R, int layout, int64_t swap_entries);
+size_t halo_bytes(int L, int n_T, int R, int layout);   // exchange area of ladders split by halves (0: none)
 int device_grid(int kv, int bt, size_t lds, int n_units, int *grid);   // kv: kernel_variant()
 // Workgroups per ladder (1, 2 or 4) for one launch over the jobs descs[0..n)
 // with workgroups of bt threads and lds bytes: 2 or 4 when every job can be
@@ -51,6 +52,9 @@ int device_grid(int kv, int bt, size_t lds, int n_units, int *grid);   // kv: ke
 // ea_options (1 = never, 2 = whenever possible, 0 = when each part keeps
 // enough work).
 int choose_split_parts(const JobDesc *descs, int n, int bt, size_t lds, int kv, int split_opt);
+// Kernel variant of a launch split into `parts`: kSlabVariant (ladders split
+// by lattice halves) when every job allows it and split_opt is not 3, else kv.
+int split_variant(const JobDesc *descs, int n, int kv, int parts, int split_opt);
 
 }  // namespace ea
 
@@ -72,8 +76,9 @@ struct ea_sim {
     int64_t swap_total = 0;           // entries in the swap tables
     size_t lds = 0;                   // dynamic LDS bytes of this job's sweep workgroups
     size_t footprint = 0;             // device bytes owned by this job
+    size_t halo_size = 0;             // bytes of h.halo (0: none)
     int split_parts = 1;              // workgroups per ladder in a lone launch (1, 2 or 4)
-    int split_opt = 0;                // ea_options.split: 0 auto, 1 never, 2 whenever possible
+    int split_opt = 0;                // ea_options.split: 0 auto, 1 never, 2 whenever possible, 3 by slot groups
     bool ever_split = false;          // a split launch has run this job: its exchange may have timed out
     int64_t *d_meas = nullptr;        // measurement sums: count, q^2 [R][n_T], q^4 [R][n_T][2], C [R][n_T][L]
     int32_t *d_obs = nullptr;         // observables outputs: energy, overlap, magnetization

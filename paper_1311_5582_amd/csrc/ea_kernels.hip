@@ -675,15 +675,15 @@ __device__ __forceinline__ uint32_t certain_segments(uint32_t E, uint32_t Sb, co
 // copy are never read for its own decisions (slots do not interact).
 // NPC > 0 fixes the number of plane counters at compile time.
 //
-// With PRE (CAMSC words, SPLIT) the Philox blocks of the own groups were drawn
-// beforehand: pre[g] is the block of own group g (at most four).
+// With PRE (CAMSC words) the Philox blocks of the groups decided here were
+// drawn beforehand: pre[g] is the block of the g-th of them.
 template <int LAYOUT, bool ACC = false, bool SPLIT = false, int RNG = 0, bool PRE = false, int NPC = 0>
 __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int N, int gw, int g0, int n_T,
                                             uint32_t t, uint32_t r, uint32_t c3base, uint32_t k0, uint32_t k1,
                                             uint32_t segw, const Field &fd, uint32_t (*P)[8] = nullptr, int np = 0,
                                             int gb = 0, int ngr_own = 0, const U4 *pre = nullptr)
 {
-    static_assert(!PRE || (SPLIT && LAYOUT == 0 && RNG == 0), "pre-drawn blocks: split CAMSC words only");
+    static_assert(!PRE || (LAYOUT == 0 && RNG == 0), "pre-drawn blocks: CAMSC words only");
     constexpr uint32_t M = 0x11111111u;
     const uint32_t j6 = sm.j6[nb.i];
     // all-ones mask for an antiferromagnetic incidence ("multiply the coupling
@@ -754,14 +754,14 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
                 }
             } else {
                 switch (ngr) {
-                    case 8: F = camsc_decide<8>(X, rows, nb.g, c); break;
-                    case 7: F = camsc_decide<7>(X, rows, nb.g, c); break;
-                    case 6: F = camsc_decide<6>(X, rows, nb.g, c); break;
-                    case 5: F = camsc_decide<5>(X, rows, nb.g, c); break;
-                    case 4: F = camsc_decide<4>(X, rows, nb.g, c); break;
-                    case 3: F = camsc_decide<3>(X, rows, nb.g, c); break;
-                    case 2: F = camsc_decide<2>(X, rows, nb.g, c); break;
-                    default: F = camsc_decide<1>(X, rows, nb.g, c); break;
+                    case 8: F = camsc_decide<8, PRE>(X, rows, nb.g, c, pre); break;
+                    case 7: F = camsc_decide<7, PRE>(X, rows, nb.g, c, pre); break;
+                    case 6: F = camsc_decide<6, PRE>(X, rows, nb.g, c, pre); break;
+                    case 5: F = camsc_decide<5, PRE>(X, rows, nb.g, c, pre); break;
+                    case 4: F = camsc_decide<4, PRE>(X, rows, nb.g, c, pre); break;
+                    case 3: F = camsc_decide<3, PRE>(X, rows, nb.g, c, pre); break;
+                    case 2: F = camsc_decide<2, PRE>(X, rows, nb.g, c, pre); break;
+                    default: F = camsc_decide<1, PRE>(X, rows, nb.g, c, pre); break;
                 }
             }
             if (SPLIT) F <<= 4 * gb;
@@ -1163,6 +1163,92 @@ __device__ __forceinline__ void count_up_word(const uint32_t *words, int N, int 
 // co-residency guarantee to make progress, only PARTS workgroups per queue.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kSpinLimit = 1u << 20;   // polls of a partner's flag before giving up
+
+// The ascending swap pass of one ladder once every slot's value is in U and
+// the pairs' draws are in `draw` (both in LDS): acceptance words over all
+// (start, pair) combinations, then the walk over the rejections in wave 0,
+// which moves the temperature rows to their new slots.  Ends after a
+// barrier; U is consumed (zero again).
+__device__ __forceinline__ void swap_pass_words(const Smem &sm, const uint32_t *stab, int n_T, int wave, int nwaves,
+                                                int lane)
+{
+    const int pairs = n_T - 1;
+    // Bit k of col[j]: would pair k swap if the configuration that
+    // sat at position j before the pass had been carried up to k
+    // (j <= k)?  Waves take start positions j in turn, lanes the
+    // pairs k, so one ballot is col[j].  No data-dependent branch:
+    // a pair's table length is uniform and a non-empty table has
+    // entry 0.
+    {
+        const int k = lane;
+        const bool live = k < pairs;
+        const int kk = live ? k : 0;
+        const int u_next = sm.U[sm.sot[kk + 1]];
+        const int sg = sm.ssgn[kk];
+        const int len = sm.slen[kk];
+        const int off = sm.soff[kk];
+        const uint32_t dr = sm.draw[kk];
+        const int u_here = sm.U[sm.sot[lane < n_T ? lane : 0]];   // lane j: energy at position j
+        for (int j = wave; j < pairs; j += nwaves) {
+            const int d = __builtin_amdgcn_readlane(u_here, j) - u_next;
+            const int n = d < 0 ? -d : d;
+            const uint32_t thr = len > 0 ? stab[off + min(n, len - 1)] : 0u;
+            const bool favourable = (sg == 0) || (d == 0) || ((sg > 0) == (d > 0));
+            const bool acc = live && k >= j && (favourable || (n < len && dr < thr));
+            const uint64_t col = __ballot(acc);
+            if (lane == 0) sm.mask[j] = col;
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        // The ascending pass, visiting only its rejections: from
+        // restart point j the next rejected pair is the first k >= j
+        // whose bit is clear in col[j], and after a rejection at k
+        // the carried configuration restarts at k + 1.
+        const uint64_t col = sm.mask[lane];
+        sm.mask[lane] = 0ull;   // consumed; ready for the next swap point
+        const uint64_t open = ~col & ((1ull << pairs) - 1ull) & (~0ull << lane);   // pairs <= 63
+        const int nr = open ? (int)__builtin_ctzll(open) : 64;
+        // a run of pairs rejected right at their restart point is one step
+        const uint64_t imm = __ballot(lane < pairs && !((col >> lane) & 1ull));
+        uint64_t rej = 0;
+        int cj = 0;
+        for (;;) {   // cj grows every turn: at most `pairs` turns
+            const int run = __builtin_ctzll(~(imm >> cj));   // imm has no bit at or above pairs
+            rej |= ((1ull << run) - 1ull) << cj;
+            cj += run;
+            const int r = __builtin_amdgcn_readlane(nr, cj);
+            if (r >= pairs) break;
+            rej |= 1ull << r;
+            cj = r + 1;
+        }
+        // lane k: pair k accepted -> the configuration from position k+1
+        // comes down; rejected -> the carried one stays (it started at the
+        // last restart point at or below k)
+        int src;
+        if (lane < pairs && !((rej >> lane) & 1ull)) {
+            src = lane + 1;
+        } else {
+            const uint64_t starts = ((rej << 1) | 1ull) & (lane >= 63 ? ~0ull : ((2ull << lane) - 1ull));
+            src = 63 - __clzll((long long)starts);
+        }
+        if (lane == pairs) src = cj;
+        const int newslot = lane < n_T ? sm.sot[src] : 0;
+        if (lane < pairs && src == lane + 1) sm.acc[lane] += 1u;
+        if (lane < n_T) {
+            sm.sot[lane] = newslot;
+            sm.perm[newslot] = lane;
+            // the slot now at temperature `lane` takes that temperature's row
+            const uint4 *from = (const uint4 *)(sm.fthr + lane * kThrCols);
+            uint4 *to = (uint4 *)(sm.thr + newslot * kThrCols);
+#pragma unroll
+            for (int c = 0; c < kThrCols / 4; ++c) to[c] = from[c];
+        }
+        sm.U[lane] = 0;   // consumed
+    }
+    __syncthreads();
+}
+
 
 template <int LAYOUT, int PARTS, int RNG, bool UNITS = false, int SEP = 0>
 __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restrict__ jobs,
@@ -1568,80 +1654,7 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                     if (wave == nwaves - 1 && lane < pairs)
                         sm.draw[lane] = philox10((uint32_t)lane, tswap, r, c3swap, k0, k1).x;
                     __syncthreads();   // slot energies U and swap draws are in
-                    // Bit k of col[j]: would pair k swap if the configuration that
-                    // sat at position j before the pass had been carried up to k
-                    // (j <= k)?  Waves take start positions j in turn, lanes the
-                    // pairs k, so one ballot is col[j].  No data-dependent branch:
-                    // a pair's table length is uniform and a non-empty table has
-                    // entry 0.
-                    {
-                        const int k = lane;
-                        const bool live = k < pairs;
-                        const int kk = live ? k : 0;
-                        const int u_next = sm.U[sm.sot[kk + 1]];
-                        const int sg = sm.ssgn[kk];
-                        const int len = sm.slen[kk];
-                        const int off = sm.soff[kk];
-                        const uint32_t dr = sm.draw[kk];
-                        const int u_here = sm.U[sm.sot[lane < n_T ? lane : 0]];   // lane j: energy at position j
-                        for (int j = wave; j < pairs; j += nwaves) {
-                            const int d = __builtin_amdgcn_readlane(u_here, j) - u_next;
-                            const int n = d < 0 ? -d : d;
-                            const uint32_t thr = len > 0 ? stab[off + min(n, len - 1)] : 0u;
-                            const bool favourable = (sg == 0) || (d == 0) || ((sg > 0) == (d > 0));
-                            const bool acc = live && k >= j && (favourable || (n < len && dr < thr));
-                            const uint64_t col = __ballot(acc);
-                            if (lane == 0) sm.mask[j] = col;
-                        }
-                    }
-                    __syncthreads();
-                    if (wave == 0) {
-                        // The ascending pass, visiting only its rejections: from
-                        // restart point j the next rejected pair is the first k >= j
-                        // whose bit is clear in col[j], and after a rejection at k
-                        // the carried configuration restarts at k + 1.
-                        const uint64_t col = sm.mask[lane];
-                        sm.mask[lane] = 0ull;   // consumed; ready for the next swap point
-                        const uint64_t open = ~col & ((1ull << pairs) - 1ull) & (~0ull << lane);   // pairs <= 63
-                        const int nr = open ? (int)__builtin_ctzll(open) : 64;
-                        // a run of pairs rejected right at their restart point is one step
-                        const uint64_t imm = __ballot(lane < pairs && !((col >> lane) & 1ull));
-                        uint64_t rej = 0;
-                        int cj = 0;
-                        for (;;) {   // cj grows every turn: at most `pairs` turns
-                            const int run = __builtin_ctzll(~(imm >> cj));   // imm has no bit at or above pairs
-                            rej |= ((1ull << run) - 1ull) << cj;
-                            cj += run;
-                            const int r = __builtin_amdgcn_readlane(nr, cj);
-                            if (r >= pairs) break;
-                            rej |= 1ull << r;
-                            cj = r + 1;
-                        }
-                        // lane k: pair k accepted -> the configuration from position k+1
-                        // comes down; rejected -> the carried one stays (it started at the
-                        // last restart point at or below k)
-                        int src;
-                        if (lane < pairs && !((rej >> lane) & 1ull)) {
-                            src = lane + 1;
-                        } else {
-                            const uint64_t starts = ((rej << 1) | 1ull) & (lane >= 63 ? ~0ull : ((2ull << lane) - 1ull));
-                            src = 63 - __clzll((long long)starts);
-                        }
-                        if (lane == pairs) src = cj;
-                        const int newslot = lane < n_T ? sm.sot[src] : 0;
-                        if (lane < pairs && src == lane + 1) sm.acc[lane] += 1u;
-                        if (lane < n_T) {
-                            sm.sot[lane] = newslot;
-                            sm.perm[newslot] = lane;
-                            // the slot now at temperature `lane` takes that temperature's row
-                            const uint4 *from = (const uint4 *)(sm.fthr + lane * kThrCols);
-                            uint4 *to = (uint4 *)(sm.thr + newslot * kThrCols);
-    #pragma unroll
-                            for (int c = 0; c < kThrCols / 4; ++c) to[c] = from[c];
-                        }
-                        sm.U[lane] = 0;   // consumed
-                    }
-                    __syncthreads();
+                    swap_pass_words(sm, stab, n_T, wave, nwaves, lane);
                     if (RNG == 1) {
                         build_ptab(sm, NW, wave, nwaves, lane);
                         __syncthreads();
@@ -1677,6 +1690,278 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
             if (tid < n_T - 1) jd.swap_acc[ladder * kMaxTemps + tid] += sm.acc[tid];
         }
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Ladders split by lattice halves (CAMSC, word draws, one word per site, even
+// L >= 4, no field, natural order).  Two workgroups share a ladder: part p
+// owns the planes z0 = p L/2 .. z0 + L/2 - 1 with every slot, so that no bond
+// word, site index or random block is formed twice (a split by slot groups
+// forms every site's bond words in each part).  A part keeps its planes and
+// one halo plane on either side in LDS (LDS plane zl + 1 holds local plane zl
+// = -1 .. L/2).  Each site of its first or last plane publishes its new word,
+// tagged with the sweep index, as soon as it is updated; before its own
+// update it takes the one halo word it needs, the partner's newest word of the
+// other class across the boundary (the partner's last plane lies below this
+// part's first, its first plane above this part's last).  So the halves meet
+// word by word and only where they touch, and no class waits for the whole
+// boundary.  At a swap point each part's slot energies are sums over its own
+// sites of the summing class; the parts exchange and add them (the next
+// sweep's first draws are made meanwhile) and run the identical swap pass.
+// Tickets as in sweep_kernel with two parts.
+// ---------------------------------------------------------------------------
+struct Slab {
+    int L, H, LL, hp, hc, z0;   // H = L / 2 planes, hp = L L / 2 sites of a class per plane, hc = H hp
+    float invH, invL;
+};
+
+// Item j (0 <= j < hc) of class c in a part: local plane zl = j / hp, then
+// row y and the x of the class's parity; LDS indices with the halo planes.
+__device__ __forceinline__ Nbrs slab_site(const Slab &s, int j, int c)
+{
+    const int w = qdiv(j, s.invH);   // y + L zl
+    const int xh = j - w * (s.L >> 1);
+    const int zl = qdiv(w, s.invL);
+    const int y = w - zl * s.L;
+    const int x = 2 * xh + ((c + y + s.z0 + zl) & 1);
+    const int row = x + s.L * y;
+    Nbrs n;
+    n.i = row + s.LL * (zl + 1);
+    n.g = row + s.LL * (s.z0 + zl);
+    n.xp = (x == s.L - 1) ? n.i - (s.L - 1) : n.i + 1;
+    n.xm = (x == 0) ? n.i + (s.L - 1) : n.i - 1;
+    n.yp = (y == s.L - 1) ? n.i - (s.L - 1) * s.L : n.i + s.L;
+    n.ym = (y == 0) ? n.i + (s.L - 1) * s.L : n.i - s.L;
+    n.zp = n.i + s.LL;
+    n.zm = n.i - s.LL;
+    return n;
+}
+
+// The low word of a tagged 64-bit word once its tag has arrived.  Bounded like
+// the energy exchange: after a timeout (error set) nobody waits long again and
+// the value is 0.
+__device__ __forceinline__ uint32_t wait_tagged(const uint64_t *w, uint32_t tag, uint32_t *error)
+{
+    uint32_t spins = 0;
+    uint64_t v;
+    while ((uint32_t)((v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 32) != tag) {
+        if (++spins > kSpinLimit ||
+            ((spins & 255u) == 0u && __hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)) {
+            atomicOr(error, 1u);
+            return 0u;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return (uint32_t)v;
+}
+
+// The blocks of item j of class 0 at sweep t for all eight slot groups of the
+// word (those past the ladder go unused), drawn during a swap step: the swap
+// pass changes thresholds, not draws.  A fixed count keeps the blocks in
+// registers.
+__device__ __forceinline__ void slab_predraw(U4 (&st)[8], const Slab &g, int j, uint32_t t, uint32_t r, uint32_t c3,
+                                             uint32_t k0, uint32_t k1)
+{
+    asm volatile("" : "+v"(j));   // as in predraw_site: keep the rounds where they are written
+    const uint32_t site = (uint32_t)slab_site(g, j, 0).g;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) st[q] = philox10(site, t, r, c3 + (uint32_t)q, k0, k1);
+}
+
+// One colour class of a part at sweep t.  mine = this part's words of class c
+// (side 0 = its first plane, side 1 = its last), theirs = the partner's words
+// of the other class, whose newest tag is `want`; with poll = false (the
+// launch's first class) the halo planes loaded from HBM are current.  A site
+// on the first or last plane reads one halo cell, which only it reads, and
+// its wave runs at a raised priority: its words are the partner's halo.  (Its
+// blocks drawn while the partner's word travels measured faster without a
+// swap step but slower with one: the extra live registers spill.)  With ACC
+// the sites' bond counts after the update go into the plane counters P (the
+// summing class); with PRE the thread's first item uses the blocks in pre.
+template <bool ACC, bool PRE>
+__device__ __forceinline__ void slab_class(const Smem &sm, const Slab &g, int c, int tid, int nthr, int NL, int n_T,
+                                           uint32_t t, uint32_t r, uint32_t c3flip, uint32_t k0, uint32_t k1,
+                                           uint32_t segw, uint64_t *mine, const uint64_t *theirs, uint32_t want,
+                                           bool poll, uint32_t *error, uint32_t (*P)[8], int np, const U4 *pre)
+{
+    const Field fd{false, 0u, 0u, 0, 0};
+    const uint64_t tag = (uint64_t)(t + 1u) << 32;
+    for (int j = tid; j < g.hc; j += nthr) {
+        const Nbrs nb = slab_site(g, j, c);
+        const bool first = j < g.hp, last = j >= g.hc - g.hp;   // exclusive: L/2 >= 2 planes
+        const int k = first ? j : j - (g.hc - g.hp);
+        const bool edge = __ballot(first || last) != 0ull;
+        if (edge) __builtin_amdgcn_s_setprio(2);
+        if (poll && (first || last))
+            sm.spin[first ? nb.zm : nb.zp] = wait_tagged(&theirs[first ? g.hp + k : k], want, error);
+        if (PRE && j == tid)
+            update_site<0, ACC, false, 0, true>(sm, nb, NL, 1, 0, n_T, t, r, c3flip, k0, k1, segw, fd, P, np, 0, 0,
+                                                pre);
+        else
+            update_site<0, ACC>(sm, nb, NL, 1, 0, n_T, t, r, c3flip, k0, k1, segw, fd, P, np);
+        if (first || last)
+            __hip_atomic_store(&mine[first ? k : g.hp + k], tag | sm.spin[nb.i], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        if (edge) __builtin_amdgcn_s_setprio(0);
+    }
+}
+
+template <bool UNITS>
+__global__ void __launch_bounds__(kMaxBlock) slab_kernel(const JobDesc *__restrict__ jobs,
+                                                         const uint32_t *__restrict__ units, int n_units,
+                                                         uint32_t *queue)
+{
+    extern __shared__ __align__(16) uint8_t smem_raw[];
+    __shared__ uint32_t s_next;
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int nwaves = nthr >> 6;
+
+    // one ticket per workgroup: the two consecutive tickets of a queue are the
+    // halves of one ladder (see sweep_kernel)
+    const uint32_t xq = blockIdx.x & 7u;
+    if (tid == 0) s_next = atomicAdd(queue + xq, 1u);
+    __syncthreads();
+    const uint32_t tk = __builtin_amdgcn_readfirstlane(s_next);
+    const int part = (int)(tk & 1u);
+    const uint32_t li = (tk >> 1) * 8u + xq;
+    if (li >= (uint32_t)n_units) return;   // the partner's ticket is past the end too
+    const uint32_t unit = UNITS ? units[li] : li;
+    const JobDesc &jd = jobs[unit >> 20];
+    const int ladder = unit & 0xFFFFF;
+    const int L = jd.L, N = jd.N, n_T = jd.n_T;
+    Slab g;
+    g.L = L;
+    g.H = L >> 1;
+    g.LL = L * L;
+    g.hp = g.LL >> 1;
+    g.hc = g.H * g.hp;
+    g.z0 = part * g.H;
+    g.invH = jd.invH;
+    g.invL = jd.invL;
+    const int NL = (g.H + 2) * g.LL;   // own planes and the two halo planes
+    const uint32_t r = (uint32_t)(ladder >> 1);
+    const uint32_t copy = (uint32_t)(ladder & 1);
+    const uint32_t c3flip = (kDomainFlip << 28) | (copy << 24);
+    const uint32_t c3swap = (kDomainSwap << 28) | (copy << 24);
+    const uint32_t k0 = jd.key0, k1 = jd.key1;
+    const uint32_t segw = jd.seg_bits;
+    const int n_swap_lds = jd.swap_lds;
+    const Smem sm = carve(smem_raw, NL, 1, n_swap_lds, 0, 0u, 0);
+    uint32_t *g_spin = jd.spins + (size_t)ladder * N;
+    const uint8_t *g_j6 = jd.j6 + (size_t)r * N;
+    uint64_t *hx = jd.halo + (size_t)ladder * 8u * (uint32_t)g.hp;   // [part][class][side][hp]
+
+    for (int idx = tid; idx < NL; idx += nthr) {
+        const int pl = qdiv(qdiv(idx, g.invL), g.invL);   // LDS plane: local plane pl - 1
+        int zg = g.z0 + pl - 1;
+        zg = zg < 0 ? zg + L : (zg >= L ? zg - L : zg);
+        const int nat = idx + (zg - pl) * g.LL;
+        sm.spin[idx] = g_spin[nat];
+        sm.j6[idx] = g_j6[nat];
+    }
+    for (int idx = tid; idx < n_T * kThrCols; idx += nthr) sm.fthr[idx] = jd.flip_thr[idx];
+    for (int idx = tid; idx < n_swap_lds; idx += nthr) sm.stab[idx] = jd.swap_thr[idx];
+    if (tid < kMaxTemps) {
+        sm.perm[tid] = tid < n_T ? jd.temp_of_slot[ladder * kMaxTemps + tid] : 0;
+        sm.acc[tid] = 0;
+        sm.U[tid] = 0;
+        sm.up[tid] = 0;
+        sm.mask[tid] = 0ull;
+        sm.soff[tid] = jd.swap_off[tid];
+        sm.slen[tid] = jd.swap_len[tid];
+        sm.ssgn[tid] = jd.swap_sgn[tid];
+    }
+    __syncthreads();
+    if (tid < n_T) sm.sot[sm.perm[tid]] = tid;
+    for (int idx = tid; idx < kMaxTemps * kThrCols; idx += nthr) {
+        const int slot = idx / kThrCols;
+        sm.thr[idx] = slot < n_T ? sm.fthr[sm.perm[slot] * kThrCols + (idx % kThrCols)] : 0u;
+    }
+    __syncthreads();
+    const uint32_t *stab = n_swap_lds ? sm.stab : jd.swap_thr;
+
+    uint32_t t = __builtin_amdgcn_readfirstlane(*jd.sweep_ctr);
+    int remaining = jd.n_sweeps;
+    const int se = jd.swap_every;
+    const int np_b = planes_for_class(g.hc, nthr);   // at most 8 (the host checks)
+    const int other = 1 - part;
+    bool poll = false;     // the launch's first class reads the halo planes loaded from HBM
+    bool c0_done = false;  // class 0 of sweep t already ran (after the last swap pass)
+    U4 st[8];
+    while (remaining > 0) {
+        int chunk = remaining;
+        bool swap_now = false;
+        if (se > 0) {
+            const int to_swap = se - (int)(t % (uint32_t)se);
+            if (to_swap <= remaining) {
+                chunk = to_swap;
+                swap_now = true;
+            }
+        }
+        uint32_t P[1][8];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) P[0][p] = 0u;
+        for (int s = 0; s < chunk; ++s) {
+            const uint32_t ts = t + (uint32_t)s;
+            for (int c = 0; c < 2; ++c) {
+                if (c == 0 && s == 0 && c0_done) continue;
+                uint64_t *mine = hx + (size_t)((part * 2 + c) * 2) * g.hp;
+                const uint64_t *theirs = hx + (size_t)((other * 2 + 1 - c) * 2) * g.hp;
+                const uint32_t want = c == 0 ? ts : ts + 1u;   // the partner's last class-(1 - c) update
+                if (c == 1 && swap_now && s == chunk - 1) {
+                    slab_class<true, false>(sm, g, c, tid, nthr, NL, n_T, ts, r, c3flip, k0, k1, segw, mine, theirs,
+                                            want, poll, jd.error, P, np_b, nullptr);
+                    reduce_planes8_add<1>(P[0], np_b, n_T, sm.U, 0);
+                } else {
+                    slab_class<false, false>(sm, g, c, tid, nthr, NL, n_T, ts, r, c3flip, k0, k1, segw, mine, theirs,
+                                             want, poll, jd.error, nullptr, 0, nullptr);
+                }
+                poll = true;
+                __syncthreads();
+            }
+        }
+        c0_done = false;
+        if (swap_now && n_T > 1) {
+            // this part's energies are complete (the class barrier); add the partner's
+            const uint32_t tswap = t + (uint32_t)chunk - 1u;
+            const uint32_t tag = tswap + 1u;
+            const bool next = remaining > chunk;
+            uint64_t *xb = jd.xchg + ((size_t)ladder * 2 + ((tswap / (uint32_t)se) & 1u)) * kMaxTemps;
+            if (tid < n_T)
+                __hip_atomic_store(&xb[part * 32 + tid], ((uint64_t)tag << 32) | (uint32_t)sm.U[tid],
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // the next sweep's draws at this thread's first class-0 site while the sums travel
+            if (next && tid < g.hc) slab_predraw(st, g, tid, tswap + 1u, r, c3flip, k0, k1);
+            if (tid < n_T) sm.U[tid] += (int32_t)wait_tagged(&xb[other * 32 + tid], tag, jd.error);
+            if (wave == nwaves - 1 && lane < n_T - 1)
+                sm.draw[lane] = philox10((uint32_t)lane, tswap, r, c3swap, k0, k1).x;
+            __syncthreads();   // slot energies U and swap draws are in
+            swap_pass_words(sm, stab, n_T, wave, nwaves, lane);
+            if (next) {
+                // class 0 of the next sweep, its first sites with the blocks drawn above
+                const uint32_t tn = tswap + 1u;
+                slab_class<false, true>(sm, g, 0, tid, nthr, NL, n_T, tn, r, c3flip, k0, k1, segw,
+                                        hx + (size_t)(part * 4) * g.hp, hx + (size_t)(other * 4 + 2) * g.hp, tn, true,
+                                        jd.error, nullptr, 0, st);
+                __syncthreads();
+                c0_done = true;
+            }
+        } else if (swap_now) {
+            if (tid < kMaxTemps) sm.U[tid] = 0;
+            __syncthreads();
+        }
+        t += (uint32_t)chunk;
+        remaining -= chunk;
+    }
+    // own planes back: they are contiguous in both orders
+    for (int idx = g.LL + tid; idx < (g.H + 1) * g.LL; idx += nthr) g_spin[idx + (g.z0 - 1) * g.LL] = sm.spin[idx];
+    if (tid < n_T && part == 0) {
+        jd.temp_of_slot[ladder * kMaxTemps + tid] = sm.perm[tid];
+        if (tid < n_T - 1) jd.swap_acc[ladder * kMaxTemps + tid] += sm.acc[tid];
     }
 }
 
@@ -1914,9 +2199,11 @@ hipError_t launch_init_spins(const JobDesc *d_job, const JobDesc &h, int layout,
 
 // Sweep kernel variants: kv = 0 CAMSC, 1 AMSC4, 2 CAMSC with plane draws, 3 AMSC3, 4 AMSC1;
 // split ladders (parts 2 or 4, CAMSC) read the unit list when `listed`; sep =
-// spin words in LDS by colour class (lone CAMSC launches).
+// spin words in LDS by colour class (lone CAMSC launches); kSlabVariant =
+// ladders split by lattice halves (two parts).
 static const void *sweep_fn(int kv, int parts, bool listed = false, int sep = 0)
 {
+    if (kv == kSlabVariant) return listed ? (const void *)slab_kernel<true> : (const void *)slab_kernel<false>;
     if (kv == 1) return (const void *)sweep_kernel<1, 1, 0>;
     if (kv == 3) return (const void *)sweep_kernel<2, 1, 0>;
     if (kv == 4) return (const void *)sweep_kernel<3, 1, 0>;
@@ -1942,7 +2229,7 @@ static const void *sweep_fn(int kv, int parts, bool listed = false, int sep = 0)
 hipError_t sweep_set_lds(int kv, int parts, size_t lds)
 {
     // the attribute is process-wide per kernel; raise it only when a launch needs more
-    static std::atomic<size_t> set_max[5][3] = {};
+    static std::atomic<size_t> set_max[kSlabVariant + 1][3] = {};
     const int pi = parts == 4 ? 2 : (parts == 2 ? 1 : 0);
     std::atomic<size_t> &cur = set_max[kv][pi];
     if (lds <= cur.load()) return hipSuccess;

@@ -93,24 +93,27 @@ static int launchset_plan(LaunchSet &ls, const std::vector<JobDesc> &descs, cons
     for (const JobDesc &d : descs)
         if (d.n_sweeps > 0) live.push_back(d);
     ls.parts = choose_split_parts(live.data(), (int)live.size(), ls.bt, ls.lds, layout, split_opt);
+    if (ls.parts > 1) ls.layout = split_variant(live.data(), (int)live.size(), layout, ls.parts, split_opt);
     if (ls.parts > 1)
         ls.grid = split_grid(ls.n_units, ls.parts);
     else if (int rc = device_grid(layout, ls.bt, ls.lds, ls.n_units, &ls.grid))
         return rc;
-    EA_HIP(sweep_set_lds(layout, ls.parts, ls.lds));   // before any capture: not a stream operation
+    EA_HIP(sweep_set_lds(ls.layout, ls.parts, ls.lds));   // before any capture: not a stream operation
     return EA_OK;
 }
 
 // The split choice of a launch over several jobs: never if any job asks for
-// never, whenever possible if every job asks for that, otherwise automatic.
+// never, whenever possible if every job asks for that (by slot groups if every
+// job asks for slot groups), otherwise automatic.
 static int batch_split_opt(ea_sim *const *sims, int n)
 {
-    bool all_force = true;
+    bool all_force = true, all_slots = true;
     for (int j = 0; j < n; ++j) {
         if (sims[j]->split_opt == 1) return 1;
-        if (sims[j]->split_opt != 2) all_force = false;
+        if (sims[j]->split_opt != 2 && sims[j]->split_opt != 3) all_force = false;
+        if (sims[j]->split_opt != 3) all_slots = false;
     }
-    return all_force ? 2 : 0;
+    return all_slots ? 3 : (all_force ? 2 : 0);
 }
 
 // Plan a launch and give it device arrays of its own.
@@ -254,6 +257,12 @@ static int autotune_shape(const std::vector<JobDesc> &descs, const std::vector<s
         if (e == hipSuccess) bufs.push_back(ct), e = hipMalloc(&xc, xchg_bytes);
         if (e == hipSuccess) bufs.push_back(xc), e = hipMalloc(&er, 4);
         if (e == hipSuccess) bufs.push_back(er);
+        void *hl = nullptr;
+        const size_t halo_sz = d.halo ? halo_bytes(d.L, d.n_T, d.ladders / 2, EA_LAYOUT_CAMSC) : 0;
+        if (e == hipSuccess && halo_sz) {
+            e = hipMalloc(&hl, halo_sz);
+            if (e == hipSuccess) bufs.push_back(hl), e = hipMemsetAsync(hl, 0, halo_sz, st);
+        }
         // own exchange words: the scratch run's sweep tags must never reach the job's
         if (e == hipSuccess) e = hipMemsetAsync(xc, 0, xchg_bytes, st);
         if (e == hipSuccess) e = hipMemsetAsync(er, 0, 4, st);
@@ -272,6 +281,7 @@ static int autotune_shape(const std::vector<JobDesc> &descs, const std::vector<s
         d.sweep_ctr = (uint32_t *)ct;
         d.xchg = (uint64_t *)xc;
         d.error = (uint32_t *)er;
+        d.halo = (uint64_t *)hl;
         work += (int64_t)d.ladders * d.N * d.n_T;
     }
     // a few sweeps, enough for ~50 ms-equivalent of the largest config at 1 ps/flip
@@ -387,13 +397,15 @@ int ea_sweep_batch(ea_sim *const *sims, int n_sims, const int64_t *n_sweeps, con
         s->h.n_sweeps = (int32_t)n_sweeps[0];
         s->h.swap_every = swap_every[0];
         EA_HIP(hipMemcpyAsync(&s->d_job->n_sweeps, &s->h.n_sweeps, 2 * sizeof(int32_t), hipMemcpyHostToDevice, st));
-        const int kv = kernel_variant(s->layout, s->h.rng);
+        int kv = kernel_variant(s->layout, s->h.rng);
         const int parts = s->split_parts;
         int grid = 0;
-        if (parts > 1)
+        if (parts > 1) {
             grid = split_grid(s->h.ladders, parts);
-        else if (int rc = device_grid(kv, s->block_threads, s->lds, s->h.ladders, &grid))
+            kv = split_variant(&s->h, 1, kv, parts, s->split_opt);
+        } else if (int rc = device_grid(kv, s->block_threads, s->lds, s->h.ladders, &grid)) {
             return rc;
+        }
         EA_HIP(launch_sweep(s->d_job, 1, s->d_units, s->h.ladders, s->d_counters + 1, kv, parts, s->h.site_order,
                             s->block_threads,
                             s->lds, grid, st));

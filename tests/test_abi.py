@@ -70,7 +70,7 @@ def _create(lib, L=4, n_T=4, R=1, J=None, betas=None, layout=0, block_threads=0,
     dict(L=1), dict(L=33), dict(n_T=0), dict(n_T=65, betas=np.full(65, 1.0)), dict(R=0),
     dict(layout=4), dict(layout=-1), dict(block_threads=100), dict(block_threads=2048), dict(block_threads=64, L=24),
     dict(betas=[1.0, 0.0, 0.5, 0.2]), dict(betas=[1.0, -1.0, 0.5, 0.2]), dict(betas=[1.0, float("nan"), 0.5, 0.2]),
-    dict(betas=[1.0, float("inf"), 0.5, 0.2]), dict(words_resident=-1), dict(split=3), dict(split=-1),
+    dict(betas=[1.0, float("inf"), 0.5, 0.2]), dict(words_resident=-1), dict(split=4), dict(split=-1),
     dict(rng=2), dict(rng=-1), dict(rng=1, layout=1),
     dict(field=0.3), dict(field=8.25), dict(field=float("nan")), dict(field=float("inf")), dict(field=0.5, rng=1),
     dict(L=32, n_T=64, words_resident=2, J=np.ones((1, 32 ** 3, 3), np.int8)),

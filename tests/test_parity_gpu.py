@@ -198,19 +198,22 @@ def test_set_state_rejects_bad_permutation():
         sim.set_state(s, perm, t)
 
 
+@pytest.mark.parametrize("mode", ["always", "slots"])
 @pytest.mark.parametrize("L,R,n_T,swap_every", [(8, 1, 16, 1), (16, 2, 32, 1), (6, 3, 24, 3), (4, 2, 8, 2),
                                                 (10, 1, 32, 0)])
-def test_split_ladders_equal_unsplit(oracle_lib, L, R, n_T, swap_every):
-    """A job with few ladders spreads each ladder's slot groups over 2 or 4
-    co-resident workgroups that exchange slot energies at swap points; the
-    chain is the same as one workgroup per ladder, and the oracle's."""
+def test_split_ladders_equal_unsplit(oracle_lib, L, R, n_T, swap_every, mode):
+    """A job with few ladders spreads each ladder over 2 or 4 workgroups: by
+    lattice halves (two parts, mode "always") or by slot groups that meet only
+    at swap points; the chain is the same as one workgroup per ladder, and the
+    oracle's."""
     seed = 500 + L + n_T
     J = inputs.couplings(L, R, seed)
     betas = inputs.geometric_betas(n_T, 0.4, 2.0)
-    a = B.Sim(L, J, betas, seed, split="always")
+    a = B.Sim(L, J, betas, seed, split=mode)
     b = B.Sim(L, J, betas, seed, split=False)
     print(f"[parity] split info {a.info()} unsplit {b.info()}", flush=True)
     assert a.info()["split_parts"] > 1 and b.info()["split_parts"] == 1
+    assert a.info()["split_by_halves"] == (mode == "always" and a.info()["split_parts"] == 2)
     for n in (5, 1, 14):
         a.sweep(n, swap_every)
         b.sweep(n, swap_every)
@@ -230,15 +233,38 @@ def test_split_ladders_equal_unsplit(oracle_lib, L, R, n_T, swap_every):
     (10, 1, 16, 2, 128, None),         # 4 parts x 1 own group, PT every second sweep
 ])
 def test_split_launch_shapes(oracle_lib, L, R, n_T, swap_every, bt, rids):
-    """Split ladders at workgroup sizes that give a thread more or fewer than
-    the two class-0 sites whose next-sweep draws the swap step makes ahead of
-    time, and every number of own slot groups: the oracle's chain, with calls
-    that end right after a swap point and mid-interval."""
-    sim, *_ = run_pair(oracle_lib, L, R, n_T, 7000 + 7 * L + n_T, 21, swap_every, split="always", block_threads=bt,
+    """Split ladders by slot groups at workgroup sizes that give a thread more
+    or fewer than the two class-0 sites whose next-sweep draws the swap step
+    makes ahead of time, and every number of own slot groups: the oracle's
+    chain, with calls that end right after a swap point and mid-interval."""
+    sim, *_ = run_pair(oracle_lib, L, R, n_T, 7000 + 7 * L + n_T, 21, swap_every, split="slots", block_threads=bt,
                        rids=rids, splits=[1, 9, 11])
     info = sim.info()
     print(f"[parity] split launch {info}", flush=True)
-    assert info["split_parts"] > 1 and info["block_threads"] == bt
+    assert info["split_parts"] > 1 and info["block_threads"] == bt and not info["split_by_halves"]
+
+
+@pytest.mark.parametrize("L,R,n_T,swap_every,bt,rids", [
+    (4, 1, 8, 1, 0, None),             # two planes per half: every site is on a boundary plane
+    (16, 2, 24, 1, 1024, None),        # one site of a class per thread
+    (20, 1, 20, 3, 256, None),         # five slot groups (no even split by groups), eight sites per thread
+    (6, 3, 24, 0, 64, None),           # three planes per half, no PT, two sites per thread
+    (8, 1, 1, 1, 0, None),             # one temperature: no swap pass
+    (16, 40, 32, 1, 0, [0, 17, 39]),   # the benchmark's shape with fewer realizations
+])
+def test_split_by_halves_equals_oracle(oracle_lib, L, R, n_T, swap_every, bt, rids):
+    """Ladders split by lattice halves along z: each part owns half the planes
+    with every slot and trades its first and last plane with the partner after
+    every colour class, and the two halves' energy sums are added at swap
+    points.  The oracle's chain, with calls ending right after a swap point and
+    mid-interval."""
+    sim, *_ = run_pair(oracle_lib, L, R, n_T, 9100 + 7 * L + n_T, 23, swap_every, split="always", block_threads=bt,
+                       rids=rids, splits=[1, 9, 13])
+    info = sim.info()
+    print(f"[parity] split by halves {info}", flush=True)
+    assert info["split_parts"] == 2 and info["split_by_halves"]
+    if bt:
+        assert info["block_threads"] == bt
 
 
 @pytest.mark.parametrize("L,R,n_T,swap_every,split,bt,wr", [
@@ -298,19 +324,20 @@ def test_field_equals_oracle(oracle_lib, L, R, n_T, layout, h, split):
     print(f"[parity] field launch {sim.info()}", flush=True)
 
 
-@pytest.mark.parametrize("L,R,n_T,parts", [
-    (16, 64, 32, 2),   # the benchmark job: 128 ladders, so 4 parts would exceed the CUs
-    (8, 4, 32, 4),     # each of 4 parts keeps 2 groups x 512 sites
-    (8, 1, 16, 1),     # too little work per part: the exchange would cost more than the split saves
-    (24, 2, 48, 1),    # two words per site: split ladders need one
+@pytest.mark.parametrize("L,R,n_T,parts,halves", [
+    (16, 64, 32, 2, True),    # the benchmark job: 128 ladders, so 4 parts would exceed the CUs
+    (8, 4, 32, 4, False),     # each of 4 parts keeps 2 groups x 512 sites
+    (8, 1, 16, 1, False),     # too little work per part: the exchange would cost more than the split saves
+    (24, 2, 48, 1, False),    # two words per site: split ladders need one
 ])
-def test_split_choice(L, R, n_T, parts):
+def test_split_choice(L, R, n_T, parts, halves):
     """The automatic choice of workgroups per ladder on a 256-CU device."""
     import torch
     if torch.cuda.get_device_properties(0).multi_processor_count != 256:
         pytest.skip("the choice depends on the number of compute units")
     sim = B.Sim(L, inputs.couplings(L, R, 3), inputs.geometric_betas(n_T, 0.5, 2.0), 3)
     assert sim.info()["split_parts"] == parts
+    assert sim.info()["split_by_halves"] == halves
     sim.close()
 
 

@@ -23,9 +23,9 @@ JOBS = [  # L, R, n_T, seed, swap_every
 ]
 
 
-def _make(L, R, n_T, seed, layout="camsc", words_resident=0):
+def _make(L, R, n_T, seed, layout="camsc", words_resident=0, split=True):
     return B.Sim(L, inputs.couplings(L, R, seed), inputs.geometric_betas(n_T, 0.4, 2.0), seed, layout=layout,
-                 words_resident=words_resident)
+                 words_resident=words_resident, split=split)
 
 
 @pytest.mark.parametrize("use_graph,autotune", [(True, True), (False, False), (True, False)])
@@ -89,15 +89,18 @@ def _trace(n, seed=9):
     return out
 
 
-@pytest.mark.parametrize("autotune", [False, True])
-def test_split_plan_and_batch_equal_alone(oracle_lib, autotune):
+@pytest.mark.parametrize("autotune,split", [(False, True), (True, True), (False, "slots")])
+def test_split_plan_and_batch_equal_alone(oracle_lib, autotune, split):
     """Jobs that together hold fewer ladders than the device has compute
-    units run with split ladders in a graph-captured plan and in a batch; every
-    replay equals the same jobs run one at a time without splitting, and one
-    realization of each job equals the oracle."""
+    units run with split ladders (by lattice halves, or by slot groups when
+    asked) in a graph-captured plan and in a batch; every replay equals the
+    same jobs run one at a time without splitting, and one realization of each
+    job equals the oracle."""
     jobs = [(16, 8, 32, 61, 1), (12, 6, 16, 62, 3), (16, 4, 24, 63, 0)]   # L, R, n_T, seed, swap_every
-    sims = [_make(L, R, n_T, seed) for L, R, n_T, seed, _ in jobs]
-    bats = [_make(L, R, n_T, seed) for L, R, n_T, seed, _ in jobs]
+    if split == "slots":   # slot groups need a count every part divides
+        jobs = [(16, 8, 32, 61, 1), (12, 6, 16, 62, 3), (16, 4, 32, 63, 0)]
+    sims = [_make(L, R, n_T, seed, split=split) for L, R, n_T, seed, _ in jobs]
+    bats = [_make(L, R, n_T, seed, split=split) for L, R, n_T, seed, _ in jobs]
     refs = [B.Sim(L, inputs.couplings(L, R, seed), inputs.geometric_betas(n_T, 0.4, 2.0), seed, split=False)
             for L, R, n_T, seed, _ in jobs]
     se = [j[4] for j in jobs]
