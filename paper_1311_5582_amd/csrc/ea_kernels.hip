@@ -675,15 +675,15 @@ __device__ __forceinline__ uint32_t certain_segments(uint32_t E, uint32_t Sb, co
 // copy are never read for its own decisions (slots do not interact).
 // NPC > 0 fixes the number of plane counters at compile time.
 //
-// With PRE (CAMSC words) the Philox blocks of the groups decided here were
-// drawn beforehand: pre[g] is the block of the g-th of them.
+// With PRE (CAMSC words, SPLIT) the Philox blocks of the own groups were drawn
+// beforehand: pre[g] is the block of own group g (at most four).
 template <int LAYOUT, bool ACC = false, bool SPLIT = false, int RNG = 0, bool PRE = false, int NPC = 0>
 __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int N, int gw, int g0, int n_T,
                                             uint32_t t, uint32_t r, uint32_t c3base, uint32_t k0, uint32_t k1,
                                             uint32_t segw, const Field &fd, uint32_t (*P)[8] = nullptr, int np = 0,
                                             int gb = 0, int ngr_own = 0, const U4 *pre = nullptr)
 {
-    static_assert(!PRE || (LAYOUT == 0 && RNG == 0), "pre-drawn blocks: CAMSC words only");
+    static_assert(!PRE || (SPLIT && LAYOUT == 0 && RNG == 0), "pre-drawn blocks: split CAMSC words only");
     constexpr uint32_t M = 0x11111111u;
     const uint32_t j6 = sm.j6[nb.i];
     // all-ones mask for an antiferromagnetic incidence ("multiply the coupling
@@ -754,14 +754,14 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
                 }
             } else {
                 switch (ngr) {
-                    case 8: F = camsc_decide<8, PRE>(X, rows, nb.g, c, pre); break;
-                    case 7: F = camsc_decide<7, PRE>(X, rows, nb.g, c, pre); break;
-                    case 6: F = camsc_decide<6, PRE>(X, rows, nb.g, c, pre); break;
-                    case 5: F = camsc_decide<5, PRE>(X, rows, nb.g, c, pre); break;
-                    case 4: F = camsc_decide<4, PRE>(X, rows, nb.g, c, pre); break;
-                    case 3: F = camsc_decide<3, PRE>(X, rows, nb.g, c, pre); break;
-                    case 2: F = camsc_decide<2, PRE>(X, rows, nb.g, c, pre); break;
-                    default: F = camsc_decide<1, PRE>(X, rows, nb.g, c, pre); break;
+                    case 8: F = camsc_decide<8>(X, rows, nb.g, c); break;
+                    case 7: F = camsc_decide<7>(X, rows, nb.g, c); break;
+                    case 6: F = camsc_decide<6>(X, rows, nb.g, c); break;
+                    case 5: F = camsc_decide<5>(X, rows, nb.g, c); break;
+                    case 4: F = camsc_decide<4>(X, rows, nb.g, c); break;
+                    case 3: F = camsc_decide<3>(X, rows, nb.g, c); break;
+                    case 2: F = camsc_decide<2>(X, rows, nb.g, c); break;
+                    default: F = camsc_decide<1>(X, rows, nb.g, c); break;
                 }
             }
             if (SPLIT) F <<= 4 * gb;
@@ -1760,48 +1760,115 @@ __device__ __forceinline__ uint32_t wait_tagged(const uint64_t *w, uint32_t tag,
 // word (those past the ladder go unused), drawn during a swap step: the swap
 // pass changes thresholds, not draws.  A fixed count keeps the blocks in
 // registers.
-__device__ __forceinline__ void slab_predraw(U4 (&st)[8], const Slab &g, int j, uint32_t t, uint32_t r, uint32_t c3,
+__device__ __forceinline__ void slab_predraw(U4 (&st)[8], uint32_t site, uint32_t t, uint32_t r, uint32_t c3,
                                              uint32_t k0, uint32_t k1)
 {
-    asm volatile("" : "+v"(j));   // as in predraw_site: keep the rounds where they are written
-    const uint32_t site = (uint32_t)slab_site(g, j, 0).g;
+    asm volatile("" : "+v"(site));   // as in predraw_site: keep the rounds where they are written
 #pragma unroll
     for (int q = 0; q < 8; ++q) st[q] = philox10(site, t, r, c3 + (uint32_t)q, k0, k1);
 }
 
-// One colour class of a part at sweep t.  mine = this part's words of class c
-// (side 0 = its first plane, side 1 = its last), theirs = the partner's words
-// of the other class, whose newest tag is `want`; with poll = false (the
-// launch's first class) the halo planes loaded from HBM are current.  A site
-// on the first or last plane reads one halo cell, which only it reads, and
-// its wave runs at a raised priority: its words are the partner's halo.  (Its
-// blocks drawn while the partner's word travels measured faster without a
-// swap step but slower with one: the extra live registers spill.)  With ACC
-// the sites' bond counts after the update go into the plane counters P (the
-// summing class); with PRE the thread's first item uses the blocks in pre.
-template <bool ACC, bool PRE>
-__device__ __forceinline__ void slab_class(const Smem &sm, const Slab &g, int c, int tid, int nthr, int NL, int n_T,
+// The part of a CAMSC site update that needs only the spins (one word per
+// site, no field), as in update_site: the site's word S, its segment words X
+// (segment j of X[k] = 2E+S of slot 4j + k) and the certain flips (E >= 3).
+struct CamscPrep {
+    uint32_t S, always;
+    uint32_t X[4];
+};
+
+__device__ __forceinline__ CamscPrep camsc_prepare(const Smem &sm, const Nbrs &nb)
+{
+    const uint32_t j6 = sm.j6[nb.i];
+    const uint32_t *sw = sm.spin;
+    CamscPrep p;
+    p.S = sw[nb.i];
+    const uint32_t e0 = p.S ^ sw[nb.xp] ^ (0u - (j6 & 1u));
+    const uint32_t e1 = p.S ^ sw[nb.xm] ^ (0u - ((j6 >> 1) & 1u));
+    const uint32_t e2 = p.S ^ sw[nb.yp] ^ (0u - ((j6 >> 2) & 1u));
+    const uint32_t e3 = p.S ^ sw[nb.ym] ^ (0u - ((j6 >> 3) & 1u));
+    const uint32_t e4 = p.S ^ sw[nb.zp] ^ (0u - ((j6 >> 4) & 1u));
+    const uint32_t e5 = p.S ^ sw[nb.zm] ^ (0u - ((j6 >> 5) & 1u));
+    const uint32_t s1 = xor3(e0, e1, e2), c1 = maj3(e0, e1, e2);
+    const uint32_t s2 = xor3(e3, e4, e5), c2 = maj3(e3, e4, e5);
+    const uint32_t E0 = s1 ^ s2, kk = s1 & s2;
+    const uint32_t E1 = xor3(c1, c2, kk), E2 = maj3(c1, c2, kk);
+    p.X[0] = p.S;
+    p.X[1] = E0;
+    p.X[2] = E1;
+    p.X[3] = E2;
+    swap_bits(p.X[0], p.X[2], 2, 0x33333333u);
+    swap_bits(p.X[1], p.X[3], 2, 0x33333333u);
+    swap_bits(p.X[0], p.X[1], 1, 0x55555555u);
+    swap_bits(p.X[2], p.X[3], 1, 0x55555555u);
+    p.always = E2 | (E1 & E0);
+    return p;
+}
+
+// The rest: decisions against the rows by slot with the blocks drawn
+// beforehand; returns the new spin word.
+__device__ __forceinline__ uint32_t camsc_finish(const Smem &sm, const CamscPrep &p, int n_T, const Ctr &c,
+                                                 const U4 *pre)
+{
+    const int ngr = n_T >= 32 ? 8 : (n_T + 3) >> 2;
+    const uint32_t valid = n_T >= 32 ? 0xFFFFFFFFu : ((1u << n_T) - 1u);
+    uint32_t F;
+    switch (ngr) {
+        case 8: F = camsc_decide<8, true>(p.X, sm.thr, 0u, c, pre); break;
+        case 7: F = camsc_decide<7, true>(p.X, sm.thr, 0u, c, pre); break;
+        case 6: F = camsc_decide<6, true>(p.X, sm.thr, 0u, c, pre); break;
+        case 5: F = camsc_decide<5, true>(p.X, sm.thr, 0u, c, pre); break;
+        case 4: F = camsc_decide<4, true>(p.X, sm.thr, 0u, c, pre); break;
+        case 3: F = camsc_decide<3, true>(p.X, sm.thr, 0u, c, pre); break;
+        case 2: F = camsc_decide<2, true>(p.X, sm.thr, 0u, c, pre); break;
+        default: F = camsc_decide<1, true>(p.X, sm.thr, 0u, c, pre); break;
+    }
+    return p.S ^ ((F | p.always) & valid);
+}
+
+// Where item j of a class sits on the part's boundary: first plane (side 0),
+// last plane (side 1) or neither; k = its index within that plane.
+struct SlabEdge {
+    bool first, last;
+    int k;
+};
+
+__device__ __forceinline__ SlabEdge slab_edge(const Slab &g, int j)
+{
+    SlabEdge e;
+    e.first = j < g.hp;
+    e.last = j >= g.hc - g.hp;   // exclusive with first: L/2 >= 2 planes
+    e.k = e.first ? j : j - (g.hc - g.hp);
+    return e;
+}
+
+// One colour class of a part at sweep t, items j0, j0 + nthr, ...  mine =
+// this part's words of class c (side 0 = its first plane, side 1 = its last),
+// theirs = the partner's words of the other class, whose newest tag is `want`;
+// with poll = false (the launch's first class) the halo planes loaded from HBM
+// are current.  A site on the first or last plane reads one halo cell, which
+// only it reads, and its wave runs at a raised priority: its words are the
+// partner's halo.  (Its blocks drawn while the partner's word travels measured
+// faster without a swap step but slower with one: the extra live registers
+// spill.)  With ACC the sites' bond counts after the update go into the plane
+// counters P (the summing class).
+template <bool ACC>
+__device__ __forceinline__ void slab_class(const Smem &sm, const Slab &g, int c, int j0, int nthr, int NL, int n_T,
                                            uint32_t t, uint32_t r, uint32_t c3flip, uint32_t k0, uint32_t k1,
                                            uint32_t segw, uint64_t *mine, const uint64_t *theirs, uint32_t want,
-                                           bool poll, uint32_t *error, uint32_t (*P)[8], int np, const U4 *pre)
+                                           bool poll, uint32_t *error, uint32_t (*P)[8], int np)
 {
     const Field fd{false, 0u, 0u, 0, 0};
     const uint64_t tag = (uint64_t)(t + 1u) << 32;
-    for (int j = tid; j < g.hc; j += nthr) {
+    for (int j = j0; j < g.hc; j += nthr) {
         const Nbrs nb = slab_site(g, j, c);
-        const bool first = j < g.hp, last = j >= g.hc - g.hp;   // exclusive: L/2 >= 2 planes
-        const int k = first ? j : j - (g.hc - g.hp);
-        const bool edge = __ballot(first || last) != 0ull;
+        const SlabEdge e = slab_edge(g, j);
+        const bool edge = __ballot(e.first || e.last) != 0ull;
         if (edge) __builtin_amdgcn_s_setprio(2);
-        if (poll && (first || last))
-            sm.spin[first ? nb.zm : nb.zp] = wait_tagged(&theirs[first ? g.hp + k : k], want, error);
-        if (PRE && j == tid)
-            update_site<0, ACC, false, 0, true>(sm, nb, NL, 1, 0, n_T, t, r, c3flip, k0, k1, segw, fd, P, np, 0, 0,
-                                                pre);
-        else
-            update_site<0, ACC>(sm, nb, NL, 1, 0, n_T, t, r, c3flip, k0, k1, segw, fd, P, np);
-        if (first || last)
-            __hip_atomic_store(&mine[first ? k : g.hp + k], tag | sm.spin[nb.i], __ATOMIC_RELAXED,
+        if (poll && (e.first || e.last))
+            sm.spin[e.first ? nb.zm : nb.zp] = wait_tagged(&theirs[e.first ? g.hp + e.k : e.k], want, error);
+        update_site<0, ACC>(sm, nb, NL, 1, 0, n_T, t, r, c3flip, k0, k1, segw, fd, P, np);
+        if (e.first || e.last)
+            __hip_atomic_store(&mine[e.first ? e.k : g.hp + e.k], tag | sm.spin[nb.i], __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         if (edge) __builtin_amdgcn_s_setprio(0);
     }
@@ -1913,12 +1980,12 @@ __global__ void __launch_bounds__(kMaxBlock) slab_kernel(const JobDesc *__restri
                 const uint64_t *theirs = hx + (size_t)((other * 2 + 1 - c) * 2) * g.hp;
                 const uint32_t want = c == 0 ? ts : ts + 1u;   // the partner's last class-(1 - c) update
                 if (c == 1 && swap_now && s == chunk - 1) {
-                    slab_class<true, false>(sm, g, c, tid, nthr, NL, n_T, ts, r, c3flip, k0, k1, segw, mine, theirs,
-                                            want, poll, jd.error, P, np_b, nullptr);
+                    slab_class<true>(sm, g, c, tid, nthr, NL, n_T, ts, r, c3flip, k0, k1, segw, mine, theirs, want,
+                                     poll, jd.error, P, np_b);
                     reduce_planes8_add<1>(P[0], np_b, n_T, sm.U, 0);
                 } else {
-                    slab_class<false, false>(sm, g, c, tid, nthr, NL, n_T, ts, r, c3flip, k0, k1, segw, mine, theirs,
-                                             want, poll, jd.error, nullptr, 0, nullptr);
+                    slab_class<false>(sm, g, c, tid, nthr, NL, n_T, ts, r, c3flip, k0, k1, segw, mine, theirs, want,
+                                      poll, jd.error, nullptr, 0);
                 }
                 poll = true;
                 __syncthreads();
@@ -1929,24 +1996,47 @@ __global__ void __launch_bounds__(kMaxBlock) slab_kernel(const JobDesc *__restri
             // this part's energies are complete (the class barrier); add the partner's
             const uint32_t tswap = t + (uint32_t)chunk - 1u;
             const uint32_t tag = tswap + 1u;
+            const uint32_t tn = tswap + 1u;
             const bool next = remaining > chunk;
             uint64_t *xb = jd.xchg + ((size_t)ladder * 2 + ((tswap / (uint32_t)se) & 1u)) * kMaxTemps;
             if (tid < n_T)
                 __hip_atomic_store(&xb[part * 32 + tid], ((uint64_t)tag << 32) | (uint32_t)sm.U[tid],
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            // the next sweep's draws at this thread's first class-0 site while the sums travel
-            if (next && tid < g.hc) slab_predraw(st, g, tid, tswap + 1u, r, c3flip, k0, k1);
+            // While the sums travel: this thread's first class-0 site of the next
+            // sweep takes its halo word, draws its blocks and forms its segment
+            // words (none of which depends on the temperatures); after the swap
+            // pass only its decisions remain.
+            const bool ahead = next && tid < g.hc;
+            const SlabEdge e0 = slab_edge(g, tid);
+            CamscPrep prep;
+            int i0 = 0;
+            if (ahead) {
+                const Nbrs nb = slab_site(g, tid, 0);
+                if (e0.first || e0.last)
+                    sm.spin[e0.first ? nb.zm : nb.zp] = wait_tagged(
+                        hx + (size_t)(other * 4 + 2) * g.hp + (e0.first ? g.hp + e0.k : e0.k), tn, jd.error);
+                slab_predraw(st, (uint32_t)nb.g, tn, r, c3flip, k0, k1);
+                prep = camsc_prepare(sm, nb);
+                i0 = nb.i;
+            }
             if (tid < n_T) sm.U[tid] += (int32_t)wait_tagged(&xb[other * 32 + tid], tag, jd.error);
             if (wave == nwaves - 1 && lane < n_T - 1)
                 sm.draw[lane] = philox10((uint32_t)lane, tswap, r, c3swap, k0, k1).x;
             __syncthreads();   // slot energies U and swap draws are in
             swap_pass_words(sm, stab, n_T, wave, nwaves, lane);
             if (next) {
-                // class 0 of the next sweep, its first sites with the blocks drawn above
-                const uint32_t tn = tswap + 1u;
-                slab_class<false, true>(sm, g, 0, tid, nthr, NL, n_T, tn, r, c3flip, k0, k1, segw,
-                                        hx + (size_t)(part * 4) * g.hp, hx + (size_t)(other * 4 + 2) * g.hp, tn, true,
-                                        jd.error, nullptr, 0, st);
+                // class 0 of the next sweep: the first sites only decide
+                uint64_t *mine = hx + (size_t)(part * 4) * g.hp;
+                if (ahead) {
+                    const Ctr cc{tn, r, c3flip, k0, k1, segw};
+                    const uint32_t v = camsc_finish(sm, prep, n_T, cc, st);
+                    sm.spin[i0] = v;
+                    if (e0.first || e0.last)
+                        __hip_atomic_store(&mine[e0.first ? e0.k : g.hp + e0.k], ((uint64_t)(tn + 1u) << 32) | v,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                slab_class<false>(sm, g, 0, tid + nthr, nthr, NL, n_T, tn, r, c3flip, k0, k1, segw, mine,
+                                  hx + (size_t)(other * 4 + 2) * g.hp, tn, true, jd.error, nullptr, 0);
                 __syncthreads();
                 c0_done = true;
             }
