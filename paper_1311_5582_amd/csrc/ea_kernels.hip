@@ -1156,8 +1156,10 @@ __device__ __forceinline__ void count_up_word(const uint32_t *words, int N, int 
 // so readers need no fence; the wait is bounded and a timeout is reported
 // through an error flag, so a launch always ends), then all run the identical
 // swap pass.  Workgroups take tickets from one of eight queues, queue
-// blockIdx mod 8 (the XCD the workgroup runs on), and the PARTS consecutive
-// tickets of a queue are the parts of one ladder, so partners share an L2.
+// blockIdx mod 8, and the PARTS consecutive tickets of a queue are the parts
+// of one ladder (blocks are meant to be dealt to the eight XCDs round robin,
+// which would put partners on one XCD; nothing relies on it: the exchange
+// words are agent-scope atomics, coherent across XCDs).
 // Tickets go to workgroups in the order they start: only the most recently
 // opened ladder of a queue can lack a part, so the launch needs no
 // co-residency guarantee to make progress, only PARTS workgroups per queue.
