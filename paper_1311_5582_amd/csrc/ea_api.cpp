@@ -335,7 +335,7 @@ int choose_split_parts(const JobDesc *descs, int n, int bt, size_t lds, int kv, 
         // from 2048)
         if (ladders * parts > cus) continue;
         // two parts may split by lattice halves, which needs no even count of slot groups
-        const bool halves = parts == 2 && split_variant(descs, n, kv, parts, split_opt) == kSlabVariant;
+        const bool halves = parts == 2 && split_variant(descs, n, kv, parts, split_opt) != kv;
         bool ok = true;
         for (int j = 0; j < n && ok; ++j) {
             const int ngr = (descs[j].n_T + 3) >> 2;
@@ -352,17 +352,18 @@ int choose_split_parts(const JobDesc *descs, int n, int bt, size_t lds, int kv, 
 }
 
 // Kernel variant of a split launch: ladders split by lattice halves
-// (kSlabVariant) when every job allows it (CAMSC word draws, one word per site,
-// even L >= 4, no field, natural order, an exchange area) and the split is
-// two ways, unless split_opt asks for slot groups (3); otherwise kv.
+// (kSlabVariant for word draws, kSlabPlanesVariant for plane draws) when every
+// job allows it (CAMSC, one word per site, even L >= 4, no field, natural
+// order, an exchange area) and the split is two ways, unless split_opt asks
+// for slot groups (3); otherwise kv.
 int split_variant(const JobDesc *descs, int n, int kv, int parts, int split_opt)
 {
-    if (parts != 2 || kv != 0 || split_opt == 3 || n < 1) return kv;
+    if (parts != 2 || (kv != 0 && kv != 2) || split_opt == 3 || n < 1) return kv;
     for (int j = 0; j < n; ++j) {
         const JobDesc &d = descs[j];
         if (!d.halo || d.NW != 1 || (d.L & 1) || d.L < 4 || d.field_m != 0 || d.site_order != 0) return kv;
     }
-    return kSlabVariant;
+    return kv == 0 ? kSlabVariant : kSlabPlanesVariant;
 }
 
 // Workgroups per ladder for a lone launch of the job.
@@ -625,7 +626,7 @@ int ea_sim_split(const ea_sim *s, int *split_parts, int *by_halves)
     if (split_parts) *split_parts = s->split_parts;
     if (by_halves)
         *by_halves = s->split_parts > 1 && split_variant(&s->h, 1, kernel_variant(s->layout, s->h.rng), s->split_parts,
-                                                         s->split_opt) == kSlabVariant;
+                                                         s->split_opt) != kernel_variant(s->layout, s->h.rng);
     return EA_OK;
 }
 

@@ -148,12 +148,14 @@ __host__ __device__ inline LdsLayout lds_layout(int N, int words, int swap_entri
 // Host-side launchers (ea_kernels.hip).  Each returns the first HIP error.
 hipError_t launch_init_spins(const JobDesc *d_job, const JobDesc &h_job, int layout, hipStream_t s);
 // Sweep kernel variant: 0 CAMSC, 1 AMSC4, 2 CAMSC with plane draws, 3 AMSC3, 4 AMSC1;
-// kSlabVariant: CAMSC word draws with ladders split by lattice halves (launches only).
+// kSlabVariant / kSlabPlanesVariant: CAMSC word / plane draws with ladders split by
+// lattice halves (launches only).
 inline int kernel_variant(int layout, int rng)
 {
     return layout == 0 ? (rng ? 2 : 0) : (layout == 1 ? 1 : (layout == 2 ? 3 : 4));
 }
 constexpr int kSlabVariant = 5;
+constexpr int kSlabPlanesVariant = 6;
 // One sweep launch over n_units ladders (units[k] = job << 20 | ladder), then
 // the sweep counters advance and the queue words are re-armed.  parts = 1:
 // persistent workgroups pull ladders from queue[0]; parts = 2 or 4 (CAMSC

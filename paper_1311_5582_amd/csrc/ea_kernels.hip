@@ -145,6 +145,7 @@ __device__ __forceinline__ int checker_index(int j, int c, int L, float invH, fl
 // neighbours along x.
 struct Order {
     int sep, nh;   // nh = N / 2
+    int base;      // natural order: the LDS word of site g is g - base (0 but in a split by lattice halves)
 };
 
 // Item j of class c with LDS indices in order SEP.
@@ -228,6 +229,7 @@ __device__ __forceinline__ Smem carve(uint8_t *base, int N, int words, int swap_
     s.j6 = base + l.j6;
     s.ord.sep = sep;
     s.ord.nh = N >> 1;
+    s.ord.base = 0;
     return s;
 }
 
@@ -417,7 +419,7 @@ __device__ __forceinline__ void plane_drain(const Smem &sm, PlaneQueue &q, int l
             lt |= x & T;
             und ^= x;
         }
-        const uint32_t at = sm.ord.sep ? (uint32_t)(cls * sm.ord.nh) + (site >> 1) : site;   // LDS word of the site
+        const uint32_t at = sm.ord.sep ? (uint32_t)(cls * sm.ord.nh) + (site >> 1) : site - sm.ord.base;   // LDS word
         if (lt) atomicXor(sm.spin + wl * (uint32_t)N + at, lt << sh);
     }
     plane_push(q, blk < 3u ? und : 0u, m1, m2, (key & 0x3FFFFu) | ((blk + 1u) << 18));
@@ -1876,7 +1878,55 @@ __device__ __forceinline__ void slab_class(const Smem &sm, const Slab &g, int c,
     }
 }
 
-template <bool UNITS>
+// One colour class of a part with plane draws (as class_pass_planes): items
+// in wave-uniform rounds, each boundary site first taking its halo word; once
+// a wave's list of undecided halves is empty its sites are final, and it
+// publishes its boundary words and (ACC, the summing class) adds the bond
+// counts of its sites into the plane counters P.
+template <bool ACC>
+__device__ void slab_class_planes(const Smem &sm, const Slab &g, int c, int tid, int nthr, int NL, int n_T,
+                                  uint32_t t, uint32_t r, uint32_t c3base, uint32_t k0, uint32_t k1, uint64_t *mine,
+                                  const uint64_t *theirs, uint32_t want, bool poll, uint32_t *error,
+                                  uint32_t (*P)[8], int np)
+{
+    const int lane = tid & 63;
+    PlaneQueue q = plane_queue(sm, tid >> 6);
+    for (int jb = tid - lane; jb < g.hc; jb += nthr) {   // the same trip count for the whole wave
+        const int j = jb + lane;
+        const bool live = j < g.hc;
+        const Nbrs nb = slab_site(g, live ? j : 0, c);
+        const SlabEdge e = slab_edge(g, j);
+        if (live && poll && (e.first || e.last))
+            sm.spin[e.first ? nb.zm : nb.zp] = wait_tagged(&theirs[e.first ? g.hp + e.k : e.k], want, error);
+        update_site_planes<false>(sm, q, live, nb, NL, 1, 0, c, n_T, t, r, c3base, k0, k1, 0, 0, lane);
+    }
+    while (q.count > 0) plane_drain(sm, q, lane, NL, 0, c, t, r, c3base, k0, k1);
+    const uint64_t tag = (uint64_t)(t + 1u) << 32;
+    for (int j = tid; j < g.hc; j += nthr) {
+        const SlabEdge e = slab_edge(g, j);
+        if (!ACC && !(e.first || e.last)) continue;
+        const Nbrs nb = slab_site(g, j, c);
+        const uint32_t *sw = sm.spin;
+        const uint32_t S = sw[nb.i];
+        if (e.first || e.last)
+            __hip_atomic_store(&mine[e.first ? e.k : g.hp + e.k], tag | S, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ACC) {
+            const uint32_t j6 = sm.j6[nb.i];
+            const uint32_t e0 = S ^ sw[nb.xp] ^ (0u - (j6 & 1u));
+            const uint32_t e1 = S ^ sw[nb.xm] ^ (0u - ((j6 >> 1) & 1u));
+            const uint32_t e2 = S ^ sw[nb.yp] ^ (0u - ((j6 >> 2) & 1u));
+            const uint32_t e3 = S ^ sw[nb.ym] ^ (0u - ((j6 >> 3) & 1u));
+            const uint32_t e4 = S ^ sw[nb.zp] ^ (0u - ((j6 >> 4) & 1u));
+            const uint32_t e5 = S ^ sw[nb.zm] ^ (0u - ((j6 >> 5) & 1u));
+            const uint32_t s1 = xor3(e0, e1, e2), c1 = maj3(e0, e1, e2);
+            const uint32_t s2 = xor3(e3, e4, e5), c2 = maj3(e3, e4, e5);
+            const uint32_t kk = s1 & s2;
+            planes_add3<0>(*P, s1 ^ s2, xor3(c1, c2, kk), maj3(c1, c2, kk), np);
+        }
+    }
+}
+
+template <bool UNITS, int RNG>
 __global__ void __launch_bounds__(kMaxBlock) slab_kernel(const JobDesc *__restrict__ jobs,
                                                          const uint32_t *__restrict__ units, int n_units,
                                                          uint32_t *queue)
@@ -1914,12 +1964,13 @@ __global__ void __launch_bounds__(kMaxBlock) slab_kernel(const JobDesc *__restri
     const int NL = (g.H + 2) * g.LL;   // own planes and the two halo planes
     const uint32_t r = (uint32_t)(ladder >> 1);
     const uint32_t copy = (uint32_t)(ladder & 1);
-    const uint32_t c3flip = (kDomainFlip << 28) | (copy << 24);
+    const uint32_t c3flip = ((RNG == 1 ? kDomainPlane : kDomainFlip) << 28) | (copy << 24);
     const uint32_t c3swap = (kDomainSwap << 28) | (copy << 24);
     const uint32_t k0 = jd.key0, k1 = jd.key1;
     const uint32_t segw = jd.seg_bits;
     const int n_swap_lds = jd.swap_lds;
-    const Smem sm = carve(smem_raw, NL, 1, n_swap_lds, 0, 0u, 0);
+    Smem sm = carve(smem_raw, NL, 1, n_swap_lds, 0, RNG == 1 ? kPlaneItemBytes : 0u, 0);
+    sm.ord.base = (g.z0 - 1) * g.LL;   // own site g sits at LDS word g - base
     uint32_t *g_spin = jd.spins + (size_t)ladder * N;
     const uint8_t *g_j6 = jd.j6 + (size_t)r * N;
     uint64_t *hx = jd.halo + (size_t)ladder * 8u * (uint32_t)g.hp;   // [part][class][side][hp]
@@ -1951,6 +2002,10 @@ __global__ void __launch_bounds__(kMaxBlock) slab_kernel(const JobDesc *__restri
         sm.thr[idx] = slot < n_T ? sm.fthr[sm.perm[slot] * kThrCols + (idx % kThrCols)] : 0u;
     }
     __syncthreads();
+    if (RNG == 1) {
+        build_ptab(sm, 1, wave, nwaves, lane);
+        __syncthreads();
+    }
     const uint32_t *stab = n_swap_lds ? sm.stab : jd.swap_thr;
 
     uint32_t t = __builtin_amdgcn_readfirstlane(*jd.sweep_ctr);
@@ -1982,12 +2037,20 @@ __global__ void __launch_bounds__(kMaxBlock) slab_kernel(const JobDesc *__restri
                 const uint64_t *theirs = hx + (size_t)((other * 2 + 1 - c) * 2) * g.hp;
                 const uint32_t want = c == 0 ? ts : ts + 1u;   // the partner's last class-(1 - c) update
                 if (c == 1 && swap_now && s == chunk - 1) {
-                    slab_class<true>(sm, g, c, tid, nthr, NL, n_T, ts, r, c3flip, k0, k1, segw, mine, theirs, want,
-                                     poll, jd.error, P, np_b);
+                    if constexpr (RNG == 1)
+                        slab_class_planes<true>(sm, g, c, tid, nthr, NL, n_T, ts, r, c3flip, k0, k1, mine, theirs,
+                                                want, poll, jd.error, P, np_b);
+                    else
+                        slab_class<true>(sm, g, c, tid, nthr, NL, n_T, ts, r, c3flip, k0, k1, segw, mine, theirs, want,
+                                         poll, jd.error, P, np_b);
                     reduce_planes8_add<1>(P[0], np_b, n_T, sm.U, 0);
                 } else {
-                    slab_class<false>(sm, g, c, tid, nthr, NL, n_T, ts, r, c3flip, k0, k1, segw, mine, theirs, want,
-                                      poll, jd.error, nullptr, 0);
+                    if constexpr (RNG == 1)
+                        slab_class_planes<false>(sm, g, c, tid, nthr, NL, n_T, ts, r, c3flip, k0, k1, mine, theirs,
+                                                 want, poll, jd.error, nullptr, 0);
+                    else
+                        slab_class<false>(sm, g, c, tid, nthr, NL, n_T, ts, r, c3flip, k0, k1, segw, mine, theirs, want,
+                                          poll, jd.error, nullptr, 0);
                 }
                 poll = true;
                 __syncthreads();
@@ -2008,7 +2071,7 @@ __global__ void __launch_bounds__(kMaxBlock) slab_kernel(const JobDesc *__restri
             // sweep takes its halo word, draws its blocks and forms its segment
             // words (none of which depends on the temperatures); after the swap
             // pass only its decisions remain.
-            const bool ahead = next && tid < g.hc;
+            const bool ahead = RNG == 0 && next && tid < g.hc;   // plane draws: no draw-ahead
             const SlabEdge e0 = slab_edge(g, tid);
             CamscPrep prep;
             int i0 = 0;
@@ -2026,7 +2089,11 @@ __global__ void __launch_bounds__(kMaxBlock) slab_kernel(const JobDesc *__restri
                 sm.draw[lane] = philox10((uint32_t)lane, tswap, r, c3swap, k0, k1).x;
             __syncthreads();   // slot energies U and swap draws are in
             swap_pass_words(sm, stab, n_T, wave, nwaves, lane);
-            if (next) {
+            if (RNG == 1) {
+                build_ptab(sm, 1, wave, nwaves, lane);
+                __syncthreads();
+            }
+            if (RNG == 0 && next) {
                 // class 0 of the next sweep: the first sites only decide
                 uint64_t *mine = hx + (size_t)(part * 4) * g.hp;
                 if (ahead) {
@@ -2195,7 +2262,7 @@ __global__ void __launch_bounds__(512) observables_kernel(const JobDesc *__restr
     for (int c = 0; c < 2; ++c)
         for (int w = 0; w < NW; ++w)
         {
-            count_unsat_word<LAYOUT>(Order{0, N >> 1}, jd.spins + ((size_t)(2 * r + c) * NW + w) * N, j6, N, jd.L,
+            count_unsat_word<LAYOUT>(Order{0, N >> 1, 0}, jd.spins + ((size_t)(2 * r + c) * NW + w) * N, j6, N, jd.L,
                                      jd.invH, jd.invL, w * SPW, n_T, np, s_U[c]);   // HBM holds the natural order
             if (magnet) count_up_word<LAYOUT>(jd.spins + ((size_t)(2 * r + c) * NW + w) * N, N, w * SPW, n_T, np, s_up[c]);
         }
@@ -2295,7 +2362,9 @@ hipError_t launch_init_spins(const JobDesc *d_job, const JobDesc &h, int layout,
 // ladders split by lattice halves (two parts).
 static const void *sweep_fn(int kv, int parts, bool listed = false, int sep = 0)
 {
-    if (kv == kSlabVariant) return listed ? (const void *)slab_kernel<true> : (const void *)slab_kernel<false>;
+    if (kv == kSlabVariant) return listed ? (const void *)slab_kernel<true, 0> : (const void *)slab_kernel<false, 0>;
+    if (kv == kSlabPlanesVariant)
+        return listed ? (const void *)slab_kernel<true, 1> : (const void *)slab_kernel<false, 1>;
     if (kv == 1) return (const void *)sweep_kernel<1, 1, 0>;
     if (kv == 3) return (const void *)sweep_kernel<2, 1, 0>;
     if (kv == 4) return (const void *)sweep_kernel<3, 1, 0>;
@@ -2321,7 +2390,7 @@ static const void *sweep_fn(int kv, int parts, bool listed = false, int sep = 0)
 hipError_t sweep_set_lds(int kv, int parts, size_t lds)
 {
     // the attribute is process-wide per kernel; raise it only when a launch needs more
-    static std::atomic<size_t> set_max[kSlabVariant + 1][3] = {};
+    static std::atomic<size_t> set_max[kSlabPlanesVariant + 1][3] = {};
     const int pi = parts == 4 ? 2 : (parts == 2 ? 1 : 0);
     std::atomic<size_t> &cur = set_max[kv][pi];
     if (lds <= cur.load()) return hipSuccess;

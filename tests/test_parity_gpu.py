@@ -244,22 +244,27 @@ def test_split_launch_shapes(oracle_lib, L, R, n_T, swap_every, bt, rids):
     assert info["split_parts"] > 1 and info["block_threads"] == bt and not info["split_by_halves"]
 
 
-@pytest.mark.parametrize("L,R,n_T,swap_every,bt,rids", [
-    (4, 1, 8, 1, 0, None),             # two planes per half: every site is on a boundary plane
-    (16, 2, 24, 1, 1024, None),        # one site of a class per thread
-    (20, 1, 20, 3, 256, None),         # five slot groups (no even split by groups), eight sites per thread
-    (6, 3, 24, 0, 64, None),           # three planes per half, no PT, two sites per thread
-    (8, 1, 1, 1, 0, None),             # one temperature: no swap pass
-    (16, 40, 32, 1, 0, [0, 17, 39]),   # the benchmark's shape with fewer realizations
+@pytest.mark.parametrize("L,R,n_T,swap_every,bt,rids,rng", [
+    (4, 1, 8, 1, 0, None, "words"),             # two planes per half: every site is on a boundary plane
+    (16, 2, 24, 1, 1024, None, "words"),        # one site of a class per thread
+    (20, 1, 20, 3, 256, None, "words"),         # five slot groups (no even split by groups), eight sites per thread
+    (6, 3, 24, 0, 64, None, "words"),           # three planes per half, no PT, two sites per thread
+    (8, 1, 1, 1, 0, None, "words"),             # one temperature: no swap pass
+    (16, 40, 32, 1, 0, [0, 17, 39], "words"),   # the benchmark's shape with fewer realizations
+    (4, 1, 8, 1, 0, None, "planes"),            # plane draws: every site on a boundary plane
+    (16, 2, 24, 1, 1024, None, "planes"),       # plane draws, one site of a class per thread
+    (20, 1, 20, 3, 256, None, "planes"),        # plane draws, a ragged last half, eight sites per thread
+    (6, 3, 24, 0, 64, None, "planes"),          # plane draws, no PT
+    (16, 40, 32, 1, 0, [0, 17, 39], "planes"),  # plane draws at the benchmark's shape
 ])
-def test_split_by_halves_equals_oracle(oracle_lib, L, R, n_T, swap_every, bt, rids):
+def test_split_by_halves_equals_oracle(oracle_lib, L, R, n_T, swap_every, bt, rids, rng):
     """Ladders split by lattice halves along z: each part owns half the planes
     with every slot and trades its first and last plane with the partner after
     every colour class, and the two halves' energy sums are added at swap
-    points.  The oracle's chain, with calls ending right after a swap point and
-    mid-interval."""
+    points.  The oracle's chain (either draw stream), with calls ending right
+    after a swap point and mid-interval."""
     sim, *_ = run_pair(oracle_lib, L, R, n_T, 9100 + 7 * L + n_T, 23, swap_every, split="always", block_threads=bt,
-                       rids=rids, splits=[1, 9, 13])
+                       rids=rids, splits=[1, 9, 13], rng=rng)
     info = sim.info()
     print(f"[parity] split by halves {info}", flush=True)
     assert info["split_parts"] == 2 and info["split_by_halves"]
