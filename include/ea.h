@@ -155,9 +155,10 @@ int ea_create(int L, const int8_t *couplings, const double *betas, int n_T,
  * PT off.  Asynchronous on the handle's stream when one was given, otherwise
  * synchronous.  EA_ESTATE if the total sweep count would reach 2^32.
  * A split job (ea_sim_info: split_parts > 1) runs 2 or 4 workgroups per
- * ladder that wait for each other at swap points with a bounded wait (the
- * launch needs only that many of its workgroups resident at once to make
- * progress); should a wait ever time out (for instance when other work holds
+ * ladder that wait for each other with a bounded wait, at swap points and,
+ * split by lattice halves (ea_sim_split), for boundary words in every colour
+ * class (the launch needs only that many of its workgroups resident at once
+ * to make progress); should a wait ever time out (for instance when other work holds
  * the device for about a second), this call (or the next ea_observables /
  * ea_state on an asynchronous stream) returns EA_EDEVICE and the state is
  * invalid until ea_set_state. */
@@ -297,6 +298,9 @@ void ea_server_destroy(ea_server *sv);
 
 /* Device bytes ea_create allocates for such a job without a field (a field
  * lengthens the swap tables; ea_sim_footprint reports a live job exactly).
+ * Includes the boundary exchange of a split by lattice halves for CAMSC jobs
+ * of one word per site, even L >= 4 and two workgroups per ladder within the
+ * current device's compute units (256 when no device can be queried).
  * Host-only computation. */
 int ea_job_footprint(int L, const double *betas, int n_T, int n_realizations, int layout, size_t *bytes);
 /* Device bytes a live job holds. */
