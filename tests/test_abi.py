@@ -102,6 +102,7 @@ def test_null_arguments(lib):
     assert lib.ea_state(None, None, None, None) == B.EA_EINVAL
     assert lib.ea_set_state(None, None, None, 0) == B.EA_EINVAL
     assert lib.ea_swap_acceptance(None, None) == B.EA_EINVAL
+    assert lib.ea_sim_split(None, None, None) == B.EA_EINVAL
     lib.ea_destroy(None)
     assert lib.ea_flip_thresholds(None, 3, None) == B.EA_EINVAL
 

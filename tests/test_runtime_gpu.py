@@ -23,9 +23,9 @@ JOBS = [  # L, R, n_T, seed, swap_every
 ]
 
 
-def _make(L, R, n_T, seed, layout="camsc", words_resident=0, split=True):
+def _make(L, R, n_T, seed, layout="camsc", words_resident=0, split=True, rng="words"):
     return B.Sim(L, inputs.couplings(L, R, seed), inputs.geometric_betas(n_T, 0.4, 2.0), seed, layout=layout,
-                 words_resident=words_resident, split=split)
+                 words_resident=words_resident, split=split, rng=rng)
 
 
 @pytest.mark.parametrize("use_graph,autotune", [(True, True), (False, False), (True, False)])
@@ -89,8 +89,9 @@ def _trace(n, seed=9):
     return out
 
 
-@pytest.mark.parametrize("autotune,split", [(False, True), (True, True), (False, "slots")])
-def test_split_plan_and_batch_equal_alone(oracle_lib, autotune, split):
+@pytest.mark.parametrize("autotune,split,rng", [(False, True, "words"), (True, True, "words"), (False, "slots", "words"),
+                                                (False, True, "planes")])
+def test_split_plan_and_batch_equal_alone(oracle_lib, autotune, split, rng):
     """Jobs that together hold fewer ladders than the device has compute
     units run with split ladders (by lattice halves, or by slot groups when
     asked) in a graph-captured plan and in a batch; every replay equals the
@@ -99,9 +100,9 @@ def test_split_plan_and_batch_equal_alone(oracle_lib, autotune, split):
     jobs = [(16, 8, 32, 61, 1), (12, 6, 16, 62, 3), (16, 4, 24, 63, 0)]   # L, R, n_T, seed, swap_every
     if split == "slots":   # slot groups need a count every part divides
         jobs = [(16, 8, 32, 61, 1), (12, 6, 16, 62, 3), (16, 4, 32, 63, 0)]
-    sims = [_make(L, R, n_T, seed, split=split) for L, R, n_T, seed, _ in jobs]
-    bats = [_make(L, R, n_T, seed, split=split) for L, R, n_T, seed, _ in jobs]
-    refs = [B.Sim(L, inputs.couplings(L, R, seed), inputs.geometric_betas(n_T, 0.4, 2.0), seed, split=False)
+    sims = [_make(L, R, n_T, seed, split=split, rng=rng) for L, R, n_T, seed, _ in jobs]
+    bats = [_make(L, R, n_T, seed, split=split, rng=rng) for L, R, n_T, seed, _ in jobs]
+    refs = [B.Sim(L, inputs.couplings(L, R, seed), inputs.geometric_betas(n_T, 0.4, 2.0), seed, split=False, rng=rng)
             for L, R, n_T, seed, _ in jobs]
     se = [j[4] for j in jobs]
     plan = B.Plan(sims, 6, se, autotune=autotune)
@@ -125,7 +126,7 @@ def test_split_plan_and_batch_equal_alone(oracle_lib, autotune, split):
     for (L, R, n_T, seed, swe), sim in zip(jobs, sims):
         r = R - 1
         o = oracle_lib.OracleSim(L, inputs.couplings(L, R, seed)[[r]], inputs.geometric_betas(n_T, 0.4, 2.0), seed,
-                                 rid=np.array([r]))
+                                 rid=np.array([r]), rng=rng)
         o.sweep(18, swe)
         s, perm, t = sim.state()
         assert np.array_equal(s[r], o.spins[0]) and np.array_equal(perm[r], o.temp_of_slot[0])
