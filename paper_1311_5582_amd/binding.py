@@ -207,7 +207,17 @@ def _torch_gpu():
 
 
 class Sim:
-    """One job: R realizations x 2 copies x n_T temperature slots on the GPU."""
+    """One job: R realizations x 2 copies x n_T temperature slots on the GPU.
+
+    layout: "camsc" (default), "amsc4", "amsc3", "amsc1"; rng: "words" or
+    "planes"; split: True/"auto" (the library's choice), False/"never",
+    "always" (whenever the job allows: by lattice halves for two parts, else
+    by slot groups), "slots" (whenever possible, by slot groups only);
+    site_order: "natural" or "by_class"; h: the external field (a multiple
+    of 1/4); allocator: an object with ctypes callbacks alloc_cb / free_cb
+    (default torch's caching allocator when torch sees a GPU).  info()
+    reports the launch: block_threads, words_resident, split_parts,
+    lds_bytes, split_by_halves."""
 
     def __init__(self, L, couplings, betas, seed, layout="camsc", block_threads=0, words_resident=0,
                  stream=None, torch_memory=True, split=True, rng="words", h=0.0, site_order="natural",
