@@ -360,20 +360,20 @@ def bench_batched(B, inputs, torch, sweeps, steps):
             "units": info["units"], "uses_graph": info["uses_graph"]}
 
 
-def bench_serving(B, inputs, n_jobs, rate, quantum, sweep_scale=1.0, policy="ratio", fill=0):
+def bench_serving(B, inputs, n_jobs, rate, quantum, sweep_scale=1.0, policy="ratio", fill=0, pack=True):
     """Poisson job trace through the continuous-batching server."""
     from paper_1311_5582_amd import serve
     trace = inputs.serving_trace(n_jobs=n_jobs, rate_per_s=rate)
     for j in trace:
         j["sweeps"] = max(1, int(j["sweeps"] * sweep_scale))
-    srv = B.Server(quantum_sweeps=quantum, policy=policy, fill_ladders=fill)
+    srv = B.Server(quantum_sweeps=quantum, policy=policy, fill_ladders=fill, pack_rounds=pack)
     recs, wall = serve.run_trace(trace, srv)
     st = srv.stats()
     srv.close()
     summ = serve.latency_summary(recs)
     busy = summ["done_last_s"] - trace[0]["arrival_s"]
     return {"jobs": n_jobs, "rate_per_s": round(rate, 3), "quantum_sweeps": quantum, "sweep_scale": sweep_scale,
-            "policy": policy, "fill_ladders": fill, "p50_latency_s": round(summ["p50_s"], 4), "p99_latency_s": round(summ["p99_s"], 4),
+            "policy": policy, "fill_ladders": fill, "pack_rounds": pack, "p50_latency_s": round(summ["p50_s"], 4), "p99_latency_s": round(summ["p99_s"], 4),
             "mean_latency_s": round(summ["mean_s"], 4), "wall_s": round(wall, 3),
             "aggregate_ps_per_flip": round(busy / summ["flips"] * 1e12, 4), "steps": st["steps"],
             "plans_built": st["plans_built"], "launches_replayed": st["launches_replayed"], "worst": summ["worst"]}
@@ -452,8 +452,11 @@ def main():
                          "--serving-rate2 for each, with --serving-policy, and print their lines")
     ap.add_argument("--serving-policy", default="ratio", choices=["ratio", "shortest", "fifo"])
     ap.add_argument("--serving-rate2", type=float, default=1.526)
+    ap.add_argument("--serving-no-pack", action="store_true",
+                    help="fill sweep: every unit of a step equally long (no packing of the last round)")
     ap.add_argument("--serving-policies", action="store_true",
-                    help="also run the trace with every waiting job admitted at once (first fit, arrival order)")
+                    help="also run the trace with every waiting job admitted at once (first fit, arrival order), "
+                         "shortest remaining work first, and without packing of a step's last round")
     ap.add_argument("--serving-quantum", type=int, default=200)
     ap.add_argument("--serving-scale", type=float, default=1.0,
                     help="multiply every job's sweep count (1.0 = the lognormal trace as drawn)")
@@ -479,7 +482,7 @@ def main():
         for fill in [int(x) for x in args.serving_fill_sweep.split(",")]:
             for rate in (20.0, args.serving_rate2):
                 r = bench_serving(B, inputs, args.serving_jobs, rate, args.serving_quantum, args.serving_scale,
-                                  policy=args.serving_policy, fill=fill)
+                                  policy=args.serving_policy, fill=fill, pack=not args.serving_no_pack)
                 res[f"fill{fill}_rate{rate}"] = r
                 progress(f"fill {fill} rate {rate}: p50 {r['p50_latency_s']} p99 {r['p99_latency_s']} "
                          f"{r['aggregate_ps_per_flip']} ps/flip")
@@ -605,6 +608,8 @@ def main():
                                                   args.serving_scale, policy="fifo"))
             leg("serving_shortest", bench_serving(B, inputs, args.serving_jobs, 20.0, args.serving_quantum,
                                                   args.serving_scale, policy="shortest"))
+            leg("serving_unpacked", bench_serving(B, inputs, args.serving_jobs, 20.0, args.serving_quantum,
+                                                  args.serving_scale, pack=False))
         # the same trace shape at 0.8 x the measured service capacity (jobs/s), served and plain
         cap = out["serving"]["jobs"] / max(out["serving"]["wall_s"], 1e-9)
         leg("serving_at_0.8_capacity", bench_serving(B, inputs, args.serving_jobs, 0.8 * cap, args.serving_quantum,
@@ -615,6 +620,9 @@ def main():
             leg("serving_shortest_at_0.8_capacity", bench_serving(B, inputs, args.serving_jobs, 0.8 * cap,
                                                                   args.serving_quantum, args.serving_scale,
                                                                   policy="shortest"))
+            leg("serving_unpacked_at_0.8_capacity", bench_serving(B, inputs, args.serving_jobs, 0.8 * cap,
+                                                                  args.serving_quantum, args.serving_scale,
+                                                                  pack=False))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(L, n_T, cfg["t_min"], cfg["t_max"], cfg["seed"], args.cpu_sweeps,
                                            usable_cores(), args.cpu_single_sweeps)

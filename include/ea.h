@@ -249,8 +249,12 @@ void ea_plan_destroy(ea_plan *plan);
  * step the running job with the most work per ladder and sweep (L^3 x n_T)
  * runs quantum sweeps and every other job round(quantum x that work / its
  * own) sweeps, so that all ladders of the step take about equally long (at
- * most the sweeps it has left); a graph-captured plan is replayed while the
- * job set and sweep counts are unchanged.  A job's results are the
+ * most the sweeps it has left).  With more ladders than compute units the
+ * launch takes ceil(ladders / CUs) rounds of such units, the last one partly
+ * idle; with pack_rounds the jobs of lowest response ratio (never all) then
+ * run shorter units, at least a quarter of the others', sized to fill the
+ * idle slots of floor(ladders / CUs) rounds.  A graph-captured plan is
+ * replayed while the job set and sweep counts are unchanged.  A job's results are the
  * same alone and in any mix. */
 #define EA_ADMIT_FIFO           0
 #define EA_ADMIT_SHORTEST       1
@@ -274,6 +278,9 @@ typedef struct ea_server_options {
     int policy;               /* EA_ADMIT_RESPONSE_RATIO (default), _SHORTEST or _FIFO            */
     int fill_ladders;         /* SHORTEST, RESPONSE_RATIO: stop admitting once the running jobs hold this
                                  many ladders (2 x realizations); 0 = 4 x the compute units      */
+    int pack_rounds;          /* 1 (default): when a step's ladders overfill their last round of
+                                 compute units, the least urgent jobs run shorter units in that
+                                 round's idle slots; 0: every unit of a step about equally long  */
     void *stream;             /* hipStream_t of the steps; NULL = a stream owned by the server    */
 } ea_server_options;
 

@@ -50,7 +50,7 @@ class ServerOptions(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("quantum_sweeps", ctypes.c_int), ("layout", ctypes.c_int),
                 ("max_active", ctypes.c_int), ("autotune", ctypes.c_int), ("keep_state", ctypes.c_int),
                 ("rng", ctypes.c_int), ("policy", ctypes.c_int), ("fill_ladders", ctypes.c_int),
-                ("stream", ctypes.c_void_p)]
+                ("pack_rounds", ctypes.c_int), ("stream", ctypes.c_void_p)]
 
 
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_CANCELLED, JOB_FAILED = 0, 1, 2, 3, 4
@@ -419,7 +419,7 @@ class Server:
     """Continuous-batching job server (see ea_server_* in include/ea.h)."""
 
     def __init__(self, hbm_budget_bytes=0, quantum_sweeps=200, layout="camsc", max_active=0, autotune=False,
-                 keep_state=False, rng="words", policy="ratio", fill_ladders=0):
+                 keep_state=False, rng="words", policy="ratio", fill_ladders=0, pack_rounds=True):
         opt = ServerOptions()
         lib().ea_default_server_options(ctypes.byref(opt))
         opt.hbm_budget_bytes = int(hbm_budget_bytes)
@@ -431,6 +431,7 @@ class Server:
         opt.rng = RNGS[rng] if isinstance(rng, str) else int(rng)
         opt.policy = {"fifo": 0, "shortest": 1, "ratio": 2}[policy] if isinstance(policy, str) else int(policy)
         opt.fill_ladders = int(fill_ladders)
+        opt.pack_rounds = int(bool(pack_rounds))
         self._h = ctypes.c_void_p()
         self.shapes = {}
         check(lib().ea_server_create(ctypes.byref(opt), ctypes.byref(self._h)))

@@ -8,8 +8,10 @@
 // finished jobs (energies and overlaps measured, device state released, which
 // admits the next jobs), and (3) launches the next step over every running
 // job, each for about as much work per ladder as `quantum` sweeps of the job
-// with the most work per sweep (capped by the sweeps it has left), replaying a
-// graph-captured plan while the job set and sweep counts are unchanged.
+// with the most work per sweep (capped by the sweeps it has left; with more
+// ladders than compute units the least urgent jobs get shorter units that fill
+// the last round's idle slots, ea_sched.h), replaying a graph-captured plan
+// while the job set and sweep counts are unchanged.
 // Results are a pure function of each job's inputs (counter-based stream,
 // device-resident sweep counters), so a job's result is the same alone and in
 // any mix.
@@ -23,6 +25,7 @@
 
 #include "ea.h"
 #include "ea_host.h"
+#include "ea_sched.h"
 
 using namespace ea;
 
@@ -53,6 +56,7 @@ struct ea_server {
     ea_server_options opt{};
     int device = 0;
     int fill_ladders = 0;             // shortest-first admission stops once the running jobs hold this many
+    int cus = 0;                      // compute units of the device
     hipStream_t stream = nullptr;     // steps
     hipStream_t admit = nullptr;      // job creation, measurement and readout
     size_t used = 0;
@@ -110,8 +114,8 @@ static int64_t remaining_work(const Job *j)
     return (j->n_sweeps - j->done) * (int64_t)j->L * j->L * j->L * j->n_T * j->R;
 }
 
-// Response ratio of a waiting job: (time waited + its estimated service time)
-// / its estimated service time, the service time from the measured rate.
+// Response ratio of a job: (time since it arrived + its estimated remaining
+// service time) / that estimate, the service time from the measured rate.
 static double response_ratio(const ea_server *sv, const Job *j, double now)
 {
     const double est = std::max(1e-6, (double)remaining_work(j) * 2.0 * sv->s_per_flip);
@@ -139,6 +143,7 @@ void ea_default_server_options(ea_server_options *opt)
     opt->autotune = 0;   // the job mix changes at every arrival; tuning each mix would cost more than it saves
     opt->policy = EA_ADMIT_RESPONSE_RATIO;
     opt->fill_ladders = 0;
+    opt->pack_rounds = 1;
 }
 
 int ea_server_create(const ea_server_options *opt_in, ea_server **out)
@@ -169,6 +174,7 @@ int ea_server_create(const ea_server_options *opt_in, ea_server **out)
     int cus = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, sv->device);
     sv->fill_ladders = opt.fill_ladders > 0 ? opt.fill_ladders : 4 * cus;
+    sv->cus = cus;
     if (e == hipSuccess && opt.stream == nullptr) e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&sv->admit, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&sv->ev0);
@@ -296,23 +302,21 @@ int ea_server_step(ea_server *sv, int *n_running, int *n_queued, int *n_finished
         // (sites x temperatures): the job with the most work per sweep runs
         // `quantum` sweeps, and every ladder of the step takes about as long,
         // so a job with cheap sweeps is not held to the pace of an expensive
-        // one and the launch's units are of one size.
-        double w_max = 0.0;
-        for (int64_t id : sv->active) {
-            const Job *j = sv->jobs[id].get();
-            w_max = std::max(w_max, (double)j->L * j->L * j->L * j->n_T);
-        }
-        std::vector<int> q;
+        // one and the launch's units are of one size; with packing, the least
+        // urgent jobs fill the last round's idle slots with shorter units.
+        const double now = now_s();
+        std::vector<StepJob> sj;
         std::vector<ea_sim *> sims;
         std::vector<int> se;
         for (int64_t id : sv->active) {
             const Job *j = sv->jobs[id].get();
-            const double w = (double)j->L * j->L * j->L * j->n_T;
-            const double want = std::min((double)kMaxStepSweeps, std::round(sv->opt.quantum_sweeps * w_max / w));
-            q.push_back((int)std::min<int64_t>((int64_t)std::max(1.0, want), j->n_sweeps - j->done));
+            sj.push_back({2 * (int64_t)j->R, (double)j->L * j->L * j->L * j->n_T, j->n_sweeps - j->done,
+                          response_ratio(sv, j, now)});
             sims.push_back(j->sim);
             se.push_back(j->swap_every);
         }
+        const std::vector<int> q =
+            step_sweeps(sj, sv->opt.quantum_sweeps, sv->cus, sv->opt.pack_rounds != 0, kMaxStepSweeps);
         if (sv->plan == nullptr || sv->plan_ids != sv->active || sv->plan_sweeps != q) {
             drop_plan(sv);
             ea_plan_options po;
