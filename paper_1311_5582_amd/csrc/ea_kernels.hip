@@ -451,12 +451,12 @@ __device__ __forceinline__ void update_site_planes(const Smem &sm, PlaneQueue &q
         if (live) {
             uint32_t *sw = sm.spin + (size_t)w * N;
             const uint32_t S = sw[nb.i];
-            const uint32_t e0 = S ^ sw[nb.xp] ^ (0u - (j6 & 1u));
-            const uint32_t e1 = S ^ sw[nb.xm] ^ (0u - ((j6 >> 1) & 1u));
-            const uint32_t e2 = S ^ sw[nb.yp] ^ (0u - ((j6 >> 2) & 1u));
-            const uint32_t e3 = S ^ sw[nb.ym] ^ (0u - ((j6 >> 3) & 1u));
-            const uint32_t e4 = S ^ sw[nb.zp] ^ (0u - ((j6 >> 4) & 1u));
-            const uint32_t e5 = S ^ sw[nb.zm] ^ (0u - ((j6 >> 5) & 1u));
+            const uint32_t e0 = xor3(S, sw[nb.xp], (0u - (j6 & 1u)));
+            const uint32_t e1 = xor3(S, sw[nb.xm], (0u - ((j6 >> 1) & 1u)));
+            const uint32_t e2 = xor3(S, sw[nb.yp], (0u - ((j6 >> 2) & 1u)));
+            const uint32_t e3 = xor3(S, sw[nb.ym], (0u - ((j6 >> 3) & 1u)));
+            const uint32_t e4 = xor3(S, sw[nb.zp], (0u - ((j6 >> 4) & 1u)));
+            const uint32_t e5 = xor3(S, sw[nb.zm], (0u - ((j6 >> 5) & 1u)));
             const uint32_t s1 = xor3(e0, e1, e2), c1 = maj3(e0, e1, e2);
             const uint32_t s2 = xor3(e3, e4, e5), c2 = maj3(e3, e4, e5);
             const uint32_t E0 = s1 ^ s2, kk = s1 & s2;
@@ -700,12 +700,12 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
     for (int w = 0; w < gw; ++w) {
         uint32_t *sw = sm.spin + (size_t)w * N;
         const uint32_t S = sw[nb.i];
-        const uint32_t e0 = S ^ sw[nb.xp] ^ m[0];
-        const uint32_t e1 = S ^ sw[nb.xm] ^ m[1];
-        const uint32_t e2 = S ^ sw[nb.yp] ^ m[2];
-        const uint32_t e3 = S ^ sw[nb.ym] ^ m[3];
-        const uint32_t e4 = S ^ sw[nb.zp] ^ m[4];
-        const uint32_t e5 = S ^ sw[nb.zm] ^ m[5];
+        const uint32_t e0 = xor3(S, sw[nb.xp], m[0]);
+        const uint32_t e1 = xor3(S, sw[nb.xm], m[1]);
+        const uint32_t e2 = xor3(S, sw[nb.yp], m[2]);
+        const uint32_t e3 = xor3(S, sw[nb.ym], m[3]);
+        const uint32_t e4 = xor3(S, sw[nb.zp], m[4]);
+        const uint32_t e5 = xor3(S, sw[nb.zm], m[5]);
         const int wg = __builtin_amdgcn_readfirstlane(g0 + w);
         if (LAYOUT == 0) {
             static_assert(RNG == 0, "plane draws update sites through class_pass_planes");
@@ -969,7 +969,7 @@ __device__ __forceinline__ void update_pair_camsc(const Smem &sm, const Nbrs &na
     for (int q = 0; q < 2; ++q) {
         uint32_t e[6];
 #pragma unroll
-        for (int d = 0; d < 6; ++d) e[d] = S[q] ^ V[q][d] ^ (0u - ((J[q] >> d) & 1u));
+        for (int d = 0; d < 6; ++d) e[d] = xor3(S[q], V[q][d], 0u - ((J[q] >> d) & 1u));
         const uint32_t s1 = xor3(e[0], e[1], e[2]), c1 = maj3(e[0], e[1], e[2]);
         const uint32_t s2 = xor3(e[3], e[4], e[5]), c2 = maj3(e[3], e[4], e[5]);
         const uint32_t E0 = s1 ^ s2, kk = s1 & s2;
@@ -1049,12 +1049,12 @@ __device__ void class_pass_planes(const Smem &sm, int c, int tid, int nthr, int 
             const uint32_t j6 = sm.j6[nb.i];
             const uint32_t *sw = sm.spin;
             const uint32_t S = sw[nb.i];
-            const uint32_t e0 = S ^ sw[nb.xp] ^ (0u - (j6 & 1u));
-            const uint32_t e1 = S ^ sw[nb.xm] ^ (0u - ((j6 >> 1) & 1u));
-            const uint32_t e2 = S ^ sw[nb.yp] ^ (0u - ((j6 >> 2) & 1u));
-            const uint32_t e3 = S ^ sw[nb.ym] ^ (0u - ((j6 >> 3) & 1u));
-            const uint32_t e4 = S ^ sw[nb.zp] ^ (0u - ((j6 >> 4) & 1u));
-            const uint32_t e5 = S ^ sw[nb.zm] ^ (0u - ((j6 >> 5) & 1u));
+            const uint32_t e0 = xor3(S, sw[nb.xp], (0u - (j6 & 1u)));
+            const uint32_t e1 = xor3(S, sw[nb.xm], (0u - ((j6 >> 1) & 1u)));
+            const uint32_t e2 = xor3(S, sw[nb.yp], (0u - ((j6 >> 2) & 1u)));
+            const uint32_t e3 = xor3(S, sw[nb.ym], (0u - ((j6 >> 3) & 1u)));
+            const uint32_t e4 = xor3(S, sw[nb.zp], (0u - ((j6 >> 4) & 1u)));
+            const uint32_t e5 = xor3(S, sw[nb.zm], (0u - ((j6 >> 5) & 1u)));
             const uint32_t s1 = xor3(e0, e1, e2), c1 = maj3(e0, e1, e2);
             const uint32_t s2 = xor3(e3, e4, e5), c2 = maj3(e3, e4, e5);
             const uint32_t kk = s1 & s2;
@@ -1786,12 +1786,12 @@ __device__ __forceinline__ CamscPrep camsc_prepare(const Smem &sm, const Nbrs &n
     const uint32_t *sw = sm.spin;
     CamscPrep p;
     p.S = sw[nb.i];
-    const uint32_t e0 = p.S ^ sw[nb.xp] ^ (0u - (j6 & 1u));
-    const uint32_t e1 = p.S ^ sw[nb.xm] ^ (0u - ((j6 >> 1) & 1u));
-    const uint32_t e2 = p.S ^ sw[nb.yp] ^ (0u - ((j6 >> 2) & 1u));
-    const uint32_t e3 = p.S ^ sw[nb.ym] ^ (0u - ((j6 >> 3) & 1u));
-    const uint32_t e4 = p.S ^ sw[nb.zp] ^ (0u - ((j6 >> 4) & 1u));
-    const uint32_t e5 = p.S ^ sw[nb.zm] ^ (0u - ((j6 >> 5) & 1u));
+    const uint32_t e0 = xor3(p.S, sw[nb.xp], (0u - (j6 & 1u)));
+    const uint32_t e1 = xor3(p.S, sw[nb.xm], (0u - ((j6 >> 1) & 1u)));
+    const uint32_t e2 = xor3(p.S, sw[nb.yp], (0u - ((j6 >> 2) & 1u)));
+    const uint32_t e3 = xor3(p.S, sw[nb.ym], (0u - ((j6 >> 3) & 1u)));
+    const uint32_t e4 = xor3(p.S, sw[nb.zp], (0u - ((j6 >> 4) & 1u)));
+    const uint32_t e5 = xor3(p.S, sw[nb.zm], (0u - ((j6 >> 5) & 1u)));
     const uint32_t s1 = xor3(e0, e1, e2), c1 = maj3(e0, e1, e2);
     const uint32_t s2 = xor3(e3, e4, e5), c2 = maj3(e3, e4, e5);
     const uint32_t E0 = s1 ^ s2, kk = s1 & s2;
@@ -1912,12 +1912,12 @@ __device__ void slab_class_planes(const Smem &sm, const Slab &g, int c, int tid,
             __hip_atomic_store(&mine[e.first ? e.k : g.hp + e.k], tag | S, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (ACC) {
             const uint32_t j6 = sm.j6[nb.i];
-            const uint32_t e0 = S ^ sw[nb.xp] ^ (0u - (j6 & 1u));
-            const uint32_t e1 = S ^ sw[nb.xm] ^ (0u - ((j6 >> 1) & 1u));
-            const uint32_t e2 = S ^ sw[nb.yp] ^ (0u - ((j6 >> 2) & 1u));
-            const uint32_t e3 = S ^ sw[nb.ym] ^ (0u - ((j6 >> 3) & 1u));
-            const uint32_t e4 = S ^ sw[nb.zp] ^ (0u - ((j6 >> 4) & 1u));
-            const uint32_t e5 = S ^ sw[nb.zm] ^ (0u - ((j6 >> 5) & 1u));
+            const uint32_t e0 = xor3(S, sw[nb.xp], (0u - (j6 & 1u)));
+            const uint32_t e1 = xor3(S, sw[nb.xm], (0u - ((j6 >> 1) & 1u)));
+            const uint32_t e2 = xor3(S, sw[nb.yp], (0u - ((j6 >> 2) & 1u)));
+            const uint32_t e3 = xor3(S, sw[nb.ym], (0u - ((j6 >> 3) & 1u)));
+            const uint32_t e4 = xor3(S, sw[nb.zp], (0u - ((j6 >> 4) & 1u)));
+            const uint32_t e5 = xor3(S, sw[nb.zm], (0u - ((j6 >> 5) & 1u)));
             const uint32_t s1 = xor3(e0, e1, e2), c1 = maj3(e0, e1, e2);
             const uint32_t s2 = xor3(e3, e4, e5), c2 = maj3(e3, e4, e5);
             const uint32_t kk = s1 & s2;
