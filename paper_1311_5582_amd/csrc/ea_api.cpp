@@ -263,9 +263,14 @@ int build_swap_tables(const double *betas, int n_T, int N, int m, std::vector<ui
         // |2 (E_a - E_b)| = |4 dU - m d(up)| <= 12 N + |m| N
         const int64_t cap = (12 * (int64_t)N + (int64_t)(m < 0 ? -m : m) * N) / g;
         int64_t n = 0;
+        uint32_t prev = 0xFFFFFFFFu;
         for (; n <= cap; ++n) {
             const uint32_t v = swap_thr_g(dabs, n, g);
             if (v == 0) break;
+            // the split by lattice halves turns each pair's test into a cut
+            // on n, which needs thresholds that never increase with n
+            if (v > prev) return fail(EA_EINVAL, "non-monotone swap table for pair %d", k);
+            prev = v;
             if (sthr) sthr->push_back(v);
         }
         // the thresholds decrease with n; check that the zero tail stays zero

@@ -190,7 +190,7 @@ struct Smem {
     int32_t *U;       // unsatisfied bonds per slot
     int32_t *perm;    // temp_of_slot
     int32_t *sot;     // slot_of_temp
-    uint32_t *draw;   // (spare)
+    uint32_t *draw;   // per pair: its swap draw (split by lattice halves: its cut, swap_cut)
     int32_t *soff, *slen, *ssgn;   // swap tables: offset, length, sign of dbeta
     uint32_t *acc;    // accepted swaps per pair in this unit
     uint64_t *mask;   // speculative accept bits per pair
@@ -1168,11 +1168,31 @@ __device__ __forceinline__ void count_up_word(const uint32_t *words, int N, int 
 // ---------------------------------------------------------------------------
 constexpr uint32_t kSpinLimit = 1u << 20;   // polls of a partner's flag before giving up
 
+// A pair with draw dr swaps at energy-difference index n (against the
+// temperatures' order) when n < len and dr < tab[n].  The table does not
+// increase with n (the host checks it), so those n are a prefix of the
+// table: the cut returned is the first n whose threshold is at or below dr
+// (len if there is none), and the test becomes n < cut.
+__device__ __forceinline__ int swap_cut(const uint32_t *tab, int len, uint32_t dr)
+{
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (tab[mid] > dr)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 // The ascending swap pass of one ladder once every slot's value is in U and
-// the pairs' draws are in `draw` (both in LDS): acceptance words over all
-// (start, pair) combinations, then the walk over the rejections in wave 0,
-// which moves the temperature rows to their new slots.  Ends after a
-// barrier; U is consumed (zero again).
+// the pairs' draws are in `draw` (both in LDS; with CUT, `draw` holds each
+// pair's cut instead, see swap_cut): acceptance words over all (start, pair)
+// combinations, then the walk over the rejections in wave 0, which moves the
+// temperature rows to their new slots.  Ends after a barrier; U is consumed
+// (zero again).
+template <bool CUT>
 __device__ __forceinline__ void swap_pass_words(const Smem &sm, const uint32_t *stab, int n_T, int wave, int nwaves,
                                                 int lane)
 {
@@ -1196,9 +1216,15 @@ __device__ __forceinline__ void swap_pass_words(const Smem &sm, const uint32_t *
         for (int j = wave; j < pairs; j += nwaves) {
             const int d = __builtin_amdgcn_readlane(u_here, j) - u_next;
             const int n = d < 0 ? -d : d;
-            const uint32_t thr = len > 0 ? stab[off + min(n, len - 1)] : 0u;
             const bool favourable = (sg == 0) || (d == 0) || ((sg > 0) == (d > 0));
-            const bool acc = live && k >= j && (favourable || (n < len && dr < thr));
+            bool by_draw;
+            if constexpr (CUT) {
+                by_draw = n < (int)dr;
+            } else {
+                const uint32_t thr = len > 0 ? stab[off + min(n, len - 1)] : 0u;
+                by_draw = n < len && dr < thr;
+            }
+            const bool acc = live && k >= j && (favourable || by_draw);
             const uint64_t col = __ballot(acc);
             if (lane == 0) sm.mask[j] = col;
         }
@@ -1658,7 +1684,7 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                     if (wave == nwaves - 1 && lane < pairs)
                         sm.draw[lane] = philox10((uint32_t)lane, tswap, r, c3swap, k0, k1).x;
                     __syncthreads();   // slot energies U and swap draws are in
-                    swap_pass_words(sm, stab, n_T, wave, nwaves, lane);
+                    swap_pass_words<false>(sm, stab, n_T, wave, nwaves, lane);
                     if (RNG == 1) {
                         build_ptab(sm, NW, wave, nwaves, lane);
                         __syncthreads();
@@ -2026,6 +2052,13 @@ __global__ void __launch_bounds__(kMaxBlock) slab_kernel(const JobDesc *__restri
                 swap_now = true;
             }
         }
+        // The pairs' swap draws and cuts (swap_cut) for this chunk's swap
+        // point, off the swap step's path: one wave takes them before its
+        // sites; the class barriers publish them.
+        if (swap_now && n_T > 1 && wave == (nwaves >> 1) && lane < n_T - 1) {
+            const uint32_t dr = philox10((uint32_t)lane, t + (uint32_t)chunk - 1u, r, c3swap, k0, k1).x;
+            sm.draw[lane] = (uint32_t)swap_cut(stab + sm.soff[lane], sm.slen[lane], dr);
+        }
         uint32_t P[1][8];
 #pragma unroll
         for (int p = 0; p < 8; ++p) P[0][p] = 0u;
@@ -2085,10 +2118,8 @@ __global__ void __launch_bounds__(kMaxBlock) slab_kernel(const JobDesc *__restri
                 i0 = nb.i;
             }
             if (tid < n_T) sm.U[tid] += (int32_t)wait_tagged(&xb[other * 32 + tid], tag, jd.error);
-            if (wave == nwaves - 1 && lane < n_T - 1)
-                sm.draw[lane] = philox10((uint32_t)lane, tswap, r, c3swap, k0, k1).x;
-            __syncthreads();   // slot energies U and swap draws are in
-            swap_pass_words(sm, stab, n_T, wave, nwaves, lane);
+            __syncthreads();   // slot energies U are in (the pairs' cuts since the summing class)
+            swap_pass_words<true>(sm, stab, n_T, wave, nwaves, lane);
             if (RNG == 1) {
                 build_ptab(sm, 1, wave, nwaves, lane);
                 __syncthreads();
