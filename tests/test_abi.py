@@ -190,3 +190,28 @@ def test_close_after_library_teardown_is_inert():
         for obj in objs:
             obj._h = ctypes.c_void_p()   # before the library comes back: the finalisers must not see the fake handle
         B._lib = saved
+
+
+def test_swap_tables_never_increase_so_tests_are_cuts():
+    """The split by lattice halves decides a pair's swap as n < cut, with cut
+    the first table index whose threshold is at or below the draw; that equals
+    the table test (n < len and draw < table[n]) only for tables that never
+    increase with n.  Check that property over the ladders' spacings (the host
+    also refuses a table that breaks it), and the cut's equivalence with the
+    table test for random draws."""
+    rng = np.random.default_rng(7)
+    for db in list(rng.uniform(1e-3, 2.0, 30)) + [0.026, 0.13, 1e-3]:
+        tab = []
+        n = 0
+        while True:
+            v = B.swap_threshold(db, n)
+            if v == 0:
+                break
+            tab.append(v)
+            n += 1
+        assert all(a >= b for a, b in zip(tab, tab[1:])), db
+        for dr in list(rng.integers(0, 2 ** 32, 50, dtype=np.uint64)) + [0, 2 ** 32 - 1] + tab[:3]:
+            dr = int(dr)
+            cut = next((i for i, v in enumerate(tab) if v <= dr), len(tab))
+            for m in range(len(tab) + 3):
+                assert (m < cut) == (m < len(tab) and dr < tab[m]), (db, dr, m)
