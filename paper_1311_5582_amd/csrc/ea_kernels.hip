@@ -1186,12 +1186,28 @@ __device__ __forceinline__ int swap_cut(const uint32_t *tab, int len, uint32_t d
     return lo;
 }
 
+// The pairs' swap draws of the swap point after sweep tswap, taken by one
+// wave ahead of the swap step (the class barriers in between publish them):
+// with the tables in LDS each pair's cut (swap_cut), else the draw itself
+// (a search over a table in HBM would hold that wave up for longer than the
+// swap step saves).
+__device__ __forceinline__ void swap_draws_ahead(const Smem &sm, const uint32_t *stab, bool cuts, int n_T,
+                                                 uint32_t tswap, uint32_t r, uint32_t c3swap, uint32_t k0, uint32_t k1,
+                                                 int wave, int nwaves, int lane)
+{
+    if (n_T > 1 && wave == (nwaves >> 1) && lane < n_T - 1) {
+        const uint32_t dr = philox10((uint32_t)lane, tswap, r, c3swap, k0, k1).x;
+        sm.draw[lane] = cuts ? (uint32_t)swap_cut(stab + sm.soff[lane], sm.slen[lane], dr) : dr;
+    }
+}
+
 // The ascending swap pass of one ladder once every slot's value is in U and
 // the pairs' draws are in `draw` (both in LDS; with CUT, `draw` holds each
 // pair's cut instead, see swap_cut): acceptance words over all (start, pair)
 // combinations, then the walk over the rejections in wave 0, which moves the
 // temperature rows to their new slots.  Ends after a barrier; U is consumed
-// (zero again).
+// (zero again).  (CUT is a template argument: a run-time choice inside the
+// pass measured 1.8% slower at PT after every sweep.)
 template <bool CUT>
 __device__ __forceinline__ void swap_pass_words(const Smem &sm, const uint32_t *stab, int n_T, int wave, int nwaves,
                                                 int lane)
@@ -1377,6 +1393,7 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
             __syncthreads();
         }
         const uint32_t *stab = n_swap_lds ? sm.stab : jd.swap_thr;
+        const bool cuts = n_swap_lds > 0;   // swap tests as cuts (swap_cut) when the tables sit in LDS
         const uint32_t *slist = n_sites_lds ? sm.sites : jd.sites;
 
         uint32_t t = __builtin_amdgcn_readfirstlane(*jd.sweep_ctr);
@@ -1405,6 +1422,10 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                     swap_now = true;
                 }
             }
+            // this chunk's swap draws (cuts), off the swap step's path (the
+            // split by slot groups with word draws draws them in its swap step)
+            if (!PREDRAW && swap_now)
+                swap_draws_ahead(sm, stab, cuts, n_T, t + (uint32_t)chunk - 1u, r, c3swap, k0, k1, wave, nwaves, lane);
             uint32_t P[1][8];
 #pragma unroll
             for (int p = 0; p < 8; ++p) P[0][p] = 0u;
@@ -1680,11 +1701,11 @@ __global__ void __launch_bounds__(kMaxBlock) sweep_kernel(const JobDesc *__restr
                             sm.U[tid] = (int32_t)(uint32_t)v;
                         }
                     }
-                    // the last wave draws (wave 0 may still be waiting for partners)
-                    if (wave == nwaves - 1 && lane < pairs)
-                        sm.draw[lane] = philox10((uint32_t)lane, tswap, r, c3swap, k0, k1).x;
-                    __syncthreads();   // slot energies U and swap draws are in
-                    swap_pass_words<false>(sm, stab, n_T, wave, nwaves, lane);
+                    __syncthreads();   // slot energies U are in (the pairs' draws since the chunk began)
+                    if (cuts)
+                        swap_pass_words<true>(sm, stab, n_T, wave, nwaves, lane);
+                    else
+                        swap_pass_words<false>(sm, stab, n_T, wave, nwaves, lane);
                     if (RNG == 1) {
                         build_ptab(sm, NW, wave, nwaves, lane);
                         __syncthreads();
@@ -2033,6 +2054,7 @@ __global__ void __launch_bounds__(kMaxBlock) slab_kernel(const JobDesc *__restri
         __syncthreads();
     }
     const uint32_t *stab = n_swap_lds ? sm.stab : jd.swap_thr;
+    const bool cuts = n_swap_lds > 0;   // swap tests as cuts (swap_cut) when the tables sit in LDS
 
     uint32_t t = __builtin_amdgcn_readfirstlane(*jd.sweep_ctr);
     int remaining = jd.n_sweeps;
@@ -2052,13 +2074,8 @@ __global__ void __launch_bounds__(kMaxBlock) slab_kernel(const JobDesc *__restri
                 swap_now = true;
             }
         }
-        // The pairs' swap draws and cuts (swap_cut) for this chunk's swap
-        // point, off the swap step's path: one wave takes them before its
-        // sites; the class barriers publish them.
-        if (swap_now && n_T > 1 && wave == (nwaves >> 1) && lane < n_T - 1) {
-            const uint32_t dr = philox10((uint32_t)lane, t + (uint32_t)chunk - 1u, r, c3swap, k0, k1).x;
-            sm.draw[lane] = (uint32_t)swap_cut(stab + sm.soff[lane], sm.slen[lane], dr);
-        }
+        // this chunk's swap draws (cuts), off the swap step's path
+        if (swap_now) swap_draws_ahead(sm, stab, cuts, n_T, t + (uint32_t)chunk - 1u, r, c3swap, k0, k1, wave, nwaves, lane);
         uint32_t P[1][8];
 #pragma unroll
         for (int p = 0; p < 8; ++p) P[0][p] = 0u;
@@ -2118,8 +2135,11 @@ __global__ void __launch_bounds__(kMaxBlock) slab_kernel(const JobDesc *__restri
                 i0 = nb.i;
             }
             if (tid < n_T) sm.U[tid] += (int32_t)wait_tagged(&xb[other * 32 + tid], tag, jd.error);
-            __syncthreads();   // slot energies U are in (the pairs' cuts since the summing class)
-            swap_pass_words<true>(sm, stab, n_T, wave, nwaves, lane);
+            __syncthreads();   // slot energies U are in (the pairs' draws since the chunk began)
+            if (cuts)
+                swap_pass_words<true>(sm, stab, n_T, wave, nwaves, lane);
+            else
+                swap_pass_words<false>(sm, stab, n_T, wave, nwaves, lane);
             if (RNG == 1) {
                 build_ptab(sm, 1, wave, nwaves, lane);
                 __syncthreads();
