@@ -30,12 +30,12 @@ def _report(tag, **kw):
 
 def run_pair(oracle_lib, L, R, n_T, seed, sweeps, swap_every, layout="camsc", t_min=0.4, t_max=2.0,
              rids=None, block_threads=0, words_resident=0, couplings=None, splits=None, rng="words", split=True,
-             h=0.0, site_order="natural"):
+             h=0.0, site_order="natural", betas=None):
     """Run the GPU on all R realizations and the oracle on `rids`; compare."""
     _report("run", L=L, R=R, n_T=n_T, seed=seed, sweeps=sweeps, swap_every=swap_every, layout=layout,
             bt=block_threads, wr=words_resident, rng=rng, split=split, h=h)
     J = inputs.couplings(L, R, seed) if couplings is None else couplings
-    betas = inputs.geometric_betas(n_T, t_min, t_max)
+    betas = inputs.geometric_betas(n_T, t_min, t_max) if betas is None else betas
     rids = list(range(R)) if rids is None else list(rids)
     sim = B.Sim(L, J, betas, seed, layout=layout, block_threads=block_threads, words_resident=words_resident,
                 rng=rng, split=split, h=h, site_order=site_order)
@@ -270,6 +270,30 @@ def test_split_by_halves_equals_oracle(oracle_lib, L, R, n_T, swap_every, bt, ri
     assert info["split_parts"] == 2 and info["split_by_halves"]
     if bt:
         assert info["block_threads"] == bt
+
+
+@pytest.mark.parametrize("split,rng", [("always", "words"), ("always", "planes"), (False, "words"), (False, "planes")])
+def test_swap_tables_in_hbm_equal_oracle(oracle_lib, split, rng):
+    """Four pairs of nearly equal temperatures (d beta = 1e-7) give swap tables
+    of 3N + 1 entries each, 4 x 12289 x 4 bytes at L=16: more than LDS holds,
+    so the swap step reads the tables from HBM and the draws made ahead of it
+    stay draws (with the tables in LDS, as in every other test, they become
+    cuts).  Those pairs accept nearly always, the others at their usual rates.
+    Split by lattice halves (either draw stream) and one workgroup per ladder."""
+    L, R, n_T = 16, 2, 24
+    betas = inputs.geometric_betas(n_T, 0.4, 2.0).copy()
+    for k in (3, 9, 15, 21):
+        betas[k + 1] = betas[k] - 1e-7
+    sim, *_ = run_pair(oracle_lib, L, R, n_T, 9400 + (split is False) + 2 * (rng == "planes"), 23, 1, split=split,
+                       rng=rng, betas=betas, splits=[1, 9, 13])
+    info = sim.info()
+    print(f"[parity] swap tables in HBM {info}", flush=True)
+    assert info["split_by_halves"] == (split == "always")
+    acc = sim.swap_acceptance().astype(np.int64)   # [R][copy][pair], 23 swap points each
+    near = [3, 9, 15, 21]
+    other = [k for k in range(n_T - 1) if k not in near]
+    assert acc[:, :, near].min() >= 18, acc[:, :, near]   # nearly always accepted
+    assert acc[:, :, other].sum() < 23 * R * 2 * len(other)   # and the table test rejects elsewhere
 
 
 @pytest.mark.parametrize("L,R,n_T,swap_every,split,bt,wr", [
