@@ -319,17 +319,15 @@ __device__ __forceinline__ void build_ptab(const Smem &sm, int NW, int wave, int
 // slots found below their threshold; `und` keeps the slots these planes left
 // undecided (their draw and threshold agree in the top 8 bits; probability
 // 2^-8 each), which finish later from the half's next blocks.
+// (planes8_compare takes the two blocks drawn already: a = half h0's, b =
+// the next half's when NH = 2.)
 template <int NH>
-__device__ __forceinline__ uint32_t camsc_planes8(uint32_t &und, uint32_t m1, uint32_t m2, const uint32_t *pt,
-                                                  uint32_t site, uint32_t t, uint32_t r, uint32_t c3, uint32_t k0,
-                                                  uint32_t k1, int lo)
+__device__ __forceinline__ uint32_t planes8_compare(uint32_t &und, uint32_t m1, uint32_t m2, const uint32_t *pt,
+                                                    const U4 &a, const U4 &b, int lo)
 {
     uint32_t lt = 0;
     const uint32_t sel_even = lo ? 0x01000C0Cu : 0x0C0C0100u;
     const uint32_t sel_odd = lo ? 0x03020C0Cu : 0x0C0C0302u;
-    const U4 a = philox10(site, t, r, c3, k0, k1);
-    U4 b = a;
-    if (NH == 2) b = philox10(site, t, r, c3 + (1u << 8), k0, k1);
     const uint32_t wa[4] = {a.x, a.y, a.z, a.w};
     const uint32_t wb[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
@@ -346,6 +344,17 @@ __device__ __forceinline__ uint32_t camsc_planes8(uint32_t &und, uint32_t m1, ui
         und ^= x;
     }
     return lt;
+}
+
+template <int NH>
+__device__ __forceinline__ uint32_t camsc_planes8(uint32_t &und, uint32_t m1, uint32_t m2, const uint32_t *pt,
+                                                  uint32_t site, uint32_t t, uint32_t r, uint32_t c3, uint32_t k0,
+                                                  uint32_t k1, int lo)
+{
+    const U4 a = philox10(site, t, r, c3, k0, k1);
+    U4 b = a;
+    if (NH == 2) b = philox10(site, t, r, c3 + (1u << 8), k0, k1);
+    return planes8_compare<NH>(und, m1, m2, pt, a, b, lo);
 }
 
 // A wave's list of halves that the first 8 planes left undecided, in LDS:
@@ -1937,7 +1946,7 @@ __device__ void slab_class_planes(const Smem &sm, const Slab &g, int c, int tid,
                                   uint32_t (*P)[8], int np)
 {
     const int lane = tid & 63;
-    PlaneQueue q = plane_queue(sm, tid >> 6);
+    PlaneQueue q = plane_queue(sm, (int)(threadIdx.x >> 6));   // tid may start past the first nthr sites
     for (int jb = tid - lane; jb < g.hc; jb += nthr) {   // the same trip count for the whole wave
         const int j = jb + lane;
         const bool live = j < g.hc;
@@ -1970,6 +1979,64 @@ __device__ void slab_class_planes(const Smem &sm, const Slab &g, int c, int tid,
             const uint32_t kk = s1 & s2;
             planes_add3<0>(*P, s1 ^ s2, xor3(c1, c2, kk), maj3(c1, c2, kk), np);
         }
+    }
+}
+
+// Plane draws ahead of a swap step (split by lattice halves, one word per
+// site): a site's bond sums, its E >= 3 mask and the first-round blocks of its
+// halves (block 0 of each), none of which depends on the temperatures.
+struct PlanePrep {
+    uint32_t S, always, m1, m2, und;
+    U4 a, b;
+};
+
+__device__ __forceinline__ PlanePrep plane_prepare(const Smem &sm, const Nbrs &nb, int n_T, uint32_t t, uint32_t r,
+                                                   uint32_t c3base, uint32_t k0, uint32_t k1)
+{
+    PlanePrep p;
+    const uint32_t *sw = sm.spin;
+    const uint32_t j6 = sm.j6[nb.i];
+    p.S = sw[nb.i];
+    const uint32_t e0 = xor3(p.S, sw[nb.xp], (0u - (j6 & 1u)));
+    const uint32_t e1 = xor3(p.S, sw[nb.xm], (0u - ((j6 >> 1) & 1u)));
+    const uint32_t e2 = xor3(p.S, sw[nb.yp], (0u - ((j6 >> 2) & 1u)));
+    const uint32_t e3 = xor3(p.S, sw[nb.ym], (0u - ((j6 >> 3) & 1u)));
+    const uint32_t e4 = xor3(p.S, sw[nb.zp], (0u - ((j6 >> 4) & 1u)));
+    const uint32_t e5 = xor3(p.S, sw[nb.zm], (0u - ((j6 >> 5) & 1u)));
+    const uint32_t s1 = xor3(e0, e1, e2), c1 = maj3(e0, e1, e2);
+    const uint32_t s2 = xor3(e3, e4, e5), c2 = maj3(e3, e4, e5);
+    const uint32_t E0 = s1 ^ s2, kk = s1 & s2;
+    const uint32_t E1 = xor3(c1, c2, kk), E2 = maj3(c1, c2, kk);
+    p.always = E2 | (E1 & E0);   // E >= 3
+    p.m1 = E0 & ~E1;
+    p.m2 = E1 & ~E0;
+    const uint32_t valid = n_T >= 32 ? 0xFFFFFFFFu : ((1u << n_T) - 1u);
+    p.und = valid & ~p.always;
+    p.a = philox10((uint32_t)nb.g, t, r, c3base, k0, k1);
+    p.b = n_T > 16 ? philox10((uint32_t)nb.g, t, r, c3base + (1u << 8), k0, k1) : p.a;
+    return p;
+}
+
+// The prepared site's first round against the thresholds after the swap pass
+// (update_site_planes with the blocks drawn); undecided halves go to the
+// wave's list.  Every lane of the wave calls it; `live` lanes hold a site.
+__device__ __forceinline__ void plane_finish(const Smem &sm, PlaneQueue &q, bool live, PlanePrep p, int site, int i0,
+                                             int NL, int n_T, uint32_t t, uint32_t r, uint32_t c3base, uint32_t k0,
+                                             uint32_t k1, int lane)
+{
+    const uint32_t valid = n_T >= 32 ? 0xFFFFFFFFu : ((1u << n_T) - 1u);
+    uint32_t und = live ? p.und : 0u, m1 = live ? p.m1 : 0u, m2 = live ? p.m2 : 0u;
+    if (live) {
+        const uint32_t lt = n_T > 16 ? planes8_compare<2>(und, m1, m2, sm.ptab, p.a, p.b, 0)
+                                     : planes8_compare<1>(und, m1, m2, sm.ptab, p.a, p.a, 0);
+        sm.spin[i0] = p.S ^ ((lt | p.always) & valid);
+    }
+    const uint32_t key = (uint32_t)site | (1u << 18);
+    plane_push(q, und & 0xFFFFu, m1 & 0xFFFFu, m2 & 0xFFFFu, key);
+    while (q.count > kItemFlush) plane_drain(sm, q, lane, NL, 0, 0, t, r, c3base, k0, k1);
+    if (n_T > 16) {
+        plane_push(q, und >> 16, m1 >> 16, m2 >> 16, key | (1u << 17));
+        while (q.count > kItemFlush) plane_drain(sm, q, lane, NL, 0, 0, t, r, c3base, k0, k1);
     }
 }
 
@@ -2121,18 +2188,25 @@ __global__ void __launch_bounds__(kMaxBlock) slab_kernel(const JobDesc *__restri
             // sweep takes its halo word, draws its blocks and forms its segment
             // words (none of which depends on the temperatures); after the swap
             // pass only its decisions remain.
-            const bool ahead = RNG == 0 && next && tid < g.hc;   // plane draws: no draw-ahead
+            // (plane draws: the bond sums and the first-round blocks of the site)
+            const bool ahead = next && tid < g.hc;
             const SlabEdge e0 = slab_edge(g, tid);
             CamscPrep prep;
-            int i0 = 0;
+            PlanePrep pp;
+            int i0 = 0, site0 = 0;
             if (ahead) {
                 const Nbrs nb = slab_site(g, tid, 0);
                 if (e0.first || e0.last)
                     sm.spin[e0.first ? nb.zm : nb.zp] = wait_tagged(
                         hx + (size_t)(other * 4 + 2) * g.hp + (e0.first ? g.hp + e0.k : e0.k), tn, jd.error);
-                slab_predraw(st, (uint32_t)nb.g, tn, r, c3flip, k0, k1);
-                prep = camsc_prepare(sm, nb);
+                if constexpr (RNG == 0) {
+                    slab_predraw(st, (uint32_t)nb.g, tn, r, c3flip, k0, k1);
+                    prep = camsc_prepare(sm, nb);
+                } else {
+                    pp = plane_prepare(sm, nb, n_T, tn, r, c3flip, k0, k1);
+                }
                 i0 = nb.i;
+                site0 = nb.g;
             }
             if (tid < n_T) sm.U[tid] += (int32_t)wait_tagged(&xb[other * 32 + tid], tag, jd.error);
             __syncthreads();   // slot energies U are in (the pairs' draws since the chunk began)
@@ -2144,19 +2218,33 @@ __global__ void __launch_bounds__(kMaxBlock) slab_kernel(const JobDesc *__restri
                 build_ptab(sm, 1, wave, nwaves, lane);
                 __syncthreads();
             }
-            if (RNG == 0 && next) {
+            if (next) {
                 // class 0 of the next sweep: the first sites only decide
                 uint64_t *mine = hx + (size_t)(part * 4) * g.hp;
-                if (ahead) {
-                    const Ctr cc{tn, r, c3flip, k0, k1, segw};
-                    const uint32_t v = camsc_finish(sm, prep, n_T, cc, st);
-                    sm.spin[i0] = v;
-                    if (e0.first || e0.last)
-                        __hip_atomic_store(&mine[e0.first ? e0.k : g.hp + e0.k], ((uint64_t)(tn + 1u) << 32) | v,
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if constexpr (RNG == 0) {
+                    if (ahead) {
+                        const Ctr cc{tn, r, c3flip, k0, k1, segw};
+                        const uint32_t v = camsc_finish(sm, prep, n_T, cc, st);
+                        sm.spin[i0] = v;
+                        if (e0.first || e0.last)
+                            __hip_atomic_store(&mine[e0.first ? e0.k : g.hp + e0.k], ((uint64_t)(tn + 1u) << 32) | v,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    slab_class<false>(sm, g, 0, tid + nthr, nthr, NL, n_T, tn, r, c3flip, k0, k1, segw, mine,
+                                      hx + (size_t)(other * 4 + 2) * g.hp, tn, true, jd.error, nullptr, 0);
+                } else {
+                    // the list of undecided halves is empty before the boundary
+                    // words go out (their late flips land from it)
+                    PlaneQueue q = plane_queue(sm, wave);
+                    plane_finish(sm, q, ahead, pp, site0, i0, NL, n_T, tn, r, c3flip, k0, k1, lane);
+                    while (q.count > 0) plane_drain(sm, q, lane, NL, 0, 0, tn, r, c3flip, k0, k1);
+                    if (ahead && (e0.first || e0.last))
+                        __hip_atomic_store(&mine[e0.first ? e0.k : g.hp + e0.k],
+                                           ((uint64_t)(tn + 1u) << 32) | sm.spin[i0], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    slab_class_planes<false>(sm, g, 0, tid + nthr, nthr, NL, n_T, tn, r, c3flip, k0, k1, mine,
+                                             hx + (size_t)(other * 4 + 2) * g.hp, tn, true, jd.error, nullptr, 0);
                 }
-                slab_class<false>(sm, g, 0, tid + nthr, nthr, NL, n_T, tn, r, c3flip, k0, k1, segw, mine,
-                                  hx + (size_t)(other * 4 + 2) * g.hp, tn, true, jd.error, nullptr, 0);
                 __syncthreads();
                 c0_done = true;
             }
