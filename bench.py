@@ -468,8 +468,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: each realization is an independent Markov chain and this "
-              "build measures one GPU's share; run with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: each realization is an independent Markov chain, so more GPUs "
+              "would each run their own share of the realizations; it measures one GPU's share: run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.valu_rate:

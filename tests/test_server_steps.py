@@ -75,7 +75,8 @@ def test_equal_units_without_packing_or_spare_rounds(stepper):
 def test_least_urgent_job_fills_the_last_round(stepper):
     """A 750-ladder job and a 64-ladder one on 256 CUs: equal units need 4
     rounds; packed, the small job (less urgent) runs units of T / 4 in the 18
-    idle slots of round 3 (18 x 4 >= 64), the big one keeps its full share.
+    idle slots of the launch's third round (18 x 4 >= 64), the big one keeps
+    its full share.
     Made more urgent, the small job keeps its share and the big one is cut."""
     big, small = 19 ** 3 * 29.0, 10 ** 3 * 16.0
     jobs = [(750, big, 10 ** 6, 1.3), (64, small, 10 ** 6, 1.0)]
