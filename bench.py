@@ -457,7 +457,7 @@ def main():
     ap.add_argument("--serving-policies", action="store_true",
                     help="also run the trace with every waiting job admitted at once (first fit, arrival order), "
                          "shortest remaining work first, and without packing of a step's last round")
-    ap.add_argument("--serving-quantum", type=int, default=200)
+    ap.add_argument("--serving-quantum", type=int, default=400)
     ap.add_argument("--serving-scale", type=float, default=1.0,
                     help="multiply every job's sweep count (1.0 = the lognormal trace as drawn)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,

@@ -268,7 +268,7 @@ void ea_plan_destroy(ea_plan *plan);
 typedef struct ea_server ea_server;
 typedef struct ea_server_options {
     size_t hbm_budget_bytes;  /* device bytes for job state; 0 = 80% of free memory at creation */
-    int quantum_sweeps;       /* sweeps per step of the job with the most work per sweep (200)    */
+    int quantum_sweeps;       /* sweeps per step of the job with the most work per sweep (400)    */
     int layout;               /* EA_LAYOUT_* of every job                                         */
     int max_active;           /* admitted jobs at once, <= 4095 (0 = 4095)                        */
     int autotune;             /* 1 = tune each job mix's workgroup size (cached by shape); default 0 */

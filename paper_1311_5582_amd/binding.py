@@ -418,7 +418,7 @@ class Plan:
 class Server:
     """Continuous-batching job server (see ea_server_* in include/ea.h)."""
 
-    def __init__(self, hbm_budget_bytes=0, quantum_sweeps=200, layout="camsc", max_active=0, autotune=False,
+    def __init__(self, hbm_budget_bytes=0, quantum_sweeps=400, layout="camsc", max_active=0, autotune=False,
                  keep_state=False, rng="words", policy="ratio", fill_ladders=0, pack_rounds=True):
         opt = ServerOptions()
         lib().ea_default_server_options(ctypes.byref(opt))

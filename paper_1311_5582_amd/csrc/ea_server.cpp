@@ -138,7 +138,7 @@ void ea_default_server_options(ea_server_options *opt)
 {
     if (!opt) return;
     std::memset(opt, 0, sizeof *opt);
-    opt->quantum_sweeps = 200;
+    opt->quantum_sweeps = 400;
     opt->layout = EA_LAYOUT_CAMSC;
     opt->autotune = 0;   // the job mix changes at every arrival; tuning each mix would cost more than it saves
     opt->policy = EA_ADMIT_RESPONSE_RATIO;
