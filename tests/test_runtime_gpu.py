@@ -177,6 +177,39 @@ def test_server_results_alone_equal_mix(oracle_lib, policy):
     srv.close()
 
 
+@pytest.mark.parametrize("pack", [True, False])
+def test_server_packed_steps_equal_alone(oracle_lib, pack):
+    """Jobs that together hold more ladders than the device has compute units
+    (400 against 256 on MI355X), all arriving at once with a small quantum:
+    with packing the least urgent jobs run shorter steps that fill the last
+    round, so the per-job sweep counts of a step change as the jobs' response
+    ratios move; every job's final state still equals the job run alone, and
+    one realization of each equals the oracle's."""
+    jobs = [dict(arrival_s=0.0, L=6, R=96, n_T=16, t_min=0.4, t_max=2.0, sweeps=61, swap_every=1, seed=2101),
+            dict(arrival_s=0.0, L=8, R=64, n_T=20, t_min=0.4, t_max=2.0, sweeps=47, swap_every=2, seed=2102),
+            dict(arrival_s=0.0, L=5, R=40, n_T=24, t_min=0.4, t_max=2.0, sweeps=33, swap_every=1, seed=2103)]
+    srv = B.Server(quantum_sweeps=9, keep_state=True, pack_rounds=pack)
+    recs, wall = serve.run_trace(jobs, srv, on_done=lambda jid, j, st: None)
+    assert len(recs) == len(jobs)
+    for jid, rec in recs.items():
+        j = rec["job"]
+        assert rec["status"] == B.JOB_DONE, rec
+        spins, perm = srv.final_state(jid)
+        alone = _make(j["L"], j["R"], j["n_T"], j["seed"])
+        alone.sweep(j["sweeps"], j["swap_every"])
+        s2, p2, _ = alone.state()
+        assert np.array_equal(spins, s2) and np.array_equal(perm, p2), f"job {jid} differs from alone (pack={pack})"
+        alone.close()
+        r = j["seed"] % j["R"]
+        orc = oracle_lib.OracleSim(j["L"], inputs.couplings(j["L"], j["R"], j["seed"])[[r]],
+                                   inputs.geometric_betas(j["n_T"], 0.4, 2.0), j["seed"], rid=np.array([r]))
+        orc.sweep(j["sweeps"], j["swap_every"])
+        assert np.array_equal(spins[r], orc.spins[0]) and np.array_equal(perm[r], orc.temp_of_slot[0])
+    st = srv.stats()
+    print(f"[runtime] packed server stats pack={pack} {st} wall {wall:.3f}s", flush=True)
+    srv.close()
+
+
 def test_server_admission_respects_budget_and_cancel():
     trace = _trace(6, seed=3)
     betas = [inputs.geometric_betas(j["n_T"], 0.4, 2.0) for j in trace]
