@@ -7,7 +7,7 @@
 // the lattice sites of one colour class are spread over the workgroup's
 // threads (Sec. 3.1); the temperature slots are the bits of a word (Sec. 3.2,
 // 4.3.3).  The ladder's spin words stay in LDS across all sweeps of a launch
-// (Sec. 4.2.2 "integer cube" in the scratchpad); when they do not fit, word
+// (the block-resident integer array of Sec. 4.2.2); when they do not fit, word
 // groups are staged through HBM once per swap interval, which is legal because
 // different slots never interact between swap points.
 //
@@ -697,8 +697,8 @@ __device__ __forceinline__ void update_site(const Smem &sm, const Nbrs &nb, int 
     static_assert(!PRE || (SPLIT && LAYOUT == 0 && RNG == 0), "pre-drawn blocks: split CAMSC words only");
     constexpr uint32_t M = 0x11111111u;
     const uint32_t j6 = sm.j6[nb.i];
-    // all-ones mask for an antiferromagnetic incidence ("multiply the coupling
-    // with a bit-mask to match the pattern of S", Sec. 4.3.3)
+    // all-ones mask for an antiferromagnetic incidence: the coupling, widened
+    // to every slot bit, is applied to S by XOR (Sec. 4.3.3)
     uint32_t m[6];
 #pragma unroll
     for (int d = 0; d < 6; ++d) m[d] = 0u - ((j6 >> d) & 1u);
